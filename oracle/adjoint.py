@@ -1,0 +1,201 @@
+"""Oracle reverse mode: dE/dA through k tracked QR-CTMRG steps, FP64 on the CPU.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The differentiated function (automatic-differentiation paragraph: untracked
+steps, then k steps with gradient tracking, then the energy) is
+
+    E(A) = e( C_k, T_k, As ),  As = P(A) / max|P(A)|,  a = sum_s As (x) As,
+    (C_{i+1}, T_{i+1}) = sym_norm( QR-step(C_i, T_i, a) ),  (C_0, T_0) held fixed.
+
+Every adjoint below is written by hand from the forward formula it reverses.
+The QR adjoint (thin QR, m >= n, diag R > 0) is
+    Abar = (Qbar + Q copyltu(M)) R^{-T},  M = R Rbar^T - Qbar^T Q,
+    copyltu(M) = tril(M) + tril(M, -1)^T,
+the form used in the AD literature the paper cites for iPEPS (Liao et al. 2019).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ctmrg as ctm
+from . import observables as obs
+
+
+def einsum_vjp(spec: str, X: np.ndarray, Y: np.ndarray, Zbar: np.ndarray):
+    """Cotangents of Z = einsum(spec, X, Y) (each index once per operand)."""
+    ins, out = spec.split("->")
+    sx, sy = ins.split(",")
+    Xbar = np.einsum(f"{out},{sy}->{sx}", Zbar, Y, optimize=True)
+    Ybar = np.einsum(f"{sx},{out}->{sy}", X, Zbar, optimize=True)
+    return Xbar, Ybar
+
+
+def copyltu(M: np.ndarray) -> np.ndarray:
+    return np.tril(M) + np.tril(M, -1).T
+
+
+def qr_backward(Q, R, Qbar, Rbar):
+    M = R @ Rbar.T - Qbar.T @ Q
+    B = Qbar + Q @ copyltu(M)
+    # B R^{-T}: solve R X^T = B^T
+    return np.linalg.solve(R, B.T).T
+
+
+# ----------------------------------------------------------------------------
+# a9 / symmetrisation adjoints
+# ----------------------------------------------------------------------------
+
+
+def norm_backward(X, Xbar):
+    """y = X/||X||  ->  Xbar_in = (ybar - y <y, ybar>) / ||X||."""
+    nrm = np.linalg.norm(X)
+    y = X / nrm
+    return (Xbar - y * np.sum(y * Xbar)) / nrm
+
+
+def sym_norm_backward(Cp, Tp, Cbar, Tbar):
+    Cs = 0.5 * (Cp + Cp.T)
+    Ts = 0.5 * (Tp + Tp.transpose(2, 1, 0))
+    Csb = norm_backward(Cs, Cbar)
+    Tsb = norm_backward(Ts, Tbar)
+    return 0.5 * (Csb + Csb.T), 0.5 * (Tsb + Tsb.transpose(2, 1, 0))
+
+
+# ----------------------------------------------------------------------------
+# One QR step, reversed.
+# ----------------------------------------------------------------------------
+
+
+def qr_step_backward(C, T, a, Cnbar, Tnbar):
+    """Given the step's inputs and cotangents of its normalised outputs,
+    return (Cbar, Tbar, abar)."""
+    chi, Dab, _ = T.shape
+    p = ctm.qr_step_parts(C, T, a)
+    Q, R, Y, Z, Tp, Cp = p["Q"], p["R"], p["Y"], p["Z"], p["Tp"], p["Cp"]
+    chin = Q.shape[1]
+    Q3 = Q.reshape(chi, Dab, chin)
+
+    Cpb, Tpb = sym_norm_backward(Cp, Tp, Cnbar, Tnbar)
+
+    # a8: W = R . Q3 ; C' = T'^T-contract W
+    W = np.tensordot(R, Q3, axes=([1], [0]))                        # [g,r,b]
+    Tpb2, Wb = einsum_vjp("gra,grb->ab", Tp, W, Cpb)
+    Tpb = Tpb + Tpb2
+    Rb, Q3b = einsum_vjp("gc,crb->grb", R, Q3, Wb)
+
+    # a7 (3c): T'[a,r,b] = Z[a,f,d,r] Q3[f,d,b]
+    Zb, Q3b2 = einsum_vjp("afdr,fdb->arb", Z, Q3, Tpb)
+    Q3b = Q3b + Q3b2
+    # a7 (3b): Z[a,f,d,r] = Y[a,u,l,f] a[u,l,d,r]
+    Yb, ab = einsum_vjp("aulf,uldr->afdr", Y, a, Zb)
+    # a7 (3a): Y[a,u,l,f] = Q3[e,u,a] T[e,l,f]
+    Q3b3, Tb = einsum_vjp("eua,elf->aulf", Q3, T, Yb)
+    Q3b = Q3b + Q3b3
+
+    # a6: QR
+    ctb = qr_backward(Q, R, Q3b.reshape(chi * Dab, chin), Rb)
+
+    # a5: ct = C . T (as chi x (Dab chi))
+    ctb2 = ctb.reshape(C.shape[0], Dab * T.shape[2])
+    Tmat = T.reshape(chi, Dab * T.shape[2])
+    Cb = ctb2 @ Tmat.T
+    Tb = Tb + (C.T @ ctb2).reshape(T.shape)
+    return Cb, Tb, ab
+
+
+# ----------------------------------------------------------------------------
+# Energy (2x1 cluster), reversed.
+# ----------------------------------------------------------------------------
+
+
+def energy_nn_backward(C, T, A, h):
+    """Return (e, Cbar, Tbar, Abar_open) for e = 2 Tr(rho h)/Tr rho."""
+    d = A.shape[0]
+    F = np.tensordot(C, T, axes=([1], [0]))                          # [q,L,r]
+    E1 = np.tensordot(F, C, axes=([2], [0]))                         # [q,L,t]
+    E2 = np.einsum("qUw,qLt->wULt", T, E1, optimize=True)
+    ao = ctm.open_double_layer(A)
+    E3 = np.einsum("wULt,xyULDR->wtxyDR", E2, ao, optimize=True)
+    Left = np.einsum("wtxyDR,tDv->wRvxy", E3, T, optimize=True)
+    rho = np.einsum("wRvab,wRvcd->abcd", Left, Left, optimize=True)
+    rm = rho.transpose(0, 2, 1, 3).reshape(d * d, d * d)
+    num = float(np.trace(rm @ h))
+    den = float(np.trace(rm))
+    e = 2.0 * num / den
+
+    rmb = (2.0 / den) * h.T - (2.0 * num / den ** 2) * np.eye(d * d)
+    rhob = rmb.reshape(d, d, d, d).transpose(0, 2, 1, 3)
+    Lb1, Lb2 = einsum_vjp("wRvab,wRvcd->abcd", Left, Left, rhob)
+    Leftb = Lb1 + Lb2
+    E3b, Tb = einsum_vjp("wtxyDR,tDv->wRvxy", E3, T, Leftb)
+    E2b, aob = einsum_vjp("wULt,xyULDR->wtxyDR", E2, ao, E3b)
+    Tb2, E1b = einsum_vjp("qUw,qLt->wULt", T, E1, E2b)
+    Tb = Tb + Tb2
+    Fb, Cb = einsum_vjp("qLr,rt->qLt", F, C, E1b)
+    Cb2, Tb3 = einsum_vjp("qp,pLr->qLr", C, T, Fb)
+    Cb = Cb + Cb2
+    Tb = Tb + Tb3
+
+    D = A.shape[1]
+    aob8 = aob.reshape(d, d, D, D, D, D, D, D, D, D)  # [s,t,u,u',l,l',d,d',r,r']
+    Ab = (np.einsum("staebfcgdh,tefgh->sabcd", aob8, A, optimize=True)
+          + np.einsum("tsaebfcgdh,tabcd->sefgh", aob8, A, optimize=True))
+    return e, Cb, Tb, Ab
+
+
+def double_layer_backward(A, abar):
+    """a[(u u'),(l l'),(d d'),(r r')] = sum_s A[s,u,l,d,r] A[s,u',l',d',r']."""
+    D = A.shape[1]
+    ab8 = abar.reshape(D, D, D, D, D, D, D, D)        # [u,u',l,l',d,d',r,r']
+    return (np.einsum("aebfcgdh,sefgh->sabcd", ab8, A, optimize=True)
+            + np.einsum("aebfcgdh,sabcd->sefgh", ab8, A, optimize=True))
+
+
+def prepare_backward(A_raw, Asbar):
+    """As = P(A)/m, m = max|P(A)| (unique maximiser assumed)."""
+    PA = ctm.c4v_average(A_raw)
+    flat = np.abs(PA).ravel()
+    i = int(np.argmax(flat))
+    m = flat[i]
+    sgn = np.sign(PA.ravel()[i])
+    g = ctm.c4v_average(Asbar) / m
+    coef = sgn * np.sum(Asbar * PA) / m ** 2
+    ei = np.zeros(PA.size)
+    ei[i] = 1.0
+    g -= coef * ctm.c4v_average(ei.reshape(PA.shape))
+    return g
+
+
+# ----------------------------------------------------------------------------
+# Checkpointed k-step gradient.
+# ----------------------------------------------------------------------------
+
+
+def energy_k(A_raw, C0, T0, k, h):
+    """Forward only: E(A) as defined in the module docstring."""
+    As = ctm.prepare_site_tensor(A_raw)
+    a = ctm.double_layer(As)
+    C, T = C0, T0
+    for _ in range(k):
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+    return obs.energy_nn(C, T, As, h)
+
+
+def energy_grad_k(A_raw, C0, T0, k, h):
+    """(E, dE/dA_raw) with the k tracked steps reversed from stored (C_i, T_i)."""
+    As = ctm.prepare_site_tensor(A_raw)
+    a = ctm.double_layer(As)
+    env = [(C0, T0)]
+    C, T = C0, T0
+    for _ in range(k):
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+        env.append((C, T))
+    e, Cb, Tb, Asb = energy_nn_backward(C, T, As, h)
+    ab = np.zeros_like(a)
+    for i in range(k - 1, -1, -1):
+        Ci, Ti = env[i]
+        Cb, Tb, abi = qr_step_backward(Ci, Ti, a, Cb, Tb)
+        ab += abi
+    Asb = Asb + double_layer_backward(As, ab)
+    return e, prepare_backward(A_raw, Asb)
