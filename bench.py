@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""QR-CTMRG throughput on one MI355X: steps/s and FP64 MFMA TFLOP/s.
+
+Workload: C4v QR-CTMRG on a random C4v-symmetrised site tensor, d = 2, D = 6,
+chi = 144 (reduced corner 5184 x 144), FP64.  One "step" is one full QR-CTMRG
+step: reduced corner, Householder QR, T' = Q^T (T a) Q, accelerated corner,
+symmetrise/normalise and the corner-spectrum convergence measure.
+
+The environment is initialised (C4v average, double layer, boundary, standard
+warm-up step) before the timed region; W untimed steps follow; then exactly K
+steps are timed between two stream synchronisations.  The dominant kernel (the
+double-layer contraction Z = Y a, a GEMM of 2 chi^2 D^8 flops) is timed per
+launch with HIP events on the library's stream in a second pass, for the
+roofline figure.  The CPU baseline is the FP64 oracle on the host cores on a
+bounded sample of the same workload.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_3b(chi: int, D: int) -> float:
+    return 2.0 * chi * chi * float(D) ** 8
+
+
+def cpu_baseline(d, D, chi, seed, budget_s=20.0):
+    """Oracle QR steps on the host (FP64, numpy/OpenBLAS) for about budget_s seconds."""
+    from oracle import ctmrg as ctm
+    from synth import inputs as inp
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(int(i.get("num_threads", 1)) for i in threadpool_info())
+    except Exception:
+        threads = os.cpu_count() or 1
+    A = inp.random_site_tensor(d, D, seed)
+    As = ctm.prepare_site_tensor(A)
+    a = ctm.double_layer(As)
+    C, T = ctm.warmup_env(a, chi, ctm.identity_boundary_vector(D))
+    s_prev = ctm.spectrum(C)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+        s = ctm.spectrum(C)
+        ctm.spectrum_delta(s, s_prev)
+        s_prev = s
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or n >= 200:
+            break
+    return {"value": n / el, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} QR-CTMRG steps (d={d}, D={D}, chi={chi}, seed {seed}) after the "
+                      f"oracle's own warm-up, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--D", type=int, default=6)
+    ap.add_argument("--chi", type=int, default=144)
+    ap.add_argument("--d", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the path would shard the 3a/3b/3c chain over the new chi index with one "
+              "all-gather of T' per step (see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2505_00494_amd as P
+    from synth import inputs as inp
+
+    d, D, chi = args.d, args.D, args.chi
+    dev = torch.device("cuda:0")
+    A = torch.as_tensor(inp.random_site_tensor(d, D, args.seed), device=dev)
+    print(f"# init d={d} D={D} chi={chi}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ctx = P.Context(A, chi)
+    t_init = time.perf_counter() - t0
+    print(f"# init {t_init:.2f} s; warm-up {args.warmup} steps", file=sys.stderr, flush=True)
+    if args.warmup:
+        ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    delta = ctx.step(args.steps)          # one call: K steps, one sync at the end
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    steps_per_s = args.steps / el
+    st = ctx.stats()
+    F = st["flops_per_step"]
+    print(f"# timed {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+
+    # per-phase pass (HIP events on the library stream around every phase)
+    nt = max(5, min(args.steps, 20))
+    ctx.set_timing(True)
+    ctx.step(nt)
+    st2 = ctx.stats()
+    ctx.set_timing(False)
+    ms = {k: v / st2["timed_steps"] for k, v in st2["ms_phase"].items()}
+    ms_3b = ms["edge_3b"]
+    achieved = flops_3b(chi, D) / (ms_3b * 1e-3) / 1e12
+
+    out = {
+        "metric": f"QR-CTMRG steps/s (d={d}, D={D}, chi={chi}, FP64)",
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"C4v QR-CTMRG step, random C4v site tensor (seed {args.seed}), "
+                               f"d={d} D={D} chi={chi}", "d": d, "D": D, "chi": chi,
+                   "seed": args.seed},
+        "tflops": F * steps_per_s / 1e12,
+        "flops_per_step": F,
+        "last_delta": delta,
+        "init_s": t_init,
+        "ms_per_phase": ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "double-layer contraction Z = Y a (3b)",
+                     "flops_per_launch": flops_3b(chi, D), "ms_per_launch": ms_3b},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(d, D, chi, args.seed, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * qrctm.h - C ABI of the MI355X QR-CTMRG library (libqrctm.so).
+ *
+ * The library runs C4v-symmetric corner-transfer-matrix renormalisation with a
+ * QR decomposition of the reduced corner in place of the eigen/SVD
+ * decomposition (Zhang, Yang, Corboz, arXiv:2505.00494, "QR-CTMRG" paragraph
+ * and Fig. 1e/f), on one GPU, in FP64.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays named "device" are GPU pointers; "host" arrays are CPU pointers.
+ *    Every array is FP64 and row-major (C order) with the leg order given.
+ *      A[s,u,l,d,r]   site tensor, d*D^4 (physical, up, left, down, right).
+ *      a[U,L,Dn,R]    double-layer / classical tensor, Dab^4.
+ *      C[x,y]         corner, chi*chi, symmetric.
+ *      T[x,m,y]       edge, chi*Dab*chi; x, y boundary legs (T[x,m,y]=T[y,m,x]),
+ *                     m the leg facing the bulk.
+ *  - Ownership: the caller owns every buffer it passes and keeps it alive while
+ *    the context uses it.  All device scratch comes from ONE caller-provided
+ *    workspace (size from ctm_workspace_bytes*); the library allocates no
+ *    device memory.  The context itself is a small host object.
+ *  - Streams: each context enqueues all its GPU work on the HIP stream given at
+ *    creation (a hipStream_t passed as void*; NULL = the null stream).  Calls
+ *    that return host scalars synchronise that stream.  A context is not
+ *    thread-safe.
+ *  - Errors: every int-returning call returns 0 on success, >0 for a warning,
+ *    <0 for an error (codes below).  No C++ exception crosses the ABI.  After an
+ *    error the context keeps its previous environment unless the message from
+ *    ctm_last_error() says the context is invalid.
+ */
+#ifndef QRCTM_H
+#define QRCTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CTM_OK          0
+#define CTM_NOTCONV     1   /* warning: max_steps reached before tol        */
+#define CTM_EINVAL     -1   /* invalid argument (sizes, null pointers)      */
+#define CTM_EWORKSPACE -2   /* workspace missing or too small               */
+#define CTM_EHIP       -3   /* HIP runtime error (text in ctm_last_error)   */
+#define CTM_ENONFINITE -4   /* NaN/Inf produced or found in the input       */
+#define CTM_ESINGULAR  -5   /* R of the reduced corner numerically singular */
+#define CTM_ESTATE     -6   /* call not valid for this context              */
+
+/* precision of the bulk contractions */
+#define CTM_PREC_FP64      0
+#define CTM_PREC_FP32_MFMA 1
+
+typedef struct ctm_ctx ctm_ctx;
+
+typedef struct ctm_opts {
+    int precision;      /* CTM_PREC_*; QR, normalisation and the spectrum stay FP64 */
+    int n_warmup;       /* standard (eigh) warm-up steps; -1 = as many as needed for
+                           chi to reach its target (QR-CTMRG paragraph: 1-4 steps) */
+    int k_tracked;      /* tracked QR steps in ctm_energy_grad (AD paragraph)       */
+    double qr_sing_tol; /* ctm_energy_grad fails with CTM_ESINGULAR when
+                           min|R_ii| / max|R_ii| of a tracked step is below this    */
+} ctm_opts;
+
+/* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = 10, qr_sing_tol = 1e-14. */
+void ctm_default_opts(ctm_opts* o);
+
+/*
+ * Workspace sizes in bytes for a context built by ctm_init (site tensor, d, D,
+ * target chi) or by ctm_init_dl (double-layer / classical tensor of bond Dab).
+ * opts may be NULL (defaults).  Returns 0 for invalid sizes.
+ */
+size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts);
+size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts);
+
+/*
+ * ctm_init: a1-a4 for a quantum iPEPS.
+ *   A      device, d*D^4, raw site tensor (read during the call only).  The
+ *          library applies the C4v average over the 8 leg permutations and
+ *          scales to max|A| = 1 (iPEPS paragraph, C4v footnote), builds the
+ *          double layer a = sum_s A (x) A (Fig. 1b), initialises C, T by
+ *          contracting ket with bra on the open legs (footnote on the initial
+ *          boundary), and runs the standard-CTMRG warm-up steps (eigh of the
+ *          enlarged corner, Fig. 1d) that grow chi to its target.
+ *   ws     device workspace of at least ctm_workspace_bytes(d, D, chi, opts).
+ *   stream hipStream_t as void*.
+ * Returns CTM_OK, CTM_EINVAL, CTM_EWORKSPACE, CTM_ENONFINITE or CTM_EHIP.
+ */
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi,
+             const ctm_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ctm_init_dl: same for a tensor network given directly by its bulk tensor
+ * (Discussion paragraph: classical 2D partition functions).
+ *   a      device, Dab^4, layout a[U,L,Dn,R]; must be C4v symmetric.
+ *   bvec   device, Dab: vector contracted with every open boundary leg to form
+ *          the initial C and T (all ones = free boundary).
+ * ctm_energy / ctm_energy_grad return CTM_ESTATE on such a context.
+ */
+int ctm_init_dl(ctm_ctx** out, const double* a, const double* bvec, int Dab, int chi,
+                const ctm_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ctm_set_tensor: replace the site tensor (same d, D) and rebuild a; C and T
+ * are kept (environment reuse between optimisation steps, AD paragraph).
+ */
+int ctm_set_tensor(ctm_ctx* ctx, const double* A);
+
+/*
+ * ctm_step: nsteps QR-CTMRG steps (QR-CTMRG paragraph, Fig. 1e/f):
+ *   reduced corner c~ = C.T (chi*Dab x chi); Householder QR c~ = Q R with
+ *   diag(R) >= 0; T' = Q^T (T a) Q; C' = T'.R.Q (accelerated corner);
+ *   symmetrise and divide C', T' by their Frobenius norms; corner spectrum
+ *   s = sort(|eig C'|)/sum and delta = ||s - s_prev||_2.
+ * delta (host, may be NULL) receives the change of the last step.
+ */
+int ctm_step(ctm_ctx* ctx, int nsteps, double* delta);
+
+/*
+ * ctm_converge: QR steps until delta < tol or max_steps steps were taken
+ * (standard-CTMRG paragraph: "repeated until convergence").  steps / delta are
+ * host outputs (may be NULL).  Returns CTM_NOTCONV when max_steps is reached.
+ */
+int ctm_converge(ctm_ctx* ctx, double tol, int max_steps, int* steps, double* delta);
+
+/* Environment access (device arrays sized for the current chi_cur <= chi). */
+int ctm_get_env(ctm_ctx* ctx, double* C, double* T, int* chi_cur /* host */);
+int ctm_set_env(ctm_ctx* ctx, const double* C, const double* T, int chi_cur);
+
+/* Normalised corner spectrum of the current C (host array of chi_cur entries). */
+int ctm_spectrum(ctm_ctx* ctx, double* s);
+
+/*
+ * ctm_energy: energy per site from the current environment (Heisenberg and
+ * J1-J2 paragraphs).  h_nn, h_nnn are HOST d^2 x d^2 bond operators, row index
+ * (s1 s2), column index (s1' s2'); h_nnn may be NULL.
+ *   E = 2 <h_nn> + 2 J2 <h_nnn>   (two bonds of each kind per site),
+ * where <h> = Tr(rho h)/Tr(rho) of the two-site reduced density matrix of a
+ * nearest-neighbour pair (2x1 cluster) or a diagonal pair (2x2 plaquette).
+ */
+int ctm_energy(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
+               double* E);
+
+/*
+ * ctm_energy_grad: E and dE/dA (AD paragraph).  Starting from the current
+ * environment, held fixed, the library runs opts.k_tracked QR steps, evaluates
+ * E, and reverses the whole computation by hand-written adjoints (contraction
+ * adjoints, the thin-QR adjoint, the double layer and the C4v average).  Only
+ * (C_i, T_i) of every tracked step are kept; each step's intermediates are
+ * recomputed in the reverse sweep.  dA is a device array of d*D^4 entries, the
+ * gradient with respect to the raw A given to ctm_init / ctm_set_tensor.
+ * The environment is left unchanged.  h_nnn must be NULL (nearest-neighbour
+ * models).
+ */
+int ctm_energy_grad(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
+                    double* E, double* dA);
+
+/* Classical networks: ln of the partition function per site, and <O> at one
+ * site from a device impurity tensor imp[U,L,Dn,R] (Dab^4). */
+int ctm_lnz_per_site(ctm_ctx* ctx, double* lnk);
+int ctm_expect_site(ctm_ctx* ctx, const double* imp, double* v);
+
+typedef struct ctm_stats_t {
+    int chi, chi_cur, Dab;
+    long long steps;          /* QR steps taken since creation                 */
+    double last_delta;
+    double flops_per_step;    /* algorithmic flops of one QR step              */
+    double r_diag_ratio;      /* min|R_ii|/max|R_ii| of the last QR            */
+    long long timed_steps;    /* QR steps timed since ctm_set_timing(ctx, 1)   */
+    double ms_phase[8];       /* GPU ms summed over the timed steps, per phase:
+                                 0 reduced corner, 1 QR, 2 T.Q (3a),
+                                 3 double-layer contraction (3b), 4 .Q (3c),
+                                 5 accelerated corner, 6 symmetrise/normalise,
+                                 7 corner spectrum                             */
+} ctm_stats_t;
+int ctm_stats(ctm_ctx* ctx, ctm_stats_t* st);
+
+/* Per-phase timing of QR steps with HIP events on the context stream (on = 1)
+ * or off (0); switching resets the accumulated times.  Timing synchronises the
+ * stream once per step. */
+int ctm_set_timing(ctm_ctx* ctx, int on);
+
+/* Message of the last failing call on ctx (or on creation if ctx is NULL). */
+const char* ctm_last_error(const ctm_ctx* ctx);
+void ctm_destroy(ctm_ctx* ctx);
+
+/*
+ * Component entry points (one kernel chain each), exposed for tests at full
+ * size.  All arrays device, row-major; stream as above; they synchronise.
+ *
+ * ctm_qr: thin Householder QR of M (m x n, m >= n) with diag(R) >= 0
+ *   (QR-CTMRG paragraph: unpivoted QR of the reduced corner).  Q is m x n,
+ *   R n x n upper triangular.  ws of ctm_qr_workspace_bytes(m, n).
+ */
+size_t ctm_qr_workspace_bytes(int m, int n);
+int ctm_qr(const double* M, double* Q, double* R, int m, int n, void* ws,
+           size_t ws_bytes, void* stream);
+
+/*
+ * ctm_gemm: C = alpha * op(A) op(B) + beta * C, FP64 on the matrix cores (the
+ *   kernel behind every contraction of the step).
+ *   op(A) is M x K: trans_a = 0 -> A[m*lda + k], 1 -> A[k*lda + m].
+ *   op(B) is K x N: trans_b = 0 -> B[k*ldb + n], 1 -> B[n*ldb + k].
+ *   C is M x N at C[m*ldc + n].  ws: device scratch of at least
+ *   ctm_gemm_workspace_bytes(M, N, K) bytes (0 for most shapes; may be NULL then).
+ */
+size_t ctm_gemm_workspace_bytes(int M, int N, int K);
+int ctm_gemm(int trans_a, int trans_b, int M, int N, int K, double alpha,
+             const double* A, int lda, const double* B, int ldb, double beta,
+             double* C, int ldc, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QRCTM_H */

@@ -1,0 +1,79 @@
+// Shared host/device helpers of the QR-CTMRG library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace qrctm {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Error carried out of the internal launchers; the ABI layer turns it into a
+// status code and a message.
+struct Status {
+    int code = 0;
+    std::string msg;
+    bool ok() const { return code == 0; }
+};
+
+inline Status hip_status(hipError_t e, const char* what) {
+    Status s;
+    if (e != hipSuccess) {
+        s.code = -3;
+        s.msg = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return s;
+}
+
+#define QRCTM_TRY(expr)                          \
+    do {                                         \
+        ::qrctm::Status _s = (expr);             \
+        if (!_s.ok()) return _s;                 \
+    } while (0)
+
+#define QRCTM_HIP(expr) QRCTM_TRY(::qrctm::hip_status((expr), #expr))
+
+inline Status launch_check(const char* what) { return hip_status(hipGetLastError(), what); }
+
+inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// GEMM on the FP64 matrix cores (gemm.hip).
+//   C[map(m,n)] = alpha * sum_k opA(m,k) opB(k,n) + beta * C[map(m,n)]
+// opA(m,k) = A[m*lda + k] (trans_a = 0) or A[k*lda + m] (trans_a = 1)
+// opB(k,n) = B[k*ldb + n] (trans_b = 0) or B[n*ldb + k] (trans_b = 1)
+// map(m,n) = (m / mdiv) * ms1 + (m % mdiv) * ms2 + (n / ndiv) * ns1 + (n % ndiv) * ns2
+// A plain row-major C with leading dimension ldc is mdiv = M, ms2 = ldc,
+// ndiv = N, ns2 = 1.
+// ---------------------------------------------------------------------------
+struct OutMap {
+    long long mdiv, ms1, ms2, ndiv, ns1, ns2;
+    static OutMap plain(long long M, long long N, long long ldc) {
+        return OutMap{M > 0 ? M : 1, 0, ldc, N > 0 ? N : 1, 0, 1};
+    }
+};
+
+struct GemmDesc {
+    int trans_a = 0, trans_b = 0;
+    long long M = 0, N = 0, K = 0;
+    const double* A = nullptr;
+    long long lda = 0;
+    const double* B = nullptr;
+    long long ldb = 0;
+    double* C = nullptr;
+    OutMap map{};
+    double alpha = 1.0, beta = 0.0;
+};
+
+// Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the
+// shape does not split.
+size_t gemm_splitk_bytes(const GemmDesc& g);
+Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStream_t st);
+
+}  // namespace qrctm

@@ -1,0 +1,761 @@
+// C ABI and step driver of the QR-CTMRG library.
+//
+// A context owns host state only; all device memory is carved out of the
+// caller's workspace (plan_workspace).  All GPU work of a context goes to its
+// stream in order; host scalars are read after a stream synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "../../include/qrctm.h"
+#include "common.h"
+#include "eigh.h"
+#include "energy.h"
+#include "qr.h"
+#include "spectrum.h"
+#include "tensor_ops.h"
+
+using namespace qrctm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Buf {
+    size_t off = 0, bytes = 0;
+};
+
+struct Plan {
+    // device buffers (byte offsets into the workspace)
+    Buf As, a, bvec, C0, C1, T0, T1, Q, R, Y, Z, Tp, W, Cp, S, spec0, spec1, small, normpart, qr,
+        splitk, eig, energy, grad;
+    size_t total = 0;
+    size_t qr_bytes = 0, splitk_bytes = 0, eig_bytes = 0, energy_bytes = 0, grad_bytes = 0;
+};
+
+struct Shape {
+    int d = 0, D = 0, Dab = 0, chi = 0;
+    bool quantum = false;
+};
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+// GEMM descriptors of one QR step at (chi_in -> chi_out) -----------------------
+struct StepPtrs {
+    const double *C, *T, *a;
+    double *Q, *R, *Y, *Z, *Tp, *W, *Cp;
+};
+
+GemmDesc g_reduced_corner(const StepPtrs& p, int chi, int Dab) {
+    GemmDesc g;  // ct[(y,m), c] = sum_x C[y,x] T[x,m,c]
+    g.M = chi; g.N = (long long)Dab * chi; g.K = chi;
+    g.A = p.C; g.lda = chi; g.B = p.T; g.ldb = (long long)Dab * chi;
+    g.C = p.Q; g.map = OutMap::plain(g.M, g.N, g.N);
+    return g;
+}
+GemmDesc g_edge_a(const StepPtrs& p, const double* Q, int chi, int chio, int Dab) {
+    GemmDesc g;  // Y[al,f,u,l] = sum_e Q[(e,u),al] T[f,l,e]   (T[x,m,y] = T[y,m,x])
+    g.trans_a = 1; g.trans_b = 1;
+    g.M = (long long)Dab * chio; g.N = (long long)chi * Dab; g.K = chi;
+    g.A = Q; g.lda = (long long)Dab * chio;
+    g.B = p.T; g.ldb = chi;
+    g.C = p.Y;
+    const long long D2 = (long long)Dab * Dab;
+    g.map = OutMap{chio, Dab, (long long)chi * D2, Dab, D2, 1};
+    return g;
+}
+GemmDesc g_edge_b(const StepPtrs& p, int chi, int chio, int Dab) {
+    GemmDesc g;  // Z[al,r,f,d] = sum_{u,l} Y[al,f,u,l] a[u,l,r,d]
+    const long long D2 = (long long)Dab * Dab;
+    g.M = (long long)chio * chi; g.N = D2; g.K = D2;
+    g.A = p.Y; g.lda = D2; g.B = p.a; g.ldb = D2;
+    g.C = p.Z;
+    g.map = OutMap{chi, (long long)chi * D2, Dab, Dab, (long long)chi * Dab, 1};
+    return g;
+}
+GemmDesc g_edge_c(const StepPtrs& p, const double* Q, int chi, int chio, int Dab) {
+    GemmDesc g;  // T'[al,r,be] = sum_{f,d} Z[al,r,f,d] Q[(f,d),be]
+    g.M = (long long)chio * Dab; g.N = chio; g.K = (long long)chi * Dab;
+    g.A = p.Z; g.lda = (long long)chi * Dab; g.B = Q; g.ldb = chio;
+    g.C = p.Tp; g.map = OutMap::plain(g.M, g.N, g.N);
+    return g;
+}
+GemmDesc g_corner_w(const StepPtrs& p, int chi, int Dab) {
+    GemmDesc g;  // W[g,r,b] = sum_c R[g,c] Q[(c,r),b]
+    g.M = chi; g.N = (long long)Dab * chi; g.K = chi;
+    g.A = p.R; g.lda = chi; g.B = p.Q; g.ldb = (long long)Dab * chi;
+    g.C = p.W; g.map = OutMap::plain(g.M, g.N, g.N);
+    return g;
+}
+GemmDesc g_corner_c(const StepPtrs& p, int chi, int Dab) {
+    GemmDesc g;  // C'[a,b] = sum_{g,r} T'[g,r,a] W[g,r,b]
+    g.trans_a = 1;
+    g.M = chi; g.N = chi; g.K = (long long)chi * Dab;
+    g.A = p.Tp; g.lda = chi; g.B = p.W; g.ldb = chi;
+    g.C = p.Cp; g.map = OutMap::plain(chi, chi, chi);
+    return g;
+}
+
+size_t step_splitk_bytes(int chi, int Dab) {
+    StepPtrs p{};
+    size_t s = 0;
+    for (int c = 1; c <= chi; ++c) {
+        s = std::max(s, gemm_splitk_bytes(g_reduced_corner(p, c, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_a(p, nullptr, c, c, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_b(p, c, c, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_c(p, nullptr, c, c, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_corner_w(p, c, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_corner_c(p, c, Dab)));
+    }
+    // warm-up shapes (chi_in < chi_out)
+    for (int ci = 1; ci <= chi; ++ci) {
+        const int co = std::min(chi, ci * Dab);
+        s = std::max(s, gemm_splitk_bytes(g_edge_a(p, nullptr, ci, ci, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_b(p, ci, ci, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_a(p, nullptr, ci, co, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_b(p, ci, co, Dab)));
+        s = std::max(s, gemm_splitk_bytes(g_edge_c(p, nullptr, ci, co, Dab)));
+    }
+    return s;
+}
+
+Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
+    Plan P;
+    size_t off = 0;
+    auto take = [&](Buf& b, size_t bytes) {
+        b.off = off;
+        b.bytes = bytes;
+        off += align_up(bytes);
+    };
+    const size_t d8 = sizeof(double);
+    const size_t chi = sh.chi, Dab = sh.Dab;
+    const size_t D4 = (size_t)sh.D * sh.D * sh.D * sh.D;
+    take(P.As, sh.quantum ? d8 * sh.d * D4 : 0);
+    take(P.a, d8 * Dab * Dab * Dab * Dab);
+    take(P.bvec, d8 * Dab);
+    take(P.C0, d8 * chi * chi);
+    take(P.C1, d8 * chi * chi);
+    take(P.T0, d8 * chi * chi * Dab);
+    take(P.T1, d8 * chi * chi * Dab);
+    take(P.Q, d8 * chi * Dab * chi);
+    take(P.R, d8 * chi * chi);
+    take(P.Y, d8 * chi * chi * Dab * Dab);
+    take(P.Z, d8 * chi * chi * Dab * Dab);
+    take(P.Tp, d8 * chi * chi * Dab);
+    take(P.W, d8 * chi * chi * Dab);
+    take(P.Cp, d8 * chi * chi);
+    take(P.S, spectrum_scratch_bytes((int)chi));
+    take(P.spec0, d8 * chi);
+    take(P.spec1, d8 * chi);
+    take(P.small, d8 * 64);
+    take(P.normpart, sym_norm_scratch_bytes());
+    P.qr_bytes = 0;
+    for (int c = 1; c <= sh.chi; ++c)
+        P.qr_bytes = std::max(P.qr_bytes, qr_scratch_layout(c * sh.Dab, c).total);
+    take(P.qr, P.qr_bytes);
+    P.splitk_bytes = step_splitk_bytes(sh.chi, sh.Dab);
+    take(P.splitk, P.splitk_bytes);
+    // warm-up eigensolver scratch: order chi_in * Dab of the largest warm-up step
+    {
+        int nmax = 0, cc = sh.Dab, steps = 0;
+        const int want = o.n_warmup < 0 ? -1 : o.n_warmup;
+        while (want < 0 ? true : steps < want) {
+            nmax = std::max(nmax, cc * sh.Dab);
+            const int cn = std::min(sh.chi, cc * sh.Dab);
+            ++steps;
+            if (want < 0 && (cn >= sh.chi || cn == cc)) break;
+            cc = cn;
+        }
+        P.eig_bytes = nmax > 0 ? eigh_scratch_bytes(nmax) : 0;
+    }
+    take(P.eig, P.eig_bytes);
+    P.energy_bytes = sh.quantum ? energy_scratch_bytes(sh.d, sh.D, sh.chi)
+                                : classical_scratch_bytes(sh.Dab, sh.chi);
+    take(P.energy, P.energy_bytes);
+    P.grad_bytes = 0;
+    take(P.grad, P.grad_bytes);
+    P.total = off;
+    return P;
+}
+
+constexpr int kPhases = 8;  // reduced corner, QR, 3a, 3b, 3c, corner, sym/norm, spectrum
+
+// small-scalar slots (doubles) inside Plan::small
+enum { SL_DELTA = 0, SL_NORMS = 2, SL_RATIO = 4, SL_SCALE = 5, SL_BAD = 8, SL_E = 16 };
+
+}  // namespace
+
+struct ctm_ctx {
+    Shape sh;
+    ctm_opts opts{};
+    hipStream_t st = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Plan plan;
+    int chi_cur = 0;
+    int cur = 0;       // which of (C0,T0)/(C1,T1) holds the environment
+    int spec_cur = 0;  // which spectrum buffer holds the spectrum of C
+    int n_spec = 0;    // its length
+    long long steps = 0;
+    double last_delta = NAN;
+    double last_ratio = NAN;
+    std::string err;
+    // optional per-phase timing of QR steps (hipEvents on the context stream)
+    bool timing = false;
+    hipEvent_t ev[kPhases + 1] = {};
+    double ms_phase[kPhases] = {};
+    long long timed_steps = 0;
+    ~ctm_ctx() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+
+    template <class T = double>
+    T* ptr(const Buf& b) const {
+        return reinterpret_cast<T*>(ws + b.off);
+    }
+    double* C() const { return ptr(cur ? plan.C1 : plan.C0); }
+    double* T() const { return ptr(cur ? plan.T1 : plan.T0); }
+    double* Cn() const { return ptr(cur ? plan.C0 : plan.C1); }
+    double* Tn() const { return ptr(cur ? plan.T0 : plan.T1); }
+    double* spec() const { return ptr(spec_cur ? plan.spec1 : plan.spec0); }
+    double* spec_next() const { return ptr(spec_cur ? plan.spec0 : plan.spec1); }
+    double* small() const { return ptr(plan.small); }
+    int* bad() const { return reinterpret_cast<int*>(ptr(plan.small) + SL_BAD); }
+};
+
+namespace {
+
+int fail(ctm_ctx* c, const Status& s) {
+    if (c) c->err = s.msg;
+    else g_create_error = s.msg;
+    return s.code;
+}
+int fail(ctm_ctx* c, int code, const std::string& msg) {
+    Status s;
+    s.code = code;
+    s.msg = msg;
+    return fail(c, s);
+}
+
+Status sync(hipStream_t st) { return hip_status(hipStreamSynchronize(st), "hipStreamSynchronize"); }
+
+Status read_bad(ctm_ctx* c, bool* bad) {
+    int h = 0;
+    QRCTM_HIP(hipMemcpyAsync(&h, c->bad(), sizeof(int), hipMemcpyDeviceToHost, c->st));
+    QRCTM_TRY(sync(c->st));
+    *bad = h != 0;
+    return Status{};
+}
+
+Status clear_bad(ctm_ctx* c) {
+    return hip_status(hipMemsetAsync(c->bad(), 0, sizeof(int), c->st), "hipMemsetAsync");
+}
+
+// One renormalisation of (C, T) with isometry Q (chi*Dab x chio) into Tp, W, Cp.
+Status renormalise_edge(ctm_ctx* c, const StepPtrs& p, const double* Q, int chi, int chio) {
+    const int Dab = c->sh.Dab;
+    void* sk = c->ptr<void>(c->plan.splitk);
+    const size_t skb = c->plan.splitk_bytes;
+    QRCTM_TRY(gemm_f64(g_edge_a(p, Q, chi, chio, Dab), sk, skb, c->st));
+    QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chio, Dab), sk, skb, c->st));
+    QRCTM_TRY(gemm_f64(g_edge_c(p, Q, chi, chio, Dab), sk, skb, c->st));
+    return Status{};
+}
+
+StepPtrs step_ptrs(ctm_ctx* c) {
+    StepPtrs p;
+    p.C = c->C(); p.T = c->T(); p.a = c->ptr(c->plan.a);
+    p.Q = c->ptr(c->plan.Q); p.R = c->ptr(c->plan.R);
+    p.Y = c->ptr(c->plan.Y); p.Z = c->ptr(c->plan.Z);
+    p.Tp = c->ptr(c->plan.Tp); p.W = c->ptr(c->plan.W); p.Cp = c->ptr(c->plan.Cp);
+    return p;
+}
+
+Status mark(ctm_ctx* c, int i) {
+    if (!c->timing) return Status{};
+    return hip_status(hipEventRecord(c->ev[i], c->st), "hipEventRecord");
+}
+
+// a5-a10 once; environment moves to the other buffer; spectrum likewise.
+Status qr_step_once(ctm_ctx* c) {
+    const int chi = c->chi_cur, Dab = c->sh.Dab;
+    StepPtrs p = step_ptrs(c);
+    void* sk = c->ptr<void>(c->plan.splitk);
+    const size_t skb = c->plan.splitk_bytes;
+    QRCTM_TRY(mark(c, 0));
+    QRCTM_TRY(gemm_f64(g_reduced_corner(p, chi, Dab), sk, skb, c->st));               // a5
+    QRCTM_TRY(mark(c, 1));
+    QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
+                     c->st, c->small() + SL_RATIO));                                 // a6
+    QRCTM_TRY(mark(c, 2));
+    QRCTM_TRY(gemm_f64(g_edge_a(p, p.Q, chi, chi, Dab), sk, skb, c->st));             // a7 3a
+    QRCTM_TRY(mark(c, 3));
+    QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chi, Dab), sk, skb, c->st));                  // a7 3b
+    QRCTM_TRY(mark(c, 4));
+    QRCTM_TRY(gemm_f64(g_edge_c(p, p.Q, chi, chi, Dab), sk, skb, c->st));             // a7 3c
+    QRCTM_TRY(mark(c, 5));
+    QRCTM_TRY(gemm_f64(g_corner_w(p, chi, Dab), sk, skb, c->st));                     // a8
+    QRCTM_TRY(gemm_f64(g_corner_c(p, chi, Dab), sk, skb, c->st));
+    QRCTM_TRY(mark(c, 6));
+    QRCTM_TRY(sym_norm(p.Cp, p.Tp, chi, Dab, c->Cn(), c->Tn(), c->ptr(c->plan.normpart),
+                       c->small() + SL_NORMS, c->bad(), c->st));                     // a9
+    QRCTM_TRY(mark(c, 7));
+    QRCTM_TRY(corner_spectrum(c->Cn(), chi, c->ptr(c->plan.S), c->spec(), c->n_spec,
+                              c->spec_next(), c->small() + SL_DELTA, c->st));        // a10
+    QRCTM_TRY(mark(c, 8));
+    if (c->timing) {
+        QRCTM_HIP(hipEventSynchronize(c->ev[kPhases]));
+        for (int i = 0; i < kPhases; ++i) {
+            float ms = 0.f;
+            QRCTM_HIP(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+            c->ms_phase[i] += ms;
+        }
+        c->timed_steps++;
+    }
+    c->cur ^= 1;
+    c->spec_cur ^= 1;
+    c->n_spec = chi;
+    c->steps++;
+    return Status{};
+}
+
+// Standard step (warm-up): eigh of the enlarged corner, chi grows to
+// min(chi_target, chi_cur * Dab).
+Status eigh_step_once(ctm_ctx* c) {
+    const int chi = c->chi_cur, Dab = c->sh.Dab;
+    const int n = chi * Dab;
+    const int chio = std::min(c->sh.chi, n);
+    StepPtrs p = step_ptrs(c);
+    void* sk = c->ptr<void>(c->plan.splitk);
+    const size_t skb = c->plan.splitk_bytes;
+    // c~ into Q, enlarged corner into Z (Z[(al,r),(f,d)] = Ct[(f,d),(al,r)])
+    QRCTM_TRY(gemm_f64(g_reduced_corner(p, chi, Dab), sk, skb, c->st));
+    QRCTM_TRY(gemm_f64(g_edge_a(p, p.Q, chi, chi, Dab), sk, skb, c->st));
+    QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chi, Dab), sk, skb, c->st));
+    // eigenpairs; U (n x chio) into Q, kept eigenvalues on the diagonal of Cp
+    QRCTM_TRY(eigh_select(p.Z, n, chio, p.Q, p.Cp, c->ptr<void>(c->plan.eig), c->plan.eig_bytes,
+                          c->st));
+    QRCTM_TRY(renormalise_edge(c, p, p.Q, chi, chio));
+    QRCTM_TRY(sym_norm(p.Cp, p.Tp, chio, Dab, c->Cn(), c->Tn(), c->ptr(c->plan.normpart),
+                       c->small() + SL_NORMS, c->bad(), c->st));
+    QRCTM_TRY(corner_spectrum(c->Cn(), chio, c->ptr(c->plan.S), c->spec(), c->n_spec,
+                              c->spec_next(), c->small() + SL_DELTA, c->st));
+    c->cur ^= 1;
+    c->spec_cur ^= 1;
+    c->n_spec = chio;
+    c->chi_cur = chio;
+    return Status{};
+}
+
+int warmup_needed(int chi0, int Dab, int chi) {
+    int n = 0, cc = chi0;
+    while (true) {
+        ++n;
+        const int cn = std::min(chi, cc * Dab);
+        if (cn >= chi || cn == cc) return n;
+        cc = cn;
+    }
+}
+
+Status fresh_spectrum(ctm_ctx* c) {
+    QRCTM_TRY(corner_spectrum(c->C(), c->chi_cur, c->ptr(c->plan.S), nullptr, 0, c->spec(),
+                              c->small() + SL_DELTA, c->st));
+    c->n_spec = c->chi_cur;
+    return Status{};
+}
+
+Status start_environment(ctm_ctx* c) {
+    const int Dab = c->sh.Dab;
+    QRCTM_TRY(init_env(c->ptr(c->plan.a), c->ptr(c->plan.bvec), Dab, c->ptr(c->plan.Cp),
+                       c->ptr(c->plan.Tp), c->st));
+    c->chi_cur = Dab;
+    QRCTM_TRY(sym_norm(c->ptr(c->plan.Cp), c->ptr(c->plan.Tp), Dab, Dab, c->C(), c->T(),
+                       c->ptr(c->plan.normpart), c->small() + SL_NORMS, c->bad(), c->st));
+    QRCTM_TRY(fresh_spectrum(c));
+    int nw = c->opts.n_warmup < 0 ? warmup_needed(Dab, Dab, c->sh.chi) : c->opts.n_warmup;
+    for (int i = 0; i < nw; ++i) QRCTM_TRY(eigh_step_once(c));
+    bool bad = false;
+    QRCTM_TRY(read_bad(c, &bad));
+    if (bad) {
+        Status s;
+        s.code = CTM_ENONFINITE;
+        s.msg = "non-finite or zero environment during initialisation";
+        return s;
+    }
+    return Status{};
+}
+
+bool valid_opts(const ctm_opts& o) {
+    return (o.precision == CTM_PREC_FP64 || o.precision == CTM_PREC_FP32_MFMA) && o.k_tracked >= 0;
+}
+
+int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_t ws_bytes,
+           void* stream, ctm_ctx** made) {
+    if (out == nullptr) return fail(nullptr, CTM_EINVAL, "out is NULL");
+    *out = nullptr;
+    ctm_opts o;
+    ctm_default_opts(&o);
+    if (opts) o = *opts;
+    if (!valid_opts(o)) return fail(nullptr, CTM_EINVAL, "invalid ctm_opts");
+    if (sh.chi < 1 || sh.chi > 1024 || sh.Dab < 1)
+        return fail(nullptr, CTM_EINVAL, "chi must be in [1, 1024] and Dab >= 1");
+    if (sh.chi < sh.Dab)
+        return fail(nullptr, CTM_EINVAL, "chi must be at least the bond dimension Dab of the bulk tensor");
+    if (!qr_fits(sh.chi * sh.Dab, sh.chi))
+        return fail(nullptr, CTM_EINVAL, "chi*Dab x chi reduced corner exceeds the QR kernel limits");
+    Plan P = plan_workspace(sh, o);
+    if (ws == nullptr || ws_bytes < P.total)
+        return fail(nullptr, CTM_EWORKSPACE, "workspace missing or smaller than ctm_workspace_bytes");
+    ctm_ctx* c = new ctm_ctx();
+    c->sh = sh;
+    c->opts = o;
+    c->st = static_cast<hipStream_t>(stream);
+    c->ws = static_cast<char*>(ws);
+    c->ws_bytes = ws_bytes;
+    c->plan = P;
+    *made = c;
+    return 0;
+}
+
+template <class F>
+int guarded(ctm_ctx* c, F&& f) {
+    try {
+        Status s = f();
+        if (!s.ok()) return fail(c, s);
+        return s.code;
+    } catch (const std::exception& e) {
+        return fail(c, CTM_EHIP, std::string("exception: ") + e.what());
+    } catch (...) {
+        return fail(c, CTM_EHIP, "unknown exception");
+    }
+}
+
+// Algorithmic flops of one QR step (Dab = D^2): reduced corner 2 chi^3 Dab,
+// Householder QR 4 m n^2 - 4 n^3 / 3 with m = chi Dab, n = chi, edge
+// renormalisation 2 chi^3 Dab^2 + 2 chi^2 Dab^4 + 2 chi^3 Dab^2, accelerated
+// corner 4 chi^3 Dab.
+double step_flops(int chi, int Dab) {
+    const double c = chi, Db = Dab, Db2 = Db * Db;
+    return 2 * c * c * c * Db + (4 * c * c * c * Db - 4.0 / 3.0 * c * c * c) +
+           2 * c * c * c * Db2 + 2 * c * c * Db2 * Db2 + 2 * c * c * c * Db2 + 4 * c * c * c * Db;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ctm_default_opts(ctm_opts* o) {
+    if (!o) return;
+    o->precision = CTM_PREC_FP64;
+    o->n_warmup = -1;
+    o->k_tracked = 10;
+    o->qr_sing_tol = 1e-14;
+}
+
+size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
+    if (d < 1 || D < 1 || chi < 1) return 0;
+    ctm_opts o;
+    ctm_default_opts(&o);
+    if (opts) o = *opts;
+    Shape sh{d, D, D * D, chi, true};
+    return plan_workspace(sh, o).total;
+}
+
+size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts) {
+    if (Dab < 1 || chi < 1) return 0;
+    ctm_opts o;
+    ctm_default_opts(&o);
+    if (opts) o = *opts;
+    Shape sh{0, 0, Dab, chi, false};
+    return plan_workspace(sh, o).total;
+}
+
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_opts* opts, void* ws,
+             size_t ws_bytes, void* stream) {
+    if (A == nullptr || d < 1 || D < 1) return fail(nullptr, CTM_EINVAL, "invalid A, d or D");
+    Shape sh{d, D, D * D, chi, true};
+    ctm_ctx* c = nullptr;
+    int rc = create(out, sh, opts, ws, ws_bytes, stream, &c);
+    if (rc != 0) return rc;
+    rc = guarded(c, [&]() -> Status {
+        QRCTM_TRY(clear_bad(c));
+        QRCTM_TRY(c4v_prepare(A, d, D, c->ptr(c->plan.As), c->small() + SL_SCALE, c->bad(), c->st));
+        QRCTM_TRY(double_layer(c->ptr(c->plan.As), d, D, c->ptr(c->plan.a), c->st));
+        QRCTM_TRY(eye_vec(c->ptr(c->plan.bvec), D, c->st));
+        bool bad = false;
+        QRCTM_TRY(read_bad(c, &bad));
+        if (bad) {
+            Status s;
+            s.code = CTM_ENONFINITE;
+            s.msg = "site tensor is non-finite or zero after the C4v average";
+            return s;
+        }
+        return start_environment(c);
+    });
+    if (rc < 0) {
+        g_create_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return rc;
+}
+
+int ctm_init_dl(ctm_ctx** out, const double* a, const double* bvec, int Dab, int chi,
+                const ctm_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+    if (a == nullptr || bvec == nullptr) return fail(nullptr, CTM_EINVAL, "a or bvec is NULL");
+    Shape sh{0, 0, Dab, chi, false};
+    ctm_ctx* c = nullptr;
+    int rc = create(out, sh, opts, ws, ws_bytes, stream, &c);
+    if (rc != 0) return rc;
+    rc = guarded(c, [&]() -> Status {
+        QRCTM_TRY(clear_bad(c));
+        QRCTM_TRY(dl_to_internal(a, Dab, c->ptr(c->plan.a), c->st));
+        QRCTM_HIP(hipMemcpyAsync(c->ptr(c->plan.bvec), bvec, sizeof(double) * Dab,
+                                 hipMemcpyDeviceToDevice, c->st));
+        return start_environment(c);
+    });
+    if (rc < 0) {
+        g_create_error = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return rc;
+}
+
+int ctm_set_tensor(ctm_ctx* c, const double* A) {
+    if (!c || !A) return fail(c, CTM_EINVAL, "NULL argument");
+    if (!c->sh.quantum) return fail(c, CTM_ESTATE, "context was built from a double-layer tensor");
+    return guarded(c, [&]() -> Status {
+        QRCTM_TRY(clear_bad(c));
+        QRCTM_TRY(c4v_prepare(A, c->sh.d, c->sh.D, c->ptr(c->plan.As), c->small() + SL_SCALE,
+                              c->bad(), c->st));
+        QRCTM_TRY(double_layer(c->ptr(c->plan.As), c->sh.d, c->sh.D, c->ptr(c->plan.a), c->st));
+        bool bad = false;
+        QRCTM_TRY(read_bad(c, &bad));
+        if (bad) {
+            Status s;
+            s.code = CTM_ENONFINITE;
+            s.msg = "site tensor is non-finite or zero";
+            return s;
+        }
+        return Status{};
+    });
+}
+
+int ctm_step(ctm_ctx* c, int nsteps, double* delta) {
+    if (!c || nsteps < 0) return fail(c, CTM_EINVAL, "invalid arguments");
+    return guarded(c, [&]() -> Status {
+        QRCTM_TRY(clear_bad(c));
+        for (int i = 0; i < nsteps; ++i) QRCTM_TRY(qr_step_once(c));
+        double h[2] = {NAN, NAN};
+        QRCTM_HIP(hipMemcpyAsync(h, c->small() + SL_DELTA, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->st));
+        bool bad = false;
+        QRCTM_TRY(read_bad(c, &bad));
+        c->last_delta = h[0];
+        if (delta) *delta = h[0];
+        if (bad || !std::isfinite(h[0])) {
+            Status s;
+            s.code = CTM_ENONFINITE;
+            s.msg = "non-finite environment in ctm_step";
+            return s;
+        }
+        return Status{};
+    });
+}
+
+int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delta) {
+    if (!c || max_steps < 0) return fail(c, CTM_EINVAL, "invalid arguments");
+    int taken = 0;
+    double dl = NAN;
+    int rc = guarded(c, [&]() -> Status {
+        QRCTM_TRY(clear_bad(c));
+        while (taken < max_steps) {
+            QRCTM_TRY(qr_step_once(c));
+            ++taken;
+            QRCTM_HIP(hipMemcpyAsync(&dl, c->small() + SL_DELTA, sizeof(double),
+                                     hipMemcpyDeviceToHost, c->st));
+            QRCTM_TRY(sync(c->st));
+            if (!std::isfinite(dl)) break;
+            if (dl < tol) break;
+        }
+        bool bad = false;
+        QRCTM_TRY(read_bad(c, &bad));
+        c->last_delta = dl;
+        if (bad || !std::isfinite(dl)) {
+            Status s;
+            s.code = CTM_ENONFINITE;
+            s.msg = "non-finite environment in ctm_converge";
+            return s;
+        }
+        return Status{};
+    });
+    if (steps) *steps = taken;
+    if (delta) *delta = dl;
+    if (rc < 0) return rc;
+    return (dl < tol) ? CTM_OK : CTM_NOTCONV;
+}
+
+int ctm_get_env(ctm_ctx* c, double* C, double* T, int* chi_cur) {
+    if (!c) return fail(c, CTM_EINVAL, "NULL context");
+    return guarded(c, [&]() -> Status {
+        const size_t nC = (size_t)c->chi_cur * c->chi_cur;
+        if (C) QRCTM_HIP(hipMemcpyAsync(C, c->C(), nC * 8, hipMemcpyDeviceToDevice, c->st));
+        if (T) QRCTM_HIP(hipMemcpyAsync(T, c->T(), nC * c->sh.Dab * 8, hipMemcpyDeviceToDevice, c->st));
+        if (chi_cur) *chi_cur = c->chi_cur;
+        return sync(c->st);
+    });
+}
+
+int ctm_set_env(ctm_ctx* c, const double* C, const double* T, int chi_cur) {
+    if (!c || !C || !T) return fail(c, CTM_EINVAL, "NULL argument");
+    if (chi_cur < 1 || chi_cur > c->sh.chi) return fail(c, CTM_EINVAL, "chi_cur out of range");
+    return guarded(c, [&]() -> Status {
+        const size_t nC = (size_t)chi_cur * chi_cur;
+        QRCTM_HIP(hipMemcpyAsync(c->C(), C, nC * 8, hipMemcpyDeviceToDevice, c->st));
+        QRCTM_HIP(hipMemcpyAsync(c->T(), T, nC * c->sh.Dab * 8, hipMemcpyDeviceToDevice, c->st));
+        c->chi_cur = chi_cur;
+        QRCTM_TRY(fresh_spectrum(c));
+        return sync(c->st);
+    });
+}
+
+int ctm_spectrum(ctm_ctx* c, double* s) {
+    if (!c || !s) return fail(c, CTM_EINVAL, "NULL argument");
+    return guarded(c, [&]() -> Status {
+        QRCTM_HIP(hipMemcpyAsync(s, c->spec(), sizeof(double) * c->n_spec, hipMemcpyDeviceToHost,
+                                 c->st));
+        return sync(c->st);
+    });
+}
+
+int ctm_energy(ctm_ctx* c, const double* h_nn, const double* h_nnn, double J2, double* E) {
+    if (!c || !h_nn || !E) return fail(c, CTM_EINVAL, "NULL argument");
+    if (!c->sh.quantum) return fail(c, CTM_ESTATE, "energy needs a site tensor (ctm_init)");
+    return guarded(c, [&]() -> Status {
+        EnergyArgs ea{};
+        ea.d = c->sh.d; ea.D = c->sh.D; ea.chi = c->chi_cur;
+        ea.C = c->C(); ea.T = c->T(); ea.As = c->ptr(c->plan.As);
+        ea.ws = c->ptr<char>(c->plan.energy); ea.ws_bytes = c->plan.energy_bytes;
+        ea.splitk = c->ptr<void>(c->plan.splitk); ea.splitk_bytes = c->plan.splitk_bytes;
+        return energy_eval(ea, h_nn, h_nnn, J2, E, c->st);
+    });
+}
+
+int ctm_energy_grad(ctm_ctx* c, const double* h_nn, const double* h_nnn, double J2, double* E,
+                    double* dA) {
+    (void)h_nn; (void)h_nnn; (void)J2; (void)E; (void)dA;
+    if (!c) return fail(c, CTM_EINVAL, "NULL context");
+    return fail(c, CTM_ESTATE, "ctm_energy_grad is not available in this build");
+}
+
+int ctm_lnz_per_site(ctm_ctx* c, double* lnk) {
+    if (!c || !lnk) return fail(c, CTM_EINVAL, "NULL argument");
+    return guarded(c, [&]() -> Status {
+        ClassicalArgs ca{};
+        ca.Dab = c->sh.Dab; ca.chi = c->chi_cur;
+        ca.C = c->C(); ca.T = c->T(); ca.a = c->ptr(c->plan.a);
+        ca.ws = c->ptr<char>(c->plan.energy); ca.ws_bytes = c->plan.energy_bytes;
+        return classical_lnz(ca, lnk, c->st);
+    });
+}
+
+int ctm_expect_site(ctm_ctx* c, const double* imp, double* v) {
+    if (!c || !imp || !v) return fail(c, CTM_EINVAL, "NULL argument");
+    return guarded(c, [&]() -> Status {
+        ClassicalArgs ca{};
+        ca.Dab = c->sh.Dab; ca.chi = c->chi_cur;
+        ca.C = c->C(); ca.T = c->T(); ca.a = c->ptr(c->plan.a);
+        ca.ws = c->ptr<char>(c->plan.energy); ca.ws_bytes = c->plan.energy_bytes;
+        return classical_expect(ca, imp, v, c->st);
+    });
+}
+
+int ctm_stats(ctm_ctx* c, ctm_stats_t* st) {
+    if (!c || !st) return fail(c, CTM_EINVAL, "NULL argument");
+    return guarded(c, [&]() -> Status {
+        double r = NAN;
+        QRCTM_HIP(hipMemcpyAsync(&r, c->small() + SL_RATIO, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->st));
+        QRCTM_TRY(sync(c->st));
+        st->chi = c->sh.chi;
+        st->chi_cur = c->chi_cur;
+        st->Dab = c->sh.Dab;
+        st->steps = c->steps;
+        st->last_delta = c->last_delta;
+        st->flops_per_step = step_flops(c->chi_cur, c->sh.Dab);
+        st->r_diag_ratio = c->steps > 0 ? r : NAN;
+        st->timed_steps = c->timed_steps;
+        for (int i = 0; i < kPhases; ++i) st->ms_phase[i] = c->ms_phase[i];
+        return Status{};
+    });
+}
+
+int ctm_set_timing(ctm_ctx* c, int on) {
+    if (!c) return fail(c, CTM_EINVAL, "NULL context");
+    return guarded(c, [&]() -> Status {
+        if (on && !c->ev[0])
+            for (auto& e : c->ev) QRCTM_HIP(hipEventCreate(&e));
+        c->timing = on != 0;
+        for (double& m : c->ms_phase) m = 0.0;
+        c->timed_steps = 0;
+        return Status{};
+    });
+}
+
+const char* ctm_last_error(const ctm_ctx* c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+void ctm_destroy(ctm_ctx* c) { delete c; }
+
+size_t ctm_qr_workspace_bytes(int m, int n) {
+    if (m < n || n < 1) return 0;
+    return qr_scratch_layout(m, n).total;
+}
+
+int ctm_qr(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
+           void* stream) {
+    if (!M || !Q || !R) return fail(nullptr, CTM_EINVAL, "NULL argument");
+    if (m < n || n < 1) return fail(nullptr, CTM_EINVAL, "need m >= n >= 1");
+    return guarded(nullptr, [&]() -> Status {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        QRCTM_TRY(qr_pos(M, Q, R, m, n, ws, ws_bytes, st, nullptr));
+        return sync(st);
+    });
+}
+
+size_t ctm_gemm_workspace_bytes(int M, int N, int K) {
+    if (M < 0 || N < 0 || K < 1) return 0;
+    GemmDesc g;
+    g.M = M; g.N = N; g.K = K;
+    return gemm_splitk_bytes(g);
+}
+
+int ctm_gemm(int trans_a, int trans_b, int M, int N, int K, double alpha, const double* A, int lda,
+             const double* B, int ldb, double beta, double* C, int ldc, void* ws, size_t ws_bytes,
+             void* stream) {
+    if (!A || !B || !C || M < 0 || N < 0 || K < 1) return fail(nullptr, CTM_EINVAL, "invalid GEMM");
+    return guarded(nullptr, [&]() -> Status {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        GemmDesc g;
+        g.trans_a = trans_a ? 1 : 0;
+        g.trans_b = trans_b ? 1 : 0;
+        g.M = M; g.N = N; g.K = K;
+        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+        g.C = C; g.map = OutMap::plain(M, N, ldc);
+        g.alpha = alpha; g.beta = beta;
+        QRCTM_TRY(gemm_f64(g, ws, ws_bytes, st));
+        return sync(st);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,394 @@
+// Observables from a converged environment.
+//
+// Quantum (Heisenberg paragraph; energy per site from the environment): the
+// two-site reduced density matrix of a nearest-neighbour pair from the 2x1
+// cluster (4 corners, 6 edges, two open sites).  The open site is never formed
+// as a double-layer tensor with open physical legs (d^2 D^8 entries); the ket
+// and the bra layer are contracted one after the other instead:
+//   E1[q,L,t]   = C T C                               (left column)
+//   E2[U,w,L,t] = sum_q T[q,U,w] E1[q,L,t]            (top edge)
+//   ket:  sum_{u,l} E2 . A[s,u,l,d,r]                 (K = D^2)
+//   bra:  sum_{u',l'} (...) . A[s',u',l',d',r']       (K = D^2)
+//   Left[w,s,s',R,v] = sum_{t,Dn} (...) T[t,Dn,v]     (bottom edge)
+//   rho[(s1 s1'),(s2 s2')] = sum Left[..,s1,s1',..] Left[..,s2,s2',..]
+// (the right half equals the left half by the mirror symmetry of the C4v
+// network).  Each contraction is one FP64 MFMA GEMM; the index reorders between
+// them are HBM-bound permutes or are folded into the GEMM output map.
+//
+// Classical (Discussion paragraph: classical partition functions): ln kappa =
+// ln Z33 + ln Z22 - 2 ln Z32 and <O> = Z33(impurity) / Z33(a).
+#include "common.h"
+#include "energy.h"
+#include "tensor_ops.h"
+
+namespace qrctm {
+namespace {
+
+constexpr int kMaxDims = 8;
+
+struct PermArgs {
+    int nd;
+    long long out_dims[kMaxDims];    // output shape
+    long long in_strides[kMaxDims];  // input stride of each OUTPUT axis
+    long long total;
+};
+
+__global__ void permute_kernel(const double* __restrict__ in, double* out, PermArgs p) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < p.total;
+         e += (long long)gridDim.x * blockDim.x) {
+        long long rem = e, src = 0;
+        for (int q = p.nd - 1; q >= 0; --q) {
+            const long long i = rem % p.out_dims[q];
+            rem /= p.out_dims[q];
+            src += i * p.in_strides[q];
+        }
+        out[e] = in[src];
+    }
+}
+
+// out = in.transpose(axes) for a row-major tensor of shape dims
+Status permute(const double* in, double* out, int nd, const long long* dims, const int* axes,
+               hipStream_t st) {
+    PermArgs p{};
+    p.nd = nd;
+    long long stride[kMaxDims];
+    long long s = 1;
+    for (int q = nd - 1; q >= 0; --q) {
+        stride[q] = s;
+        s *= dims[q];
+    }
+    p.total = s;
+    for (int q = 0; q < nd; ++q) {
+        p.out_dims[q] = dims[axes[q]];
+        p.in_strides[q] = stride[axes[q]];
+    }
+    const int blocks = (int)std::min<long long>(ceil_div(p.total, 256), 65536);
+    hipLaunchKernelGGL(permute_kernel, dim3(blocks), dim3(256), 0, st, in, out, p);
+    return launch_check("permute_kernel");
+}
+
+constexpr int kRedBlocks = 512;
+
+// partial sums of sum_i x[i] * y[ (i / ny) + (i % ny) * nx ] (transposed y when tr)
+__global__ void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                   long long n, long long rows, long long cols, int tr,
+                                   double* part) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long j = tr ? (e % cols) * rows + e / cols : e;
+        acc += x[e] * y[j];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_kernel(const double* __restrict__ part, int n, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s;
+    }
+}
+
+Status dot(const double* x, const double* y, long long n, long long rows, long long cols, int tr,
+           double* part, double* out, hipStream_t st) {
+    const int blocks = (int)std::max<long long>(1, std::min<long long>(ceil_div(n, 256), kRedBlocks));
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(blocks), dim3(256), 0, st, x, y, n, rows, cols, tr,
+                       part);
+    QRCTM_TRY(launch_check("dot_partial_kernel"));
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, st, part, blocks, out);
+    return launch_check("sum_kernel");
+}
+
+// e = 2 Tr(rm h)/Tr(rm) (+ 2 J2 Tr(rm2 h2)/Tr(rm2)) from rho[(s1 s1'),(s2 s2')]
+__global__ void bond_energy_kernel(const double* __restrict__ rho, const double* __restrict__ h,
+                                   int d, double scale, double* out, int accumulate) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double num = 0.0, den = 0.0;
+    const int d2 = d * d;
+    for (int s1 = 0; s1 < d; ++s1)
+        for (int t1 = 0; t1 < d; ++t1)
+            for (int s2 = 0; s2 < d; ++s2)
+                for (int t2 = 0; t2 < d; ++t2) {
+                    const double r = rho[(size_t)(s1 * d + t1) * d2 + (s2 * d + t2)];
+                    num += r * h[(size_t)(t1 * d + t2) * d2 + (s1 * d + s2)];
+                    if (s1 == t1 && s2 == t2) den += r;
+                }
+    const double v = scale * num / den;
+    *out = accumulate ? *out + v : v;
+}
+
+struct ELayout {
+    size_t E1, F, X, Yb, Left, Lp, Ak, rho, h, scal, splitk, total;
+    size_t splitk_bytes;
+};
+
+ELayout e_layout(int d, int D, int chi) {
+    ELayout L{};
+    size_t off = 0;
+    auto take = [&](size_t count) {
+        const size_t o = off;
+        off += (count * sizeof(double) + 255) / 256 * 256;
+        return o;
+    };
+    const size_t c = chi, D2 = (size_t)D * D, D4 = D2 * D2;
+    L.E1 = take(c * D2 * c);
+    L.F = take(c * D2 * c);
+    L.X = take((size_t)d * d * c * c * D4);
+    L.Yb = take((size_t)d * d * c * c * D4);
+    L.Left = take(c * (size_t)d * d * D2 * c);
+    L.Lp = take(c * (size_t)d * d * D2 * c);
+    L.Ak = take((size_t)d * D4);
+    L.rho = take((size_t)d * d * d * d);
+    L.h = take((size_t)d * d * d * d);
+    L.scal = take(16);
+    // split-K partials of the rho GEMM (M = N = d^2, K = chi^2 D^2)
+    GemmDesc g;
+    g.M = (long long)d * d; g.N = g.M; g.K = (long long)c * c * D2;
+    L.splitk_bytes = gemm_splitk_bytes(g) + sizeof(double) * kRedBlocks;
+    L.splitk = take(L.splitk_bytes / sizeof(double) + 1);
+    L.total = off;
+    return L;
+}
+
+struct CLayout {
+    size_t F, E1, X1, X2, imp, part, scal, total;
+};
+
+CLayout c_layout(int Dab, int chi) {
+    CLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t count) {
+        const size_t o = off;
+        off += (count * sizeof(double) + 255) / 256 * 256;
+        return o;
+    };
+    const size_t c = chi, D = Dab;
+    L.F = take(c * D * c);
+    L.E1 = take(c * D * c);
+    L.X1 = take(c * c * D * D);
+    L.X2 = take(c * c * D * D);
+    L.imp = take(D * D * D * D);
+    L.part = take(kRedBlocks);
+    L.scal = take(16);
+    L.total = off;
+    return L;
+}
+
+// E1[q,L,t] = sum C[q,p] T[p,L,r] C[r,t]
+Status left_column(const double* C, const double* T, int chi, int Dab, double* F, double* E1,
+                   hipStream_t st) {
+    GemmDesc g;
+    g.M = chi; g.N = (long long)Dab * chi; g.K = chi;
+    g.A = C; g.lda = chi; g.B = T; g.ldb = (long long)Dab * chi;
+    g.C = F; g.map = OutMap::plain(g.M, g.N, g.N);
+    QRCTM_TRY(gemm_f64(g, nullptr, 0, st));
+    GemmDesc h;
+    h.M = (long long)chi * Dab; h.N = chi; h.K = chi;
+    h.A = F; h.lda = chi; h.B = C; h.ldb = chi;
+    h.C = E1; h.map = OutMap::plain(h.M, h.N, h.N);
+    return gemm_f64(h, nullptr, 0, st);
+}
+
+// Z33 of the 3x3 network with centre tensor ct (internal layout a[U][L][R][Dn])
+Status z33(const ClassicalArgs& ca, const CLayout& L, const double* ct, double* out,
+           hipStream_t st) {
+    char* b = ca.ws;
+    const int chi = ca.chi, Dab = ca.Dab;
+    const long long D2 = (long long)Dab * Dab;
+    double* E1 = reinterpret_cast<double*>(b + L.E1);
+    double* X1 = reinterpret_cast<double*>(b + L.X1);
+    double* X2 = reinterpret_cast<double*>(b + L.X2);
+    // X1[w][t][U][L] = sum_q T[q,U,w] E1[q,L,t]
+    GemmDesc g;
+    g.trans_a = 1;
+    g.M = (long long)Dab * chi; g.N = (long long)Dab * chi; g.K = chi;
+    g.A = ca.T; g.lda = (long long)Dab * chi; g.B = E1; g.ldb = (long long)Dab * chi;
+    g.C = X1;
+    g.map = OutMap{chi, Dab, (long long)chi * D2, chi, 1, D2};
+    QRCTM_TRY(gemm_f64(g, nullptr, 0, st));
+    // X2[w][t][R][Dn] = X1[(w,t),(U,L)] ct[(U,L),(R,Dn)]
+    GemmDesc h;
+    h.M = (long long)chi * chi; h.N = D2; h.K = D2;
+    h.A = X1; h.lda = D2; h.B = ct; h.ldb = D2;
+    h.C = X2; h.map = OutMap::plain(h.M, h.N, h.N);
+    QRCTM_TRY(gemm_f64(h, nullptr, 0, st));
+    // Y3[w][t][R][Dn] = sum_v E1[w,R,v] T[t,Dn,v]   (into X1)
+    GemmDesc k;
+    k.trans_b = 1;
+    k.M = (long long)chi * Dab; k.N = (long long)chi * Dab; k.K = chi;
+    k.A = E1; k.lda = chi; k.B = ca.T; k.ldb = chi;
+    k.C = X1;
+    k.map = OutMap{Dab, (long long)chi * D2, Dab, Dab, D2, 1};
+    QRCTM_TRY(gemm_f64(k, nullptr, 0, st));
+    return dot(X2, X1, (long long)chi * chi * D2, 0, 1, 0, reinterpret_cast<double*>(b + L.part),
+               out, st);
+}
+
+Status classical_parts(const ClassicalArgs& ca, double* z33v, double* z22v, double* z32v,
+                       const double* imp_dev, hipStream_t st) {
+    const CLayout L = c_layout(ca.Dab, ca.chi);
+    Status s;
+    if (ca.ws_bytes < L.total) {
+        s.code = -2;
+        s.msg = "classical observables: scratch too small";
+        return s;
+    }
+    char* b = ca.ws;
+    const int chi = ca.chi, Dab = ca.Dab;
+    double* F = reinterpret_cast<double*>(b + L.F);
+    double* E1 = reinterpret_cast<double*>(b + L.E1);
+    double* part = reinterpret_cast<double*>(b + L.part);
+    double* sc = reinterpret_cast<double*>(b + L.scal);
+    QRCTM_TRY(left_column(ca.C, ca.T, chi, Dab, F, E1, st));
+    if (z32v) QRCTM_TRY(dot(E1, E1, (long long)chi * Dab * chi, 0, 1, 0, part, sc + 0, st));
+    if (z22v) {
+        GemmDesc g;  // C2 = C C into F
+        g.M = chi; g.N = chi; g.K = chi;
+        g.A = ca.C; g.lda = chi; g.B = ca.C; g.ldb = chi;
+        g.C = F; g.map = OutMap::plain(chi, chi, chi);
+        QRCTM_TRY(gemm_f64(g, nullptr, 0, st));
+        QRCTM_TRY(dot(F, F, (long long)chi * chi, chi, chi, 1, part, sc + 1, st));
+    }
+    const double* ct = ca.a;
+    if (imp_dev) {
+        double* imp = reinterpret_cast<double*>(b + L.imp);
+        QRCTM_TRY(dl_to_internal(imp_dev, Dab, imp, st));
+        QRCTM_TRY(z33(ca, L, imp, sc + 3, st));
+    }
+    QRCTM_TRY(z33(ca, L, ct, sc + 2, st));
+    double h[4] = {0, 0, 0, 0};
+    QRCTM_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
+    QRCTM_HIP(hipStreamSynchronize(st));
+    if (z32v) *z32v = h[0];
+    if (z22v) *z22v = h[1];
+    if (z33v) *z33v = imp_dev ? h[3] / h[2] : h[2];
+    return s;
+}
+
+}  // namespace
+
+size_t energy_scratch_bytes(int d, int D, int chi) { return e_layout(d, D, chi).total; }
+size_t classical_scratch_bytes(int Dab, int chi) { return c_layout(Dab, chi).total; }
+
+Status classical_lnz(const ClassicalArgs& ca, double* lnk, hipStream_t st) {
+    double a = 0, b = 0, c = 0;
+    QRCTM_TRY(classical_parts(ca, &a, &b, &c, nullptr, st));
+    *lnk = std::log(a) + std::log(b) - 2.0 * std::log(c);
+    return Status{};
+}
+
+Status classical_expect(const ClassicalArgs& ca, const double* imp, double* v, hipStream_t st) {
+    return classical_parts(ca, v, nullptr, nullptr, imp, st);
+}
+
+Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
+                   double* E, hipStream_t st) {
+    Status s;
+    if (h_nnn != nullptr && J2 != 0.0) {
+        s.code = -1;
+        s.msg = "energy: the next-nearest-neighbour term is not available in this build";
+        return s;
+    }
+    const int d = ea.d, D = ea.D, chi = ea.chi;
+    const int Dab = D * D;
+    const ELayout L = e_layout(d, D, chi);
+    if (ea.ws_bytes < L.total) {
+        s.code = -2;
+        s.msg = "energy: scratch too small";
+        return s;
+    }
+    char* b = ea.ws;
+    auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    double *E1 = P(L.E1), *F = P(L.F), *X = P(L.X), *Yb = P(L.Yb), *Left = P(L.Left), *Lp = P(L.Lp);
+    double *Ak = P(L.Ak), *rho = P(L.rho), *hd = P(L.h), *sc = P(L.scal);
+    void* sk = b + L.splitk;
+    const long long c = chi, DD = D, D2 = Dab, dd = d;
+
+    QRCTM_TRY(left_column(ea.C, ea.T, chi, Dab, F, E1, st));
+    // E2[(U,w),(L,t)] = sum_q T[q,U,w] E1[q,L,t]  -> X, layout [u][u'][w][l][l'][t]
+    {
+        GemmDesc g;
+        g.trans_a = 1;
+        g.M = D2 * c; g.N = D2 * c; g.K = c;
+        g.A = ea.T; g.lda = D2 * c; g.B = E1; g.ldb = D2 * c;
+        g.C = X; g.map = OutMap::plain(g.M, g.N, g.N);
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    // -> Yb[w][t][u'][l'][u][l]
+    {
+        const long long dims[6] = {DD, DD, c, DD, DD, c};
+        const int axes[6] = {2, 5, 1, 4, 0, 3};
+        QRCTM_TRY(permute(X, Yb, 6, dims, axes, st));
+    }
+    // Ak[u][l][s][d][r] from As[s][u][l][d][r]
+    {
+        const long long dims[5] = {dd, DD, DD, DD, DD};
+        const int axes[5] = {1, 2, 0, 3, 4};
+        QRCTM_TRY(permute(ea.As, Ak, 5, dims, axes, st));
+    }
+    // ket: rows (w,t,u',l'), K (u,l), cols (s,d,r) -> X as [w][t][s][d][r][u'][l']
+    {
+        GemmDesc g;
+        g.M = c * c * D2; g.N = dd * D2; g.K = D2;
+        g.A = Yb; g.lda = D2; g.B = Ak; g.ldb = dd * D2;
+        g.C = X;
+        g.map = OutMap{D2, dd * D2 * D2, 1, dd * D2, 0, D2};
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    // bra: rows (w,t,s,d,r), K (u',l'), cols (s',d',r') -> Yb [w][t][s][d][r][s'][d'][r']
+    {
+        GemmDesc g;
+        g.M = c * c * dd * D2; g.N = dd * D2; g.K = D2;
+        g.A = X; g.lda = D2; g.B = Ak; g.ldb = dd * D2;
+        g.C = Yb; g.map = OutMap::plain(g.M, g.N, g.N);
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    // -> X [w][s][s'][r][r'][t][d][d']
+    {
+        const long long dims[8] = {c, c, dd, DD, DD, dd, DD, DD};
+        const int axes[8] = {0, 2, 5, 4, 7, 1, 3, 6};
+        QRCTM_TRY(permute(Yb, X, 8, dims, axes, st));
+    }
+    // Left[(w,s,s',R), v] = sum_{(t,Dn)} X[(w,s,s',R),(t,Dn)] T[(t,Dn), v]
+    {
+        GemmDesc g;
+        g.M = c * dd * dd * D2; g.N = c; g.K = c * D2;
+        g.A = X; g.lda = c * D2; g.B = ea.T; g.ldb = c;
+        g.C = Left; g.map = OutMap::plain(g.M, g.N, g.N);
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    // Lp[(s,s'), (w,R,v)]
+    {
+        const long long dims[5] = {c, dd, dd, D2, c};
+        const int axes[5] = {1, 2, 0, 3, 4};
+        QRCTM_TRY(permute(Left, Lp, 5, dims, axes, st));
+    }
+    // rho = Lp Lp^T
+    {
+        GemmDesc g;
+        g.trans_b = 1;
+        g.M = dd * dd; g.N = dd * dd; g.K = c * D2 * c;
+        g.A = Lp; g.lda = g.K; g.B = Lp; g.ldb = g.K;
+        g.C = rho; g.map = OutMap::plain(g.M, g.N, g.N);
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    QRCTM_HIP(hipMemcpyAsync(hd, h_nn, sizeof(double) * d * d * d * d, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, rho, hd, d, 2.0, sc, 0);
+    QRCTM_TRY(launch_check("bond_energy_kernel"));
+    double h = NAN;
+    QRCTM_HIP(hipMemcpyAsync(&h, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    QRCTM_HIP(hipStreamSynchronize(st));
+    *E = h;
+    (void)J2;
+    return s;
+}
+
+}  // namespace qrctm

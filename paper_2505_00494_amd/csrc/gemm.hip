@@ -1,0 +1,285 @@
+// FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64), gfx950.
+//
+// Every contraction of the QR-CTMRG step is one call of this kernel: the index
+// permutations of the tensor network are absorbed into the operand strides
+// (row- or column-major A and B) and into a two-level output map, so no tensor
+// is ever transposed in memory.
+//
+// Tiling: a workgroup computes a BM x BN tile of C with (BM/WM) x (BN/WN) waves;
+// each wave owns a WM x WN sub-tile held in (WM/16) x (WN/16) MFMA accumulators.
+// K advances in slabs of BK staged through LDS (double buffered, one barrier per
+// slab), stored k-major so that every MFMA operand fetch is 16 consecutive
+// doubles per quarter-wave.
+#include "common.h"
+
+namespace qrctm {
+namespace {
+
+struct KArgs {
+    long long M, N, K;
+    const double* A;
+    long long lda;
+    const double* B;
+    long long ldb;
+    double* C;
+    OutMap map;
+    double alpha, beta;
+    long long kchunk;  // K range per split (split index = blockIdx.y)
+    int tiles_m, tiles_n;
+    int partial;       // 1: write raw sums to C + split*M*N (plain M x N)
+};
+
+__device__ __forceinline__ long long out_index(const OutMap& mp, long long m, long long n) {
+    return (m / mp.mdiv) * mp.ms1 + (m % mp.mdiv) * mp.ms2 + (n / mp.ndiv) * mp.ns1 +
+           (n % mp.ndiv) * mp.ns2;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KArgs p) {
+    constexpr int NWN = BN / WN;
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
+    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile/thread mismatch");
+    constexpr int PAD = 2;  // doubles; breaks the power-of-two row stride
+    __shared__ double As[2][BK][BM + PAD];
+    __shared__ double Bs[2][BK][BN + PAD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / NWN, wn = wave % NWN;
+
+    // grouped tile order: GROUP consecutive tile rows share B columns in L2
+    constexpr int GROUP = 8;
+    const int bid = blockIdx.x;
+    const int per_group = GROUP * p.tiles_n;
+    const int g = bid / per_group;
+    const int first_m = g * GROUP;
+    const int gsz = min(p.tiles_m - first_m, GROUP);
+    const int tm = first_m + (bid % per_group) % gsz;
+    const int tn = (bid % per_group) / gsz;
+    const long long m0 = (long long)tm * BM, n0 = (long long)tn * BN;
+
+    const long long kbeg = (long long)blockIdx.y * p.kchunk;
+    const long long kend = min(p.K, kbeg + p.kchunk);
+
+    double ra[LA], rb[LB];
+
+    auto load = [&](long long k0) {
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int e = tid + i * NT;
+            int mm, kk;
+            if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+            const long long gm = m0 + mm, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < p.M && gk < kend) v = TA ? p.A[gk * p.lda + gm] : p.A[gm * p.lda + gk];
+            ra[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int e = tid + i * NT;
+            int nn, kk;
+            if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+            const long long gn = n0 + nn, gk = k0 + kk;
+            double v = 0.0;
+            if (gn < p.N && gk < kend) v = TB ? p.B[gn * p.ldb + gk] : p.B[gk * p.ldb + gn];
+            rb[i] = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int e = tid + i * NT;
+            int mm, kk;
+            if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+            As[buf][kk][mm] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int e = tid + i * NT;
+            int nn, kk;
+            if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+            Bs[buf][kk][nn] = rb[i];
+        }
+    };
+
+    dbl4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    const int lrow = lane & 15;  // operand row/col within a 16-block
+    const int lk = lane >> 4;    // k within a 4-slab
+
+    int buf = 0;
+    if (kbeg < kend) {
+        load(kbeg);
+        store(0);
+    }
+    __syncthreads();
+    for (long long k0 = kbeg; k0 < kend; k0 += BK) {
+        const bool more = k0 + BK < kend;
+        if (more) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            double af[FM], bf[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) af[i] = As[buf][kk * 4 + lk][wm * WM + i * 16 + lrow];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bf[j] = Bs[buf][kk * 4 + lk][wn * WN + j * 16 + lrow];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
+    const long long MN = p.M * p.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const long long n = n0 + wn * WN + j * 16 + lrow;
+            if (n >= p.N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long m = m0 + wm * WM + i * 16 + 4 * lk + r;
+                if (m >= p.M) continue;
+                const double v = acc[i][j][r];
+                if (p.partial) {
+                    p.C[(long long)blockIdx.y * MN + m * p.N + n] = v;
+                } else {
+                    const long long o = out_index(p.map, m, n);
+                    p.C[o] = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * p.C[o];
+                }
+            }
+        }
+}
+
+// Sum of split-K partials, then the output map / alpha / beta.
+__global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits, long long M,
+                                     long long N, double* C, OutMap mp, double alpha,
+                                     double beta) {
+    const long long MN = M * N;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < MN;
+         e += (long long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int z = 0; z < splits; ++z) s += part[z * MN + e];
+        const long long m = e / N, n = e % N;
+        const long long o = out_index(mp, m, n);
+        C[o] = beta == 0.0 ? alpha * s : alpha * s + beta * C[o];
+    }
+}
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+void launch_cfg(const KArgs& a, int splits, hipStream_t st) {
+    constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    dim3 grid(a.tiles_m * a.tiles_n, splits);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, TA, TB>), grid, dim3(NT), 0, st, a);
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+void launch_t(const KArgs& a, int ta, int tb, int splits, hipStream_t st) {
+    if (!ta && !tb) launch_cfg<BM, BN, BK, WM, WN, false, false>(a, splits, st);
+    else if (!ta && tb) launch_cfg<BM, BN, BK, WM, WN, false, true>(a, splits, st);
+    else if (ta && !tb) launch_cfg<BM, BN, BK, WM, WN, true, false>(a, splits, st);
+    else launch_cfg<BM, BN, BK, WM, WN, true, true>(a, splits, st);
+}
+
+struct Plan {
+    int cfg;      // 0: 128x128, 1: 64x64
+    int bm, bn;
+    int splits;
+    long long kchunk;
+};
+
+constexpr int kTargetBlocks = 512;
+
+Plan make_plan(const GemmDesc& g) {
+    Plan pl{};
+    const long long t128 = ceil_div(g.M, 128) * ceil_div(g.N, 128);
+    if (t128 >= 256) {
+        pl.cfg = 0; pl.bm = 128; pl.bn = 128;
+    } else {
+        pl.cfg = 1; pl.bm = 64; pl.bn = 64;
+    }
+    const long long tiles = ceil_div(g.M, pl.bm) * ceil_div(g.N, pl.bn);
+    pl.splits = 1;
+    pl.kchunk = g.K > 0 ? g.K : 1;
+    if (tiles < kTargetBlocks / 2 && g.K >= 512) {
+        long long s = kTargetBlocks / tiles;
+        const long long max_s = g.K / 256;  // keep >= 256 of K per split
+        if (s > max_s) s = max_s;
+        if (s > 64) s = 64;
+        if (s >= 2) {
+            long long kc = ceil_div(g.K, s);
+            kc = ceil_div(kc, 16) * 16;
+            pl.splits = (int)ceil_div(g.K, kc);
+            pl.kchunk = kc;
+        }
+    }
+    return pl;
+}
+
+}  // namespace
+
+size_t gemm_splitk_bytes(const GemmDesc& g) {
+    const Plan pl = make_plan(g);
+    return pl.splits > 1 ? (size_t)pl.splits * g.M * g.N * sizeof(double) : 0;
+}
+
+Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStream_t st) {
+    Status s;
+    if (g.M <= 0 || g.N <= 0) return s;
+    if (g.K <= 0) {
+        // C = beta * C (alpha * empty sum)
+        // handled by a split-less pass of the reduce kernel with zero partials
+        // is wasteful; K == 0 never occurs on the CTMRG path.
+        s.code = -1;
+        s.msg = "gemm_f64: K must be positive";
+        return s;
+    }
+    const Plan pl = make_plan(g);
+    KArgs a{};
+    a.M = g.M; a.N = g.N; a.K = g.K;
+    a.A = g.A; a.lda = g.lda; a.B = g.B; a.ldb = g.ldb;
+    a.alpha = g.alpha; a.beta = g.beta; a.map = g.map;
+    a.kchunk = pl.kchunk;
+    a.tiles_m = (int)ceil_div(g.M, pl.bm);
+    a.tiles_n = (int)ceil_div(g.N, pl.bn);
+    if (pl.splits > 1) {
+        const size_t need = (size_t)pl.splits * g.M * g.N * sizeof(double);
+        if (splitk_ws == nullptr || splitk_bytes < need) {
+            s.code = -2;
+            s.msg = "gemm_f64: split-K scratch too small";
+            return s;
+        }
+        a.C = static_cast<double*>(splitk_ws);
+        a.partial = 1;
+    } else {
+        a.C = g.C;
+        a.partial = 0;
+    }
+    if (pl.cfg == 0) launch_t<128, 128, 16, 64, 64>(a, g.trans_a, g.trans_b, pl.splits, st);
+    else launch_t<64, 64, 16, 32, 32>(a, g.trans_a, g.trans_b, pl.splits, st);
+    QRCTM_TRY(launch_check("gemm_f64_kernel"));
+    if (pl.splits > 1) {
+        const long long MN = g.M * g.N;
+        const int blocks = (int)std::min<long long>(ceil_div(MN, 256), 4096);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, st,
+                           static_cast<const double*>(splitk_ws), pl.splits, g.M, g.N, g.C, g.map,
+                           g.alpha, g.beta);
+        QRCTM_TRY(launch_check("splitk_reduce_kernel"));
+    }
+    return s;
+}
+
+}  // namespace qrctm

@@ -1,0 +1,20 @@
+// Householder QR with diag(R) >= 0 (qr.hip).
+#pragma once
+#include "common.h"
+
+namespace qrctm {
+
+struct QrScratch {
+    size_t off_V, off_tau, off_part, off_rowbuf, off_G, off_T, off_MT, off_ratio, off_splitk;
+    size_t splitk_bytes;
+    size_t total;
+};
+
+QrScratch qr_scratch_layout(int m, int n);
+bool qr_fits(int m, int n);
+// Q (m x n) and R (n x n) from M (m x n), all device, row-major.  diag_ratio_dev
+// (device, may be null) receives min|R_ii| / max|R_ii|.  Q may alias M.
+Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
+              hipStream_t st, double* diag_ratio_dev);
+
+}  // namespace qrctm

@@ -1,0 +1,358 @@
+// Thin Householder QR of a tall matrix M (m x n, m >= n) with diag(R) >= 0.
+//
+// QR-CTMRG replaces the eigen/SVD decomposition by an unpivoted QR of the
+// reduced corner (QR-CTMRG paragraph, Fig. 1e).  The factorisation here is the
+// Householder one, organised for a machine with 256 compute units:
+//
+//  1. qr_factor_kernel (cooperative launch, one workgroup per compute unit):
+//     every workgroup keeps a contiguous block of rows of M in LDS for the
+//     whole factorisation.  Column j needs, over all rows below j, the sum of
+//     squares of column j and its dot products with every later column; each
+//     workgroup reduces its rows (wavefront-parallel over columns, LDS over
+//     row groups), publishes the partial sums, and after ONE grid barrier every
+//     workgroup combines them in a fixed order, forms the reflector and updates
+//     its own rows.  The reflector is generated with beta = +||x|| (the
+//     non-negative-diagonal variant, cancellation-free gamma = alpha - beta), so
+//     R has diag(R) >= 0 without a sign fix.
+//  2. the compact-WY factor T of H_0 ... H_{n-1} = I - V T V^T from the Gram
+//     matrix G = V^T V (an FP64 MFMA GEMM) and tau (qr_tfactor_kernel);
+//  3. the explicit thin factor Q = [I; 0] - V (T V1^T) by two more MFMA GEMMs
+//     (V1 = first n rows of V).
+#include <hip/hip_cooperative_groups.h>
+
+#include "common.h"
+#include "qr.h"
+
+namespace cg = cooperative_groups;
+
+namespace qrctm {
+namespace {
+
+constexpr int kQrThreads = 256;
+constexpr int kColGroup = 64;  // columns handled in parallel by one row group
+constexpr int kRowGroups = kQrThreads / kColGroup;
+constexpr size_t kQrLdsBudget = 150 * 1024;
+
+struct QrLayout {
+    int P;   // workgroups
+    int rb;  // rows per workgroup
+    size_t lds_bytes;
+};
+
+size_t lds_for(int rb, int n) {
+    // row block + v (rb) + w (n) + row-group partials (kRowGroups x (n+1)) + scalars
+    return sizeof(double) * ((size_t)rb * n + rb + n + (size_t)kRowGroups * (n + 1) + 8);
+}
+
+// Partial sums of column jc over the rows of this block that lie strictly below jc:
+// slot 0 = sum x_i^2, slot 1 + (k - jc - 1) = sum x_i a_ik for k > jc.
+__device__ void column_partials(const double* Ab, int nr, int r0, int n, int jc, double* red,
+                                double* out) {
+    const int tid = threadIdx.x;
+    const int cg_ = tid % kColGroup, rg = tid / kColGroup;
+    const int nslots = n - jc;  // slot s: s == 0 -> column jc itself, else column jc + s
+    const int istart = max(0, jc + 1 - r0);
+    for (int s = cg_; s < nslots; s += kColGroup) {
+        const int k = jc + s;
+        double acc = 0.0;
+        for (int i = istart + rg; i < nr; i += kRowGroups) acc += Ab[i * n + jc] * Ab[i * n + k];
+        red[rg * (n + 1) + s] = acc;
+    }
+    __syncthreads();
+    for (int s = tid; s < nslots; s += kQrThreads) {
+        double acc = 0.0;
+        for (int g = 0; g < kRowGroups; ++g) acc += red[g * (n + 1) + s];
+        out[s] = acc;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __restrict__ M, int m,
+                                                               int n, int rb, double* V, double* R,
+                                                               double* tau, double* part,
+                                                               double* rowbuf) {
+    extern __shared__ double lds[];
+    cg::grid_group grid = cg::this_grid();
+    const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
+    const int r0 = p * rb;
+    const int nr = max(0, min(rb, m - r0));
+    double* Ab = lds;
+    double* vloc = Ab + (size_t)rb * n;
+    double* wv = vloc + rb;
+    double* red = wv + n;
+    double* sc = red + kRowGroups * (n + 1);
+    const size_t pstride = (size_t)P * (n + 1);
+
+    for (int e = tid; e < nr * n; e += kQrThreads) Ab[e] = M[(size_t)r0 * n + e];
+    __syncthreads();
+
+    // column 0 partials and row 0
+    column_partials(Ab, nr, r0, n, 0, red, part + (size_t)p * (n + 1));
+    if (r0 <= 0 && 0 < r0 + nr)
+        for (int k = tid; k < n; k += kQrThreads) rowbuf[k] = Ab[(0 - r0) * n + k];
+
+    for (int j = 0; j < n; ++j) {
+        grid.sync();
+        const double* pp = part + (size_t)(j & 1) * pstride;
+        const double* row = rowbuf + (size_t)(j & 1) * n;
+        const int nslots = n - j;
+        // combine partials in a fixed order (deterministic)
+        for (int s = tid; s < nslots; s += kQrThreads) {
+            double acc = 0.0;
+            for (int q = 0; q < P; ++q) acc += pp[(size_t)q * (n + 1) + s];
+            wv[j + s] = acc;  // wv[j] = sigma^2, wv[k] = dot_k (k > j)
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double alpha = row[j];
+            const double sigma2 = wv[j];
+            double beta, t, gamma;
+            int mode;  // 0: H = I, 1: sign flip e_j, 2: general reflector
+            if (sigma2 == 0.0) {
+                if (alpha >= 0.0) { mode = 0; beta = alpha; t = 0.0; gamma = 1.0; }
+                else { mode = 1; beta = -alpha; t = 2.0; gamma = 1.0; }
+            } else {
+                mode = 2;
+                beta = sqrt(alpha * alpha + sigma2);
+                gamma = alpha <= 0.0 ? alpha - beta : -sigma2 / (alpha + beta);
+                t = -gamma / beta;
+            }
+            sc[0] = beta; sc[1] = t; sc[2] = gamma; sc[3] = (double)mode; sc[4] = alpha;
+        }
+        __syncthreads();
+        const double beta = sc[0], t = sc[1], gamma = sc[2], alpha = sc[4];
+        const int mode = (int)sc[3];
+        // w_k = v^T a_k over rows >= j (v_j = 1)
+        for (int k = j + 1 + tid; k < n; k += kQrThreads) {
+            const double ajk = row[k];
+            double w;
+            if (mode == 2) w = wv[k] / gamma + ajk;
+            else w = ajk;  // v = e_j
+            wv[k] = w;
+        }
+        (void)alpha;
+        __syncthreads();
+        if (p == 0) {
+            for (int k = tid; k < n; k += kQrThreads) {
+                double r;
+                if (k < j) r = 0.0;
+                else if (k == j) r = beta;
+                else r = row[k] - t * wv[k];
+                R[(size_t)j * n + k] = r;
+            }
+            if (tid == 0) tau[j] = t;
+        }
+        // v for local rows
+        for (int i = tid; i < nr; i += kQrThreads) {
+            const int gi = r0 + i;
+            double v;
+            if (gi < j) v = 0.0;
+            else if (gi == j) v = 1.0;
+            else v = (mode == 2) ? Ab[i * n + j] / gamma : 0.0;
+            vloc[i] = v;
+            V[(size_t)gi * n + j] = v;
+        }
+        __syncthreads();
+        // apply H_j to the local rows strictly below j (row j is R's row)
+        if (mode != 0) {
+            const int istart = max(0, j + 1 - r0);
+            const int ncol = n - j - 1;
+            const int rows = nr - istart;
+            for (int e = tid; e < rows * ncol; e += kQrThreads) {
+                const int i = istart + e / ncol, k = j + 1 + e % ncol;
+                Ab[i * n + k] -= t * vloc[i] * wv[k];
+            }
+        }
+        __syncthreads();
+        if (j + 1 < n) {
+            column_partials(Ab, nr, r0, n, j + 1, red,
+                            part + (size_t)((j + 1) & 1) * pstride + (size_t)p * (n + 1));
+            // publish row j+1 (already final in columns > j)
+            if (r0 <= j + 1 && j + 1 < r0 + nr) {
+                double* nrow = rowbuf + (size_t)((j + 1) & 1) * n;
+                for (int k = tid; k < n; k += kQrThreads) nrow[k] = Ab[(j + 1 - r0) * n + k];
+            }
+        }
+    }
+}
+
+// T[i][j] (i <= j): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j].
+// Also the diagonal ratio min|R_ii| / max|R_ii| into diag_ratio.
+__global__ __launch_bounds__(1024) void qr_tfactor_kernel(const double* __restrict__ G,
+                                                          const double* __restrict__ tau, int n,
+                                                          double* T, const double* R,
+                                                          double* diag_ratio) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) T[e] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double tj = tau[j];
+        double val = 0.0;
+        const int i = tid;
+        if (i < j) {
+            double acc = 0.0;
+            for (int l = i; l < j; ++l) acc += T[(size_t)i * n + l] * G[(size_t)l * n + j];
+            val = -tj * acc;
+        }
+        __syncthreads();
+        if (i < j) T[(size_t)i * n + j] = val;
+        if (i == j) T[(size_t)j * n + j] = tj;
+        __syncthreads();
+    }
+    if (tid == 0 && diag_ratio != nullptr) {
+        double mn = INFINITY, mx = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double d = fabs(R[(size_t)k * n + k]);
+            mn = fmin(mn, d);
+            mx = fmax(mx, d);
+        }
+        *diag_ratio = mx > 0.0 ? mn / mx : 0.0;
+    }
+}
+
+__global__ void eye_kernel(double* Q, long long m, int n) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < m * n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / n, c = e % n;
+        Q[e] = (i == c) ? 1.0 : 0.0;
+    }
+}
+
+QrLayout plan_qr(int m, int n) {
+    QrLayout L{};
+    // fewest workgroups whose row blocks fit in LDS (fewer partial sums to combine)
+    int P = 1;
+    while (P < 256 && lds_for((int)ceil_div(m, P), n) > kQrLdsBudget) P *= 2;
+    // at most 128 rows per workgroup to spread the O(m n^2) updates
+    while (P < 256 && ceil_div(m, P) > 128) P *= 2;
+    if (P > 256) P = 256;
+    L.P = P;
+    L.rb = (int)ceil_div(m, P);
+    L.P = (int)ceil_div(m, L.rb);
+    L.lds_bytes = lds_for(L.rb, n);
+    return L;
+}
+
+}  // namespace
+
+QrScratch qr_scratch_layout(int m, int n) {
+    QrScratch s{};
+    const QrLayout L = plan_qr(m, n);
+    size_t off = 0;
+    auto take = [&](size_t count) {
+        const size_t o = off;
+        off += ((count * sizeof(double) + 255) / 256) * 256;
+        return o;
+    };
+    s.off_V = take((size_t)m * n);
+    s.off_tau = take(n);
+    s.off_part = take(2 * (size_t)L.P * (n + 1));
+    s.off_rowbuf = take(2 * (size_t)n);
+    s.off_G = take((size_t)n * n);
+    s.off_T = take((size_t)n * n);
+    s.off_MT = take((size_t)n * n);
+    s.off_ratio = take(1);
+    GemmDesc gg;
+    gg.M = n; gg.N = n; gg.K = m;
+    const size_t sk = gemm_splitk_bytes(gg);
+    s.off_splitk = take(sk / sizeof(double) + 1);
+    s.splitk_bytes = sk;
+    s.total = off;
+    return s;
+}
+
+bool qr_fits(int m, int n) {
+    if (m < n || n < 1) return false;
+    const QrLayout L = plan_qr(m, n);
+    return L.lds_bytes <= kQrLdsBudget + 8192 && n <= 1024;
+}
+
+Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
+              hipStream_t st, double* diag_ratio_dev) {
+    Status s;
+    if (!qr_fits(m, n)) {
+        s.code = -1;
+        s.msg = "qr: shape not supported (need m >= n, n <= 1024, row blocks within LDS)";
+        return s;
+    }
+    const QrScratch L = qr_scratch_layout(m, n);
+    if (ws_bytes < L.total) {
+        s.code = -2;
+        s.msg = "qr: workspace too small";
+        return s;
+    }
+    char* base = static_cast<char*>(ws);
+    double* V = reinterpret_cast<double*>(base + L.off_V);
+    double* tau = reinterpret_cast<double*>(base + L.off_tau);
+    double* part = reinterpret_cast<double*>(base + L.off_part);
+    double* rowbuf = reinterpret_cast<double*>(base + L.off_rowbuf);
+    double* G = reinterpret_cast<double*>(base + L.off_G);
+    double* T = reinterpret_cast<double*>(base + L.off_T);
+    double* MT = reinterpret_cast<double*>(base + L.off_MT);
+    double* ratio = diag_ratio_dev ? diag_ratio_dev : reinterpret_cast<double*>(base + L.off_ratio);
+    void* sk = base + L.off_splitk;
+
+    const QrLayout ql = plan_qr(m, n);
+    {
+        int dev = 0;
+        QRCTM_HIP(hipGetDevice(&dev));
+        QRCTM_HIP(hipFuncSetAttribute((const void*)qr_factor_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)ql.lds_bytes));
+        int nblk = 0;
+        QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, qr_factor_kernel, kQrThreads,
+                                                               ql.lds_bytes));
+        int ncu = 0;
+        QRCTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        if ((long long)nblk * ncu < ql.P) {
+            s.code = -1;
+            s.msg = "qr: cooperative grid does not fit on the device";
+            return s;
+        }
+        const double* Mp = M;
+        int mm = m, nn = n, rbb = ql.rb;
+        void* args[] = {(void*)&Mp, (void*)&mm, (void*)&nn, (void*)&rbb, (void*)&V,
+                        (void*)&R,  (void*)&tau, (void*)&part, (void*)&rowbuf};
+        QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_factor_kernel, dim3(ql.P),
+                                             dim3(kQrThreads), args, ql.lds_bytes, st));
+    }
+    // G = V^T V
+    {
+        GemmDesc g;
+        g.trans_a = 1; g.trans_b = 0;
+        g.M = n; g.N = n; g.K = m;
+        g.A = V; g.lda = n; g.B = V; g.ldb = n;
+        g.C = G; g.map = OutMap::plain(n, n, n);
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    hipLaunchKernelGGL(qr_tfactor_kernel, dim3(1), dim3(1024), 0, st, G, tau, n, T, R, ratio);
+    QRCTM_TRY(launch_check("qr_tfactor_kernel"));
+    // MT = T V1^T
+    {
+        GemmDesc g;
+        g.trans_a = 0; g.trans_b = 1;
+        g.M = n; g.N = n; g.K = n;
+        g.A = T; g.lda = n; g.B = V; g.ldb = n;
+        g.C = MT; g.map = OutMap::plain(n, n, n);
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    {
+        const long long tot = (long long)m * n;
+        const int blocks = (int)std::min<long long>(ceil_div(tot, 256), 4096);
+        hipLaunchKernelGGL(eye_kernel, dim3(blocks), dim3(256), 0, st, Q, (long long)m, n);
+        QRCTM_TRY(launch_check("eye_kernel"));
+    }
+    // Q = E - V MT
+    {
+        GemmDesc g;
+        g.trans_a = 0; g.trans_b = 0;
+        g.M = m; g.N = n; g.K = n;
+        g.A = V; g.lda = n; g.B = MT; g.ldb = n;
+        g.C = Q; g.map = OutMap::plain(m, n, n);
+        g.alpha = -1.0; g.beta = 1.0;
+        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
+    }
+    return s;
+}
+
+}  // namespace qrctm

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, and the workspace planner and argument
+checks behave."""
+import ctypes
+
+import pytest
+
+import paper_2505_00494_amd as P
+from paper_2505_00494_amd import qrctm as B
+
+
+def test_library_exports_every_declared_function():
+    L = P.lib()
+    names = P.header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(L, n)]
+    assert missing == []
+
+
+def test_default_opts():
+    o = B.default_opts()
+    assert o.precision == B.PREC_FP64 and o.n_warmup == -1 and o.k_tracked == 10
+
+
+def test_workspace_sizes_grow_with_problem():
+    L = P.lib()
+    small = L.ctm_workspace_bytes(2, 2, 16, None)
+    mid = L.ctm_workspace_bytes(2, 4, 64, None)
+    big = L.ctm_workspace_bytes(2, 6, 144, None)
+    assert 0 < small < mid < big
+    # Y and Z intermediates alone are chi^2 D^4 doubles each at D=6, chi=144
+    assert big > 2 * 144 * 144 * 36 * 36 * 8
+    assert L.ctm_workspace_bytes(0, 2, 16, None) == 0
+    assert L.ctm_workspace_bytes_dl(2, 32, None) > 0
+    assert L.ctm_qr_workspace_bytes(10, 20) == 0
+
+
+def test_invalid_arguments_rejected_before_any_gpu_work():
+    L = P.lib()
+    ctx = ctypes.c_void_p()
+    # null tensor
+    rc = L.ctm_init(ctypes.byref(ctx), None, 2, 2, 16, None, None, 0, None)
+    assert rc == B.CTM_EINVAL
+    assert b"invalid" in L.ctm_last_error(None)
+    # missing workspace (pointer value is never dereferenced on this path)
+    fake = ctypes.c_void_p(0x1000)
+    rc = L.ctm_init(ctypes.byref(ctx), fake, 2, 2, 16, None, None, 0, None)
+    assert rc == B.CTM_EWORKSPACE
+    # chi smaller than the bond dimension of the bulk tensor
+    rc = L.ctm_init(ctypes.byref(ctx), fake, 2, 4, 8, None, fake, 1 << 40, None)
+    assert rc == B.CTM_EINVAL
+    # invalid precision
+    o = B.default_opts()
+    o.precision = 7
+    rc = L.ctm_init(ctypes.byref(ctx), fake, 2, 2, 16, ctypes.byref(o), fake, 1 << 40, None)
+    assert rc == B.CTM_EINVAL
+    # null context on every context call
+    assert L.ctm_step(None, 1, None) == B.CTM_EINVAL
+    assert L.ctm_converge(None, 1e-10, 1, None, None) == B.CTM_EINVAL
+    assert L.ctm_energy(None, None, None, 0.0, None) == B.CTM_EINVAL
+    # QR shape check
+    assert L.ctm_qr(fake, fake, fake, 4, 8, fake, 1 << 20, None) == B.CTM_EINVAL
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        P.Context(A=[[1.0]], chi=4)

@@ -1,0 +1,155 @@
+"""GPU parity of the CTMRG path against the CPU oracle, through the C ABI.
+
+* One QR step at a time from the same environment: C and T elementwise (the
+  QR with diag(R) >= 0 makes the step a deterministic function of (C, T, a)).
+* Initialisation + warm-up (a1-a4): spectrum and environment.
+* The classical Ising network against Onsager / Yang and against the oracle.
+* The nearest-neighbour energy against the oracle.
+Tolerances are FP64 rounding budgets (see the design notes): 1e-12 relative on
+single steps, 1e-10 on energies.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2505_00494_amd as P  # noqa: E402
+from oracle import ctmrg as ctm  # noqa: E402
+from oracle import observables as obs  # noqa: E402
+from synth import inputs as inp  # noqa: E402
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def _oracle_setup(d, D, chi, seed):
+    A = inp.random_site_tensor(d, D, seed)
+    As = ctm.prepare_site_tensor(A)
+    a = ctm.double_layer(As)
+    C, T = ctm.warmup_env(a, chi, ctm.identity_boundary_vector(D))
+    return A, As, a, C, T
+
+
+def _rel(x, y):
+    return np.abs(x - y).max() / np.abs(y).max()
+
+
+@pytest.mark.parametrize("d,D,chi,nsteps", [(2, 2, 16, 6), (2, 3, 36, 4), (2, 4, 64, 3),
+                                            (2, 6, 144, 2)])
+def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps):
+    print(f"steps d={d} D={D} chi={chi}", flush=True)
+    A, As, a, C, T = _oracle_setup(d, D, chi, seed=1)
+    ctx = P.Context(_dev(A), chi, n_warmup=0)
+    ctx.set_env(_dev(C), _dev(T))
+    s_prev = ctm.spectrum(C)
+    for i in range(nsteps):
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+        s = ctm.spectrum(C)
+        dl_ref = ctm.spectrum_delta(s, s_prev)
+        s_prev = s
+        dl = ctx.step(1)
+        Cg, Tg = [x.cpu().numpy() for x in ctx.get_env()]
+        tol = 1e-12 * (10 ** i)
+        assert _rel(Cg, C) < tol, (i, _rel(Cg, C))
+        assert _rel(Tg, T) < tol, (i, _rel(Tg, T))
+        assert np.abs(ctx.spectrum() - s).max() < 1e-12
+        assert abs(dl - dl_ref) < 1e-12 + 1e-9 * dl_ref
+    st = ctx.stats()
+    assert st["steps"] == nsteps and st["chi_cur"] == chi
+    assert 0 < st["r_diag_ratio"] <= 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("d,D,chi", [(2, 2, 16), (2, 4, 64), (2, 6, 144)])
+def test_init_and_warmup_match_oracle(d, D, chi):
+    print(f"init d={d} D={D} chi={chi}", flush=True)
+    A, As, a, C, T = _oracle_setup(d, D, chi, seed=1)
+    ctx = P.Context(_dev(A), chi)
+    Cg, Tg = [x.cpu().numpy() for x in ctx.get_env()]
+    assert Cg.shape == C.shape and Tg.shape == T.shape
+    # corner after the standard step is diag(lambda): gauge invariant
+    assert np.abs(np.diag(Cg) - np.diag(C)).max() < 1e-12
+    assert np.abs(Cg - np.diag(np.diag(Cg))).max() == 0.0
+    assert np.abs(ctx.spectrum() - ctm.spectrum(C)).max() < 1e-12
+    # edge: eigenvector signs are fixed; compare columns whose eigenvalue is
+    # separated from its neighbours (degenerate pairs have no unique basis)
+    lam = np.diag(C)
+    gap = np.ones(chi, bool)
+    for i in range(chi):
+        for j in range(chi):
+            if i != j and abs(abs(lam[i]) - abs(lam[j])) < 1e-9 * abs(lam).max():
+                gap[i] = False
+    idx = np.where(gap)[0]
+    assert idx.size > chi // 2
+    sub = np.ix_(idx, range(T.shape[1]), idx)
+    assert _rel(Tg[sub], T[sub]) < 1e-9
+    ctx.close()
+
+
+def test_converge_config0_matches_oracle():
+    d, D, chi = 2, 2, 16
+    A = inp.random_site_tensor(d, D, 1)
+    As = ctm.prepare_site_tensor(A)
+    a = ctm.double_layer(As)
+    r = ctm.ctmrg(a, chi, ctm.identity_boundary_vector(D), tol=1e-12, max_steps=40)
+    ctx = P.Context(_dev(A), chi)
+    ok, steps, dl = ctx.converge(1e-12, 40)
+    assert steps == r.steps
+    h = inp.heisenberg_bond_rotated()
+    e_ref = obs.energy_nn(r.C, r.T, As, h)
+    e = ctx.energy(h)
+    assert abs(e - e_ref) < 1e-10 * abs(e_ref)
+    assert np.abs(ctx.spectrum() - ctm.spectrum(r.C)).max() < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("d,D,chi", [(2, 2, 16), (2, 3, 27), (2, 4, 64)])
+def test_energy_matches_oracle(d, D, chi):
+    A, As, a, C, T = _oracle_setup(d, D, chi, seed=2)
+    for _ in range(3):
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+    ctx = P.Context(_dev(A), chi, n_warmup=0)
+    ctx.set_env(_dev(C), _dev(T))
+    for h in (inp.heisenberg_bond_rotated(), inp.heisenberg_bond()):
+        e_ref = obs.energy_nn(C, T, As, h)
+        assert abs(ctx.energy(h) - e_ref) < 1e-12 * abs(e_ref) + 1e-14
+    ctx.close()
+
+
+def onsager_lnz_1d(K):
+    from scipy import integrate
+    kap = 2 * np.sinh(2 * K) / np.cosh(2 * K) ** 2
+    g = lambda t: np.log(0.5 * (1 + np.sqrt(1 - kap * kap * np.sin(t) ** 2)))
+    v, _ = integrate.quad(g, 0, np.pi / 2, epsabs=1e-14, epsrel=1e-14, limit=200)
+    return np.log(2 * np.cosh(2 * K)) + v / np.pi
+
+
+def test_ising_free_energy_and_magnetisation_on_gpu():
+    K = 0.40
+    a = inp.ising_classical_tensor(K)
+    ctx = P.Context(a=_dev(a), bvec=_dev(inp.ising_boundary_vector(K)), chi=32)
+    ok, steps, dl = ctx.converge(1e-13, 4000)
+    assert ok
+    assert abs(ctx.lnz_per_site() - onsager_lnz_1d(K)) < 1e-10
+    assert abs(ctx.expect_site(_dev(inp.ising_impurity_tensor(K)))) < 1e-12
+    ctx.close()
+    K = 0.50
+    a = inp.ising_classical_tensor(K)
+    ctx = P.Context(a=_dev(a), bvec=_dev(inp.ising_boundary_vector(K, biased=True)), chi=32)
+    ok, steps, dl = ctx.converge(1e-13, 2000)
+    m = ctx.expect_site(_dev(inp.ising_impurity_tensor(K)))
+    yang = (1 - np.sinh(2 * K) ** -4) ** 0.125
+    assert abs(m - yang) < 1e-9
+    assert abs(ctx.lnz_per_site() - onsager_lnz_1d(K)) < 1e-10
+    ctx.close()
+
+
+def test_nonfinite_tensor_is_reported():
+    A = inp.random_site_tensor(2, 2, 1)
+    A[0, 0, 0, 0, 0] = np.nan
+    with pytest.raises(P.CTMError) as e:
+        P.Context(_dev(A), 16)
+    assert e.value.code == -4
