@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqrctm.so")
 SOURCES = ["gemm.hip", "qr.hip", "tensor_ops.hip", "spectrum.hip", "eigh.hip", "energy.hip",
-           "ctm_abi.cpp"]
+           "adjoint.hip", "ctm_abi.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are disabled for every kernel

@@ -1,0 +1,23 @@
+// Non-GEMM kernels of the reverse pass (adjoint.hip).
+#pragma once
+#include "common.h"
+
+namespace qrctm {
+
+size_t sym_norm_backward_scratch_bytes();
+// (Cn, Tn) = sym_norm(Cp, Tp) with norms = (||sym Cp||, ||sym Tp||); given the
+// cotangents (Cb, Tb) of (Cn, Tn), write those of (Cp, Tp).
+Status sym_norm_backward(const double* Cn, const double* Tn, const double* Cb, const double* Tb,
+                         const double* norms, int chi, int Dab, double* Cpb, double* Tpb,
+                         double* part, hipStream_t st);
+Status copyltu(const double* M, int n, double* Ms, hipStream_t st);
+Status tri_inv_upper(const double* R, int n, double* Ri, hipStream_t st);
+// Asb += reverse of a_int = sum_s As (x) As (a_int layout [U][L][R][Dn])
+Status double_layer_backward(const double* abar, const double* As, int d, int D, double* Asb,
+                             hipStream_t st);
+// dA from the cotangent of As = P(A)/max|P(A)|
+Status c4v_backward(const double* Asb, const double* As, const double* scale, const int* imax,
+                    int d, int D, double* dA, hipStream_t st);
+Status ratio_min(const double* r, double* acc, bool reset, hipStream_t st);
+
+}  // namespace qrctm

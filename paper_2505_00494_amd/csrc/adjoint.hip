@@ -1,0 +1,232 @@
+// Kernels of the hand-written reverse pass (automatic-differentiation
+// paragraph: gradient through k tracked QR-CTMRG steps).  The GEMM adjoints
+// reuse gemm.hip; this file holds the non-GEMM pieces:
+//   sym_norm_backward   reverse of "symmetrise, divide by the Frobenius norm",
+//   copyltu             tril(M) + tril(M,-1)^T for the thin-QR adjoint
+//                       Abar = (Qbar + Q copyltu(R Rbar^T - Qbar^T Q)) R^{-T},
+//   tri_inv_upper       R^{-1} of the upper-triangular R (one column per thread),
+//   double_layer_backward, c4v_backward (reverse of a2 and a1),
+//   ratio_min           running minimum of min|R_ii|/max|R_ii| over tracked steps.
+#include "adjoint.h"
+#include "common.h"
+
+namespace qrctm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kBlocks = 512;
+
+__global__ __launch_bounds__(kThreads) void dots_kernel(const double* __restrict__ Cn,
+                                                        const double* __restrict__ Cb,
+                                                        const double* __restrict__ Tn,
+                                                        const double* __restrict__ Tb, long long nC,
+                                                        long long nT, double* part) {
+    __shared__ double rc[kThreads], rt[kThreads];
+    double sc = 0.0, st = 0.0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nC + nT;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (e < nC) sc += Cn[e] * Cb[e];
+        else st += Tn[e - nC] * Tb[e - nC];
+    }
+    rc[threadIdx.x] = sc;
+    rt[threadIdx.x] = st;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rc[threadIdx.x] += rc[threadIdx.x + w];
+            rt[threadIdx.x] += rt[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = rc[0];
+        part[2 * blockIdx.x + 1] = rt[0];
+    }
+}
+
+// Cpb[x,y] = (sym(Cb)[x,y] - <Cn,Cb> Cn[x,y]) / ||Cs||, same for T over (x <-> y)
+__global__ __launch_bounds__(kThreads) void sym_norm_bwd_kernel(
+    const double* __restrict__ part, int nparts, const double* __restrict__ norms,
+    const double* __restrict__ Cn, const double* __restrict__ Cb, const double* __restrict__ Tn,
+    const double* __restrict__ Tb, int chi, int Dab, double* Cpb, double* Tpb) {
+    __shared__ double s[2];
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < nparts; ++q) {
+            a += part[2 * q];
+            b += part[2 * q + 1];
+        }
+        s[0] = a;
+        s[1] = b;
+    }
+    __syncthreads();
+    const double dc = s[0], dt = s[1];
+    const double ic = 1.0 / norms[0], it = 1.0 / norms[1];
+    const long long nC = (long long)chi * chi, nT = nC * Dab;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nC + nT;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (e < nC) {
+            const long long x = e / chi, y = e % chi;
+            Cpb[e] = (0.5 * (Cb[e] + Cb[y * chi + x]) - dc * Cn[e]) * ic;
+        } else {
+            const long long f = e - nC;
+            const long long x = f / ((long long)Dab * chi), m = (f / chi) % Dab, y = f % chi;
+            Tpb[f] = (0.5 * (Tb[f] + Tb[(y * Dab + m) * chi + x]) - dt * Tn[f]) * it;
+        }
+    }
+}
+
+__global__ void copyltu_kernel(const double* __restrict__ M, int n, double* Ms) {
+    const long long nn = (long long)n * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / n, j = e % n;
+        Ms[e] = i >= j ? M[e] : M[j * n + i];
+    }
+}
+
+// column j of R^{-1}: back substitution R x = e_j, x_i = 0 for i > j
+__global__ void tri_inv_upper_kernel(const double* __restrict__ R, int n, double* Ri) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int i = n - 1; i > j; --i) Ri[(size_t)i * n + j] = 0.0;
+    for (int i = j; i >= 0; --i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+        for (int k = i + 1; k <= j; ++k) acc -= R[(size_t)i * n + k] * Ri[(size_t)k * n + j];
+        Ri[(size_t)i * n + j] = acc / R[(size_t)i * n + i];
+    }
+}
+
+// Asb[s,u,l,d,r] += sum_{u',l',d',r'} (abar[(u u'),(l l'),(r r'),(d d')] +
+//                   abar[(u' u),(l' l),(r' r),(d' d)]) As[s,u',l',d',r']
+__global__ void dl_backward_kernel(const double* __restrict__ abar, const double* __restrict__ As,
+                                   int d, int D, double* Asb) {
+    const int D4 = D * D * D * D;
+    const int D2 = D * D;
+    const int n = d * D4;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int s = e / D4;
+        int rem = e % D4;
+        const int r = rem % D; rem /= D;
+        const int dd = rem % D; rem /= D;
+        const int l = rem % D; rem /= D;
+        const int u = rem;
+        double acc = 0.0;
+        for (int q = 0; q < D4; ++q) {
+            int t = q;
+            const int r2 = t % D; t /= D;
+            const int d2 = t % D; t /= D;
+            const int l2 = t % D; t /= D;
+            const int u2 = t;
+            const double x = As[(size_t)s * D4 + q];
+            const size_t i1 = (((size_t)(u * D + u2) * D2 + (l * D + l2)) * D2 + (r * D + r2)) * D2 +
+                              (dd * D + d2);
+            const size_t i2 = (((size_t)(u2 * D + u) * D2 + (l2 * D + l)) * D2 + (r2 * D + r)) * D2 +
+                              (d2 * D + dd);
+            acc += (abar[i1] + abar[i2]) * x;
+        }
+        Asb[e] += acc;
+    }
+}
+
+__device__ __forceinline__ int c4v_pos(int g, int i) {
+    const int k = g >> 1;
+    return (g & 1) ? ((k - i) & 3) : ((i + k) & 3);
+}
+
+// dA = P(Asb)/m - sign * <Asb, P(A)>/m^2 * P(e_imax), As = P(A)/m (so <Asb,P(A)> = m <Asb,As>)
+__global__ __launch_bounds__(1024) void c4v_backward_kernel(const double* __restrict__ Asb,
+                                                            const double* __restrict__ As,
+                                                            const double* __restrict__ scale,
+                                                            const int* __restrict__ imax, int d,
+                                                            int D, double* dA) {
+    __shared__ double red[1024];
+    const int D4 = D * D * D * D;
+    const int n = d * D4;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) acc += Asb[e] * As[e];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double m = *scale;
+    const int im = *imax;
+    const double sgn = As[im] < 0.0 ? -1.0 : 1.0;
+    const double coef = sgn * red[0] * m / (m * m);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int s = e / D4;
+        int rem = e % D4;
+        int idx[4];
+        for (int q = 3; q >= 0; --q) { idx[q] = rem % D; rem /= D; }
+        double g = 0.0, pe = 0.0;
+        for (int gg = 0; gg < 8; ++gg) {
+            int src[4];
+            for (int q = 0; q < 4; ++q) src[q] = idx[c4v_pos(gg, q)];
+            const int j = s * D4 + ((src[0] * D + src[1]) * D + src[2]) * D + src[3];
+            g += Asb[j];
+            pe += (j == im) ? 1.0 : 0.0;
+        }
+        dA[e] = 0.125 * g / m - coef * 0.125 * pe;
+    }
+}
+
+__global__ void ratio_min_kernel(const double* __restrict__ r, double* acc, int reset) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *acc = reset ? *r : fmin(*acc, *r);
+}
+
+int grid(long long n) {
+    long long b = ceil_div(n, kThreads);
+    if (b < 1) b = 1;
+    if (b > kBlocks) b = kBlocks;
+    return (int)b;
+}
+
+}  // namespace
+
+size_t sym_norm_backward_scratch_bytes() { return sizeof(double) * 2 * kBlocks; }
+
+Status sym_norm_backward(const double* Cn, const double* Tn, const double* Cb, const double* Tb,
+                         const double* norms, int chi, int Dab, double* Cpb, double* Tpb,
+                         double* part, hipStream_t st) {
+    const long long nC = (long long)chi * chi, nT = nC * Dab;
+    const int b = grid(nC + nT);
+    hipLaunchKernelGGL(dots_kernel, dim3(b), dim3(kThreads), 0, st, Cn, Cb, Tn, Tb, nC, nT, part);
+    QRCTM_TRY(launch_check("dots_kernel"));
+    hipLaunchKernelGGL(sym_norm_bwd_kernel, dim3(b), dim3(kThreads), 0, st, part, b, norms, Cn, Cb, Tn,
+                       Tb, chi, Dab, Cpb, Tpb);
+    return launch_check("sym_norm_bwd_kernel");
+}
+
+Status copyltu(const double* M, int n, double* Ms, hipStream_t st) {
+    hipLaunchKernelGGL(copyltu_kernel, dim3(grid((long long)n * n)), dim3(kThreads), 0, st, M, n, Ms);
+    return launch_check("copyltu_kernel");
+}
+
+Status tri_inv_upper(const double* R, int n, double* Ri, hipStream_t st) {
+    hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, R, n, Ri);
+    return launch_check("tri_inv_upper_kernel");
+}
+
+Status double_layer_backward(const double* abar, const double* As, int d, int D, double* Asb,
+                             hipStream_t st) {
+    const long long n = (long long)d * D * D * D * D;
+    hipLaunchKernelGGL(dl_backward_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, abar, As, d,
+                       D, Asb);
+    return launch_check("dl_backward_kernel");
+}
+
+Status c4v_backward(const double* Asb, const double* As, const double* scale, const int* imax,
+                    int d, int D, double* dA, hipStream_t st) {
+    hipLaunchKernelGGL(c4v_backward_kernel, dim3(1), dim3(1024), 0, st, Asb, As, scale, imax, d, D,
+                       dA);
+    return launch_check("c4v_backward_kernel");
+}
+
+Status ratio_min(const double* r, double* acc, bool reset, hipStream_t st) {
+    hipLaunchKernelGGL(ratio_min_kernel, dim3(1), dim3(64), 0, st, r, acc, reset ? 1 : 0);
+    return launch_check("ratio_min_kernel");
+}
+
+}  // namespace qrctm

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/qrctm.h"
+#include "adjoint.h"
 #include "common.h"
 #include "eigh.h"
 #include "energy.h"
@@ -124,6 +125,97 @@ size_t step_splitk_bytes(int chi, int Dab) {
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// Reverse pass of one QR step: the GEMM adjoints, in order.  Each entry is the
+// adjoint of one forward contraction (see qr_step_backward for the sequence).
+// ---------------------------------------------------------------------------
+struct BwPtrs {
+    const double *C, *T, *a, *Q, *R, *Y, *Z, *Tp, *W;
+    double *Cpb, *Tpb, *Wb, *Rb, *Qb, *Zg, *Y2, *abar, *Mm, *Ms, *Rinv, *ctb, *Cb2, *Tb2;
+};
+
+constexpr int kBwGemms = 16;
+
+GemmDesc bw_gemm(int id, const BwPtrs& p, int chi, int Dab) {
+    const long long c = chi, Db = Dab, Db2 = (long long)Dab * Dab;
+    auto G = [](int ta, int tb, long long M, long long N, long long K, const double* A, long long lda,
+                const double* B, long long ldb, double* C, OutMap mp, double alpha, double beta) {
+        GemmDesc g;
+        g.trans_a = ta; g.trans_b = tb;
+        g.M = M; g.N = N; g.K = K;
+        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+        g.C = C; g.map = mp; g.alpha = alpha; g.beta = beta;
+        return g;
+    };
+    auto pl = [](long long M, long long N) { return OutMap::plain(M, N, N); };
+    switch (id) {
+        // a8: C' = sum T'[g,r,a] W[g,r,b]
+        case 0: return G(0, 1, c * Db, c, c, p.W, c, p.Cpb, c, p.Tpb, pl(c * Db, c), 1.0, 1.0);
+        case 1: return G(0, 0, c * Db, c, c, p.Tp, c, p.Cpb, c, p.Wb, pl(c * Db, c), 1.0, 0.0);
+        // a8: W = R Q
+        case 2: return G(0, 1, c, c, Db * c, p.Wb, Db * c, p.Q, Db * c, p.Rb, pl(c, c), 1.0, 0.0);
+        case 3: return G(1, 0, c, Db * c, c, p.R, c, p.Wb, Db * c, p.Qb, pl(c, Db * c), 1.0, 0.0);
+        // a7 3c: T'[(a,r),b] = Z[(a,r),(f,d)] Q[(f,d),b]; Zbar stored as [a][f][r][d]
+        case 4: return G(0, 1, c * Db, c * Db, c, p.Tpb, c, p.Q, c, p.Zg,
+                         OutMap{Db, c * Db2, Db, Db, Db2, 1}, 1.0, 0.0);
+        case 5: return G(1, 0, c * Db, c, c * Db, p.Z, c * Db, p.Tpb, c, p.Qb, pl(c * Db, c), 1.0, 1.0);
+        // a7 3b: Z[(a,f),(r,d)] = Y[(a,f),(u,l)] a[(u,l),(r,d)]; Ybar stored as [u][a][f][l]
+        case 6: return G(0, 1, c * c, Db2, Db2, p.Zg, Db2, p.a, Db2, p.Y2,
+                         OutMap{c, c * Db, Db, Db, c * c * Db, 1}, 1.0, 0.0);
+        case 7: return G(1, 0, Db2, Db2, c * c, p.Y, Db2, p.Zg, Db2, p.abar, pl(Db2, Db2), 1.0, 1.0);
+        // a7 3a: Y[(u,a),(f,l)] = sum_e Q[(e,u),a] T[(f,l),e]
+        case 8: return G(0, 0, Db * c, c, c * Db, p.Y2, c * Db, p.T, c, p.Qb,
+                         OutMap{Db * c, 0, 1, c, 0, Db * c}, 1.0, 1.0);
+        case 9: return G(1, 1, c * Db, c, Db * c, p.Y2, c * Db, p.Q, Db * c, p.Tb2, pl(c * Db, c), 1.0, 0.0);
+        // a6: thin-QR adjoint
+        case 10: return G(0, 1, c, c, c, p.R, c, p.Rb, c, p.Mm, pl(c, c), 1.0, 0.0);
+        case 11: return G(1, 0, c, c, c * Db, p.Qb, c, p.Q, c, p.Mm, pl(c, c), -1.0, 1.0);
+        case 12: return G(0, 0, c * Db, c, c, p.Q, c, p.Ms, c, p.Qb, pl(c * Db, c), 1.0, 1.0);
+        case 13: return G(0, 1, c * Db, c, c, p.Qb, c, p.Rinv, c, p.ctb, pl(c * Db, c), 1.0, 0.0);
+        // a5: ct = C T
+        case 14: return G(0, 1, c, c, Db * c, p.ctb, Db * c, p.T, Db * c, p.Cb2, pl(c, c), 1.0, 0.0);
+        default: return G(1, 0, c, Db * c, c, p.C, c, p.ctb, Db * c, p.Tb2, pl(c, Db * c), 1.0, 1.0);
+    }
+}
+
+struct GradLayout {
+    size_t ckC, ckT, Cb, Tb, Cb2, Tb2, Ctmp, Ttmp, Cpb, Tpb, Wb, Rb, Qb, Zg, Mm, Ms, Rinv, ctb, abar,
+        Asb, part, ratio, splitk;
+    size_t splitk_bytes = 0, total = 0;
+};
+
+GradLayout grad_layout(const Shape& sh, int k) {
+    GradLayout L;
+    if (!sh.quantum) return L;
+    size_t off = 0;
+    auto take = [&](size_t count) {
+        const size_t o = off;
+        off += (count * sizeof(double) + 255) / 256 * 256;
+        return o;
+    };
+    const size_t c = sh.chi, Db = sh.Dab, c2 = c * c;
+    L.ckC = take((size_t)(k + 1) * c2);
+    L.ckT = take((size_t)(k + 1) * c2 * Db);
+    L.Cb = take(c2); L.Tb = take(c2 * Db);
+    L.Cb2 = take(c2); L.Tb2 = take(c2 * Db);
+    L.Ctmp = take(c2); L.Ttmp = take(c2 * Db);
+    L.Cpb = take(c2); L.Tpb = take(c2 * Db); L.Wb = take(c2 * Db); L.Rb = take(c2);
+    L.Qb = take(c2 * Db); L.Zg = take(c2 * Db * Db);
+    L.Mm = take(c2); L.Ms = take(c2); L.Rinv = take(c2); L.ctb = take(c2 * Db);
+    L.abar = take(Db * Db * Db * Db);
+    L.Asb = take((size_t)sh.d * sh.D * sh.D * sh.D * sh.D);
+    L.part = take(sym_norm_backward_scratch_bytes() / sizeof(double) + 1);
+    L.ratio = take(8);
+    BwPtrs p{};
+    size_t sk = 0;
+    for (int cc = 1; cc <= sh.chi; ++cc)
+        for (int id = 0; id < kBwGemms; ++id) sk = std::max(sk, gemm_splitk_bytes(bw_gemm(id, p, cc, sh.Dab)));
+    L.splitk_bytes = sk;
+    L.splitk = take(sk / sizeof(double) + 1);
+    L.total = off;
+    return L;
+}
+
 Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     Plan P;
     size_t off = 0;
@@ -177,7 +269,7 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     P.energy_bytes = sh.quantum ? energy_scratch_bytes(sh.d, sh.D, sh.chi)
                                 : classical_scratch_bytes(sh.Dab, sh.chi);
     take(P.energy, P.energy_bytes);
-    P.grad_bytes = 0;
+    P.grad_bytes = grad_layout(sh, o.k_tracked).total;
     take(P.grad, P.grad_bytes);
     P.total = off;
     return P;
@@ -186,7 +278,7 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
 constexpr int kPhases = 8;  // reduced corner, QR, 3a, 3b, 3c, corner, sym/norm, spectrum
 
 // small-scalar slots (doubles) inside Plan::small
-enum { SL_DELTA = 0, SL_NORMS = 2, SL_RATIO = 4, SL_SCALE = 5, SL_BAD = 8, SL_E = 16 };
+enum { SL_DELTA = 0, SL_NORMS = 2, SL_RATIO = 4, SL_SCALE = 5, SL_BAD = 8, SL_IMAX = 10, SL_E = 16 };
 
 }  // namespace
 
@@ -227,6 +319,7 @@ struct ctm_ctx {
     double* spec_next() const { return ptr(spec_cur ? plan.spec0 : plan.spec1); }
     double* small() const { return ptr(plan.small); }
     int* bad() const { return reinterpret_cast<int*>(ptr(plan.small) + SL_BAD); }
+    int* imax() const { return reinterpret_cast<int*>(ptr(plan.small) + SL_IMAX); }
 };
 
 namespace {
@@ -282,30 +375,45 @@ Status mark(ctm_ctx* c, int i) {
     return hip_status(hipEventRecord(c->ev[i], c->st), "hipEventRecord");
 }
 
-// a5-a10 once; environment moves to the other buffer; spectrum likewise.
-Status qr_step_once(ctm_ctx* c) {
+// a5-a9 from (Cin, Tin) into (Cout, Tout); intermediates stay in the step
+// buffers (Q, R, Y, Z, Tp, W, Cp) and the norms in the small-scalar slots.
+Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Cout, double* Tout,
+                    bool timed) {
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     StepPtrs p = step_ptrs(c);
+    p.C = Cin;
+    p.T = Tin;
+    const bool tm = timed && c->timing;
+    auto mark = [&](int i) -> Status {
+        if (!tm) return Status{};
+        return hip_status(hipEventRecord(c->ev[i], c->st), "hipEventRecord");
+    };
     void* sk = c->ptr<void>(c->plan.splitk);
     const size_t skb = c->plan.splitk_bytes;
-    QRCTM_TRY(mark(c, 0));
+    QRCTM_TRY(mark(0));
     QRCTM_TRY(gemm_f64(g_reduced_corner(p, chi, Dab), sk, skb, c->st));               // a5
-    QRCTM_TRY(mark(c, 1));
+    QRCTM_TRY(mark(1));
     QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
                      c->st, c->small() + SL_RATIO));                                 // a6
-    QRCTM_TRY(mark(c, 2));
+    QRCTM_TRY(mark(2));
     QRCTM_TRY(gemm_f64(g_edge_a(p, p.Q, chi, chi, Dab), sk, skb, c->st));             // a7 3a
-    QRCTM_TRY(mark(c, 3));
+    QRCTM_TRY(mark(3));
     QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chi, Dab), sk, skb, c->st));                  // a7 3b
-    QRCTM_TRY(mark(c, 4));
+    QRCTM_TRY(mark(4));
     QRCTM_TRY(gemm_f64(g_edge_c(p, p.Q, chi, chi, Dab), sk, skb, c->st));             // a7 3c
-    QRCTM_TRY(mark(c, 5));
+    QRCTM_TRY(mark(5));
     QRCTM_TRY(gemm_f64(g_corner_w(p, chi, Dab), sk, skb, c->st));                     // a8
     QRCTM_TRY(gemm_f64(g_corner_c(p, chi, Dab), sk, skb, c->st));
-    QRCTM_TRY(mark(c, 6));
-    QRCTM_TRY(sym_norm(p.Cp, p.Tp, chi, Dab, c->Cn(), c->Tn(), c->ptr(c->plan.normpart),
+    QRCTM_TRY(mark(6));
+    QRCTM_TRY(sym_norm(p.Cp, p.Tp, chi, Dab, Cout, Tout, c->ptr(c->plan.normpart),
                        c->small() + SL_NORMS, c->bad(), c->st));                     // a9
-    QRCTM_TRY(mark(c, 7));
+    return mark(7);
+}
+
+// a5-a10 once; environment moves to the other buffer; spectrum likewise.
+Status qr_step_once(ctm_ctx* c) {
+    const int chi = c->chi_cur;
+    QRCTM_TRY(qr_step_core(c, c->C(), c->T(), c->Cn(), c->Tn(), true));
     QRCTM_TRY(corner_spectrum(c->Cn(), chi, c->ptr(c->plan.S), c->spec(), c->n_spec,
                               c->spec_next(), c->small() + SL_DELTA, c->st));        // a10
     QRCTM_TRY(mark(c, 8));
@@ -350,6 +458,121 @@ Status eigh_step_once(ctm_ctx* c) {
     c->spec_cur ^= 1;
     c->n_spec = chio;
     c->chi_cur = chio;
+    return Status{};
+}
+
+struct GradPtrs {
+    double *ckC, *ckT, *Cb, *Tb, *Cb2, *Tb2, *Ctmp, *Ttmp, *Cpb, *Tpb, *Wb, *Rb, *Qb, *Zg, *Mm, *Ms,
+        *Rinv, *ctb, *abar, *Asb, *part, *ratio;
+    void* splitk;
+    size_t splitk_bytes;
+};
+
+GradPtrs grad_ptrs(ctm_ctx* c) {
+    const GradLayout L = grad_layout(c->sh, c->opts.k_tracked);
+    char* b = c->ptr<char>(c->plan.grad);
+    auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    GradPtrs g;
+    g.ckC = P(L.ckC); g.ckT = P(L.ckT); g.Cb = P(L.Cb); g.Tb = P(L.Tb); g.Cb2 = P(L.Cb2);
+    g.Tb2 = P(L.Tb2); g.Ctmp = P(L.Ctmp); g.Ttmp = P(L.Ttmp); g.Cpb = P(L.Cpb); g.Tpb = P(L.Tpb);
+    g.Wb = P(L.Wb); g.Rb = P(L.Rb); g.Qb = P(L.Qb); g.Zg = P(L.Zg); g.Mm = P(L.Mm); g.Ms = P(L.Ms);
+    g.Rinv = P(L.Rinv); g.ctb = P(L.ctb); g.abar = P(L.abar); g.Asb = P(L.Asb); g.part = P(L.part);
+    g.ratio = P(L.ratio);
+    g.splitk = b + L.splitk;
+    g.splitk_bytes = L.splitk_bytes;
+    return g;
+}
+
+// Reverse of one QR step (a5-a9) from (Ci, Ti), given the cotangents (Cb, Tb)
+// of its normalised outputs; writes the cotangents of (Ci, Ti) into (Cb2, Tb2)
+// and accumulates that of the double layer into abar.  The step's forward
+// intermediates are recomputed first (only (C_i, T_i) are stored).
+Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, const double* Ci, const double* Ti) {
+    const int chi = c->chi_cur, Dab = c->sh.Dab;
+    QRCTM_TRY(qr_step_core(c, Ci, Ti, g.Ctmp, g.Ttmp, false));
+    StepPtrs sp = step_ptrs(c);
+    BwPtrs p;
+    p.C = Ci; p.T = Ti; p.a = sp.a; p.Q = sp.Q; p.R = sp.R; p.Y = sp.Y; p.Z = sp.Z; p.Tp = sp.Tp;
+    p.W = sp.W;
+    p.Cpb = g.Cpb; p.Tpb = g.Tpb; p.Wb = g.Wb; p.Rb = g.Rb; p.Qb = g.Qb; p.Zg = g.Zg;
+    p.Y2 = sp.Z;  // Z is dead once Zbar and Qbar += Z^T Tpbar are formed
+    p.abar = g.abar; p.Mm = g.Mm; p.Ms = g.Ms; p.Rinv = g.Rinv; p.ctb = g.ctb;
+    p.Cb2 = g.Cb2; p.Tb2 = g.Tb2;
+    auto run = [&](int id) { return gemm_f64(bw_gemm(id, p, chi, Dab), g.splitk, g.splitk_bytes, c->st); };
+    // a9: symmetrise / normalise
+    QRCTM_TRY(sym_norm_backward(g.Ctmp, g.Ttmp, g.Cb, g.Tb, c->small() + SL_NORMS, chi, Dab, g.Cpb,
+                                g.Tpb, g.part, c->st));
+    for (int id = 0; id <= 9; ++id) QRCTM_TRY(run(id));   // a8, a7 (3c, 3b, 3a)
+    QRCTM_TRY(run(10));                                    // a6: M = R Rbar^T - Qbar^T Q
+    QRCTM_TRY(run(11));
+    QRCTM_TRY(copyltu(g.Mm, chi, g.Ms, c->st));
+    QRCTM_TRY(run(12));                                    // Qbar + Q copyltu(M)
+    QRCTM_TRY(tri_inv_upper(sp.R, chi, g.Rinv, c->st));
+    QRCTM_TRY(run(13));                                    // ... R^{-T}
+    QRCTM_TRY(run(14));                                    // a5
+    QRCTM_TRY(run(15));
+    return Status{};
+}
+
+__global__ void zero_kernel(double* x, long long n) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        x[e] = 0.0;
+}
+
+Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA) {
+    const int k = c->opts.k_tracked;
+    const int chi = c->chi_cur, Dab = c->sh.Dab;
+    const size_t nC = (size_t)chi * chi, nT = nC * Dab;
+    const GradPtrs g = grad_ptrs(c);
+    // checkpoints C_0..C_k (compact, chi_cur-sized)
+    QRCTM_HIP(hipMemcpyAsync(g.ckC, c->C(), nC * 8, hipMemcpyDeviceToDevice, c->st));
+    QRCTM_HIP(hipMemcpyAsync(g.ckT, c->T(), nT * 8, hipMemcpyDeviceToDevice, c->st));
+    for (int i = 0; i < k; ++i) {
+        QRCTM_TRY(qr_step_core(c, g.ckC + i * nC, g.ckT + i * nT, g.ckC + (i + 1) * nC,
+                               g.ckT + (i + 1) * nT, false));
+        QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, i == 0, c->st));
+    }
+    EnergyArgs ea{};
+    ea.d = c->sh.d; ea.D = c->sh.D; ea.chi = chi;
+    ea.C = g.ckC + (size_t)k * nC; ea.T = g.ckT + (size_t)k * nT; ea.As = c->ptr(c->plan.As);
+    ea.ws = c->ptr<char>(c->plan.energy); ea.ws_bytes = c->plan.energy_bytes;
+    ea.splitk = nullptr; ea.splitk_bytes = 0;
+    QRCTM_TRY(energy_grad_eval(ea, h_nn, E, g.Cb, g.Tb, g.Asb, c->st));
+    const long long na = (long long)Dab * Dab * Dab * Dab;
+    hipLaunchKernelGGL(zero_kernel, dim3((int)std::min<long long>(ceil_div(na, 256), 4096)), dim3(256),
+                       0, c->st, g.abar, na);
+    QRCTM_TRY(launch_check("zero_kernel"));
+    double* Cb = g.Cb;
+    double* Tb = g.Tb;
+    double* Cb2 = g.Cb2;
+    double* Tb2 = g.Tb2;
+    for (int i = k - 1; i >= 0; --i) {
+        GradPtrs gi = g;
+        gi.Cb = Cb; gi.Tb = Tb; gi.Cb2 = Cb2; gi.Tb2 = Tb2;
+        QRCTM_TRY(qr_step_backward(c, gi, g.ckC + i * nC, g.ckT + i * nT));
+        std::swap(Cb, Cb2);
+        std::swap(Tb, Tb2);
+    }
+    QRCTM_TRY(double_layer_backward(g.abar, c->ptr(c->plan.As), c->sh.d, c->sh.D, g.Asb, c->st));
+    QRCTM_TRY(c4v_backward(g.Asb, c->ptr(c->plan.As), c->small() + SL_SCALE, c->imax(), c->sh.d,
+                           c->sh.D, dA, c->st));
+    double ratio = 1.0;
+    if (k > 0) QRCTM_HIP(hipMemcpyAsync(&ratio, g.ratio, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    QRCTM_TRY(sync(c->st));
+    if (k > 0 && !(ratio >= c->opts.qr_sing_tol)) {
+        Status s;
+        s.code = CTM_ESINGULAR;
+        s.msg = "reduced corner numerically rank deficient in a tracked step (min|R_ii|/max|R_ii| = " +
+                std::to_string(ratio) + "); the QR adjoint needs R^{-1}";
+        return s;
+    }
+    if (!std::isfinite(*E)) {
+        Status s;
+        s.code = CTM_ENONFINITE;
+        s.msg = "non-finite energy";
+        return s;
+    }
     return Status{};
 }
 
@@ -485,7 +708,8 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
     if (rc != 0) return rc;
     rc = guarded(c, [&]() -> Status {
         QRCTM_TRY(clear_bad(c));
-        QRCTM_TRY(c4v_prepare(A, d, D, c->ptr(c->plan.As), c->small() + SL_SCALE, c->bad(), c->st));
+        QRCTM_TRY(c4v_prepare(A, d, D, c->ptr(c->plan.As), c->small() + SL_SCALE, c->bad(),
+                              c->imax(), c->st));
         QRCTM_TRY(double_layer(c->ptr(c->plan.As), d, D, c->ptr(c->plan.a), c->st));
         QRCTM_TRY(eye_vec(c->ptr(c->plan.bvec), D, c->st));
         bool bad = false;
@@ -536,7 +760,7 @@ int ctm_set_tensor(ctm_ctx* c, const double* A) {
     return guarded(c, [&]() -> Status {
         QRCTM_TRY(clear_bad(c));
         QRCTM_TRY(c4v_prepare(A, c->sh.d, c->sh.D, c->ptr(c->plan.As), c->small() + SL_SCALE,
-                              c->bad(), c->st));
+                              c->bad(), c->imax(), c->st));
         QRCTM_TRY(double_layer(c->ptr(c->plan.As), c->sh.d, c->sh.D, c->ptr(c->plan.a), c->st));
         bool bad = false;
         QRCTM_TRY(read_bad(c, &bad));
@@ -652,9 +876,11 @@ int ctm_energy(ctm_ctx* c, const double* h_nn, const double* h_nnn, double J2, d
 
 int ctm_energy_grad(ctm_ctx* c, const double* h_nn, const double* h_nnn, double J2, double* E,
                     double* dA) {
-    (void)h_nn; (void)h_nnn; (void)J2; (void)E; (void)dA;
-    if (!c) return fail(c, CTM_EINVAL, "NULL context");
-    return fail(c, CTM_ESTATE, "ctm_energy_grad is not available in this build");
+    if (!c || !h_nn || !E || !dA) return fail(c, CTM_EINVAL, "NULL argument");
+    if (!c->sh.quantum) return fail(c, CTM_ESTATE, "gradient needs a site tensor (ctm_init)");
+    if (h_nnn != nullptr && J2 != 0.0)
+        return fail(c, CTM_EINVAL, "ctm_energy_grad supports nearest-neighbour models (h_nnn = NULL)");
+    return guarded(c, [&]() -> Status { return energy_grad_impl(c, h_nn, E, dA); });
 }
 
 int ctm_lnz_per_site(ctm_ctx* c, double* lnk) {

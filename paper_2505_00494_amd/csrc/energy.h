@@ -17,6 +17,11 @@ size_t energy_scratch_bytes(int d, int D, int chi);
 Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
                    double* E, hipStream_t st);
 
+// E (host) and its cotangents with respect to C, T (device, chi x chi and
+// chi x Dab x chi, overwritten) and As (device, d D^4, overwritten).
+Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, double* E, double* Cb,
+                        double* Tb, double* Asb, hipStream_t st);
+
 struct ClassicalArgs {
     int Dab, chi;
     const double *C, *T, *a;  // a in the internal layout a[U][L][R][Dn]

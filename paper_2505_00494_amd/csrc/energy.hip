@@ -126,7 +126,9 @@ __global__ void bond_energy_kernel(const double* __restrict__ rho, const double*
 }
 
 struct ELayout {
-    size_t E1, F, X, Yb, Left, Lp, Ak, rho, h, scal, splitk, total;
+    size_t E1, F, E2, Yb, E3, E4, E4p, Left, Lp, Ak, rho, h, scal;
+    size_t Lpb, Leftb, E1b, Fb, Akb, rhob;
+    size_t splitk, total;
     size_t splitk_bytes;
 };
 
@@ -138,21 +140,46 @@ ELayout e_layout(int d, int D, int chi) {
         off += (count * sizeof(double) + 255) / 256 * 256;
         return o;
     };
-    const size_t c = chi, D2 = (size_t)D * D, D4 = D2 * D2;
+    const size_t c = chi, D2 = (size_t)D * D, D4 = D2 * D2, dd = d;
     L.E1 = take(c * D2 * c);
     L.F = take(c * D2 * c);
-    L.X = take((size_t)d * d * c * c * D4);
-    L.Yb = take((size_t)d * d * c * c * D4);
-    L.Left = take(c * (size_t)d * d * D2 * c);
-    L.Lp = take(c * (size_t)d * d * D2 * c);
-    L.Ak = take((size_t)d * D4);
-    L.rho = take((size_t)d * d * d * d);
-    L.h = take((size_t)d * d * d * d);
+    L.E2 = take(c * c * D4);
+    L.Yb = take(c * c * D4);
+    L.E3 = take(dd * c * c * D4);
+    L.E4 = take(dd * dd * c * c * D4);
+    L.E4p = take(dd * dd * c * c * D4);
+    L.Left = take(c * dd * dd * D2 * c);
+    L.Lp = take(c * dd * dd * D2 * c);
+    L.Ak = take(dd * D4);
+    L.rho = take(dd * dd * dd * dd);
+    L.h = take(dd * dd * dd * dd);
     L.scal = take(16);
-    // split-K partials of the rho GEMM (M = N = d^2, K = chi^2 D^2)
-    GemmDesc g;
-    g.M = (long long)d * d; g.N = g.M; g.K = (long long)c * c * D2;
-    L.splitk_bytes = gemm_splitk_bytes(g) + sizeof(double) * kRedBlocks;
+    L.Lpb = take(c * dd * dd * D2 * c);
+    L.Leftb = take(c * dd * dd * D2 * c);
+    L.E1b = take(c * D2 * c);
+    L.Fb = take(c * D2 * c);
+    L.Akb = take(dd * D4);
+    L.rhob = take(dd * dd * dd * dd);
+    // split-K partials: the largest of the reductions over chi^2 D^2 or chi^2 d D^2
+    size_t sk = 0;
+    {
+        GemmDesc g;
+        g.M = (long long)dd * dd; g.N = g.M; g.K = (long long)c * c * D2;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+        g.M = (long long)D2; g.N = (long long)dd * D2; g.K = (long long)c * c * dd * D2;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+        g.K = (long long)c * c * D2;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+        g.M = (long long)c * D2; g.N = (long long)c; g.K = (long long)c * dd * dd * D2;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+        g.M = (long long)c; g.N = (long long)c; g.K = (long long)c * D2;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+        g.M = (long long)c; g.N = (long long)c * D2; g.K = (long long)c * D2;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+        g.M = (long long)dd * dd; g.N = (long long)c * D2 * c; g.K = (long long)dd * dd;
+        sk = std::max(sk, gemm_splitk_bytes(g));
+    }
+    L.splitk_bytes = sk + 256;
     L.splitk = take(L.splitk_bytes / sizeof(double) + 1);
     L.total = off;
     return L;
@@ -289,6 +316,103 @@ Status classical_expect(const ClassicalArgs& ca, const double* imp, double* v, h
     return classical_parts(ca, v, nullptr, nullptr, imp, st);
 }
 
+namespace {
+
+GemmDesc gd(int ta, int tb, long long M, long long N, long long K, const double* A, long long lda,
+            const double* B, long long ldb, double* C, OutMap mp, double beta = 0.0) {
+    GemmDesc g;
+    g.trans_a = ta; g.trans_b = tb;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+    g.C = C; g.map = mp; g.beta = beta;
+    return g;
+}
+
+OutMap plain(long long M, long long N) { return OutMap::plain(M, N, N); }
+
+// rho[(s1 s1'),(s2 s2')] of the nearest-neighbour pair; keeps every
+// intermediate in the tape for the reverse pass.
+Status nn_rho_forward(const EnergyArgs& ea, const ELayout& L, hipStream_t st) {
+    char* b = ea.ws;
+    auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    const int d = ea.d, D = ea.D, chi = ea.chi;
+    const long long c = chi, DD = D, D2 = (long long)D * D, dd = d;
+    void* sk = b + L.splitk;
+    const size_t skb = L.splitk_bytes;
+    QRCTM_TRY(left_column(ea.C, ea.T, chi, (int)D2, P(L.F), P(L.E1), st));
+    // E2[(U,w),(L,t)] = sum_q T[q,U,w] E1[q,L,t]   ([u][u'][w][l][l'][t])
+    QRCTM_TRY(gemm_f64(gd(1, 0, D2 * c, D2 * c, c, ea.T, D2 * c, P(L.E1), D2 * c, P(L.E2),
+                          plain(D2 * c, D2 * c)), sk, skb, st));
+    {   // Yb[w][t][u'][l'][u][l]
+        const long long dims[6] = {DD, DD, c, DD, DD, c};
+        const int axes[6] = {2, 5, 1, 4, 0, 3};
+        QRCTM_TRY(permute(P(L.E2), P(L.Yb), 6, dims, axes, st));
+    }
+    {   // Ak[u][l][s][d][r] from As[s][u][l][d][r]
+        const long long dims[5] = {dd, DD, DD, DD, DD};
+        const int axes[5] = {1, 2, 0, 3, 4};
+        QRCTM_TRY(permute(ea.As, P(L.Ak), 5, dims, axes, st));
+    }
+    // ket: rows (w,t,u',l'), K (u,l), cols (s,d,r) -> E3 [w][t][s][d][r][u'][l']
+    QRCTM_TRY(gemm_f64(gd(0, 0, c * c * D2, dd * D2, D2, P(L.Yb), D2, P(L.Ak), dd * D2, P(L.E3),
+                          OutMap{D2, dd * D2 * D2, 1, dd * D2, 0, D2}), sk, skb, st));
+    // bra: rows (w,t,s,d,r), K (u',l'), cols (s',d',r') -> E4
+    QRCTM_TRY(gemm_f64(gd(0, 0, c * c * dd * D2, dd * D2, D2, P(L.E3), D2, P(L.Ak), dd * D2,
+                          P(L.E4), plain(c * c * dd * D2, dd * D2)), sk, skb, st));
+    {   // E4p [w][s][s'][r][r'][t][d][d']
+        const long long dims[8] = {c, c, dd, DD, DD, dd, DD, DD};
+        const int axes[8] = {0, 2, 5, 4, 7, 1, 3, 6};
+        QRCTM_TRY(permute(P(L.E4), P(L.E4p), 8, dims, axes, st));
+    }
+    // Left[(w,s,s',R), v] = sum_{(t,Dn)} E4p[(w,s,s',R),(t,Dn)] T[(t,Dn), v]
+    QRCTM_TRY(gemm_f64(gd(0, 0, c * dd * dd * D2, c, c * D2, P(L.E4p), c * D2, ea.T, c, P(L.Left),
+                          plain(c * dd * dd * D2, c)), sk, skb, st));
+    {   // Lp[(s,s'), (w,R,v)]
+        const long long dims[5] = {c, dd, dd, D2, c};
+        const int axes[5] = {1, 2, 0, 3, 4};
+        QRCTM_TRY(permute(P(L.Left), P(L.Lp), 5, dims, axes, st));
+    }
+    // rho = Lp Lp^T
+    const long long K = c * D2 * c;
+    QRCTM_TRY(gemm_f64(gd(0, 1, dd * dd, dd * dd, K, P(L.Lp), K, P(L.Lp), K, P(L.rho),
+                          plain(dd * dd, dd * dd)), sk, skb, st));
+    return Status{};
+}
+
+// rhob = dE/drho + (dE/drho)^T for E = 2 Tr(rm h)/Tr(rm) (rho layout [(s1 s1'),(s2 s2')])
+__global__ void rho_bar_kernel(const double* __restrict__ rho, const double* __restrict__ h, int d,
+                               double* rhob) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int d2 = d * d;
+    double num = 0.0, den = 0.0;
+    for (int s1 = 0; s1 < d; ++s1)
+        for (int t1 = 0; t1 < d; ++t1)
+            for (int s2 = 0; s2 < d; ++s2)
+                for (int t2 = 0; t2 < d; ++t2) {
+                    const double r = rho[(size_t)(s1 * d + t1) * d2 + (s2 * d + t2)];
+                    num += r * h[(size_t)(t1 * d + t2) * d2 + (s1 * d + s2)];
+                    if (s1 == t1 && s2 == t2) den += r;
+                }
+    const double e = 2.0 * num / den;
+    for (int s1 = 0; s1 < d; ++s1)
+        for (int t1 = 0; t1 < d; ++t1)
+            for (int s2 = 0; s2 < d; ++s2)
+                for (int t2 = 0; t2 < d; ++t2) {
+                    const double g = (2.0 / den) * (h[(size_t)(t1 * d + t2) * d2 + (s1 * d + s2)] -
+                                                    ((s1 == t1 && s2 == t2) ? 0.5 * e : 0.0));
+                    rhob[(size_t)(s1 * d + t1) * d2 + (s2 * d + t2)] = g;
+                }
+    // symmetrise: rho = Lp Lp^T uses Lp on both sides
+    for (int i = 0; i < d2; ++i)
+        for (int j = i; j < d2; ++j) {
+            const double v = rhob[(size_t)i * d2 + j] + rhob[(size_t)j * d2 + i];
+            rhob[(size_t)i * d2 + j] = v;
+            rhob[(size_t)j * d2 + i] = v;
+        }
+}
+
+}  // namespace
+
 Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
                    double* E, hipStream_t st) {
     Status s;
@@ -297,8 +421,31 @@ Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn
         s.msg = "energy: the next-nearest-neighbour term is not available in this build";
         return s;
     }
+    const int d = ea.d;
+    const ELayout L = e_layout(d, ea.D, ea.chi);
+    if (ea.ws_bytes < L.total) {
+        s.code = -2;
+        s.msg = "energy: scratch too small";
+        return s;
+    }
+    char* b = ea.ws;
+    auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    QRCTM_TRY(nn_rho_forward(ea, L, st));
+    QRCTM_HIP(hipMemcpyAsync(P(L.h), h_nn, sizeof(double) * d * d * d * d, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, 2.0,
+                       P(L.scal), 0);
+    QRCTM_TRY(launch_check("bond_energy_kernel"));
+    double hv = NAN;
+    QRCTM_HIP(hipMemcpyAsync(&hv, P(L.scal), sizeof(double), hipMemcpyDeviceToHost, st));
+    QRCTM_HIP(hipStreamSynchronize(st));
+    *E = hv;
+    return s;
+}
+
+Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, double* E, double* Cb,
+                        double* Tb, double* Asb, hipStream_t st) {
+    Status s;
     const int d = ea.d, D = ea.D, chi = ea.chi;
-    const int Dab = D * D;
     const ELayout L = e_layout(d, D, chi);
     if (ea.ws_bytes < L.total) {
         s.code = -2;
@@ -307,87 +454,74 @@ Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn
     }
     char* b = ea.ws;
     auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
-    double *E1 = P(L.E1), *F = P(L.F), *X = P(L.X), *Yb = P(L.Yb), *Left = P(L.Left), *Lp = P(L.Lp);
-    double *Ak = P(L.Ak), *rho = P(L.rho), *hd = P(L.h), *sc = P(L.scal);
+    const long long c = chi, DD = D, D2 = (long long)D * D, dd = d;
     void* sk = b + L.splitk;
-    const long long c = chi, DD = D, D2 = Dab, dd = d;
-
-    QRCTM_TRY(left_column(ea.C, ea.T, chi, Dab, F, E1, st));
-    // E2[(U,w),(L,t)] = sum_q T[q,U,w] E1[q,L,t]  -> X, layout [u][u'][w][l][l'][t]
-    {
-        GemmDesc g;
-        g.trans_a = 1;
-        g.M = D2 * c; g.N = D2 * c; g.K = c;
-        g.A = ea.T; g.lda = D2 * c; g.B = E1; g.ldb = D2 * c;
-        g.C = X; g.map = OutMap::plain(g.M, g.N, g.N);
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    // -> Yb[w][t][u'][l'][u][l]
-    {
-        const long long dims[6] = {DD, DD, c, DD, DD, c};
-        const int axes[6] = {2, 5, 1, 4, 0, 3};
-        QRCTM_TRY(permute(X, Yb, 6, dims, axes, st));
-    }
-    // Ak[u][l][s][d][r] from As[s][u][l][d][r]
-    {
-        const long long dims[5] = {dd, DD, DD, DD, DD};
-        const int axes[5] = {1, 2, 0, 3, 4};
-        QRCTM_TRY(permute(ea.As, Ak, 5, dims, axes, st));
-    }
-    // ket: rows (w,t,u',l'), K (u,l), cols (s,d,r) -> X as [w][t][s][d][r][u'][l']
-    {
-        GemmDesc g;
-        g.M = c * c * D2; g.N = dd * D2; g.K = D2;
-        g.A = Yb; g.lda = D2; g.B = Ak; g.ldb = dd * D2;
-        g.C = X;
-        g.map = OutMap{D2, dd * D2 * D2, 1, dd * D2, 0, D2};
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    // bra: rows (w,t,s,d,r), K (u',l'), cols (s',d',r') -> Yb [w][t][s][d][r][s'][d'][r']
-    {
-        GemmDesc g;
-        g.M = c * c * dd * D2; g.N = dd * D2; g.K = D2;
-        g.A = X; g.lda = D2; g.B = Ak; g.ldb = dd * D2;
-        g.C = Yb; g.map = OutMap::plain(g.M, g.N, g.N);
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    // -> X [w][s][s'][r][r'][t][d][d']
-    {
-        const long long dims[8] = {c, c, dd, DD, DD, dd, DD, DD};
-        const int axes[8] = {0, 2, 5, 4, 7, 1, 3, 6};
-        QRCTM_TRY(permute(Yb, X, 8, dims, axes, st));
-    }
-    // Left[(w,s,s',R), v] = sum_{(t,Dn)} X[(w,s,s',R),(t,Dn)] T[(t,Dn), v]
-    {
-        GemmDesc g;
-        g.M = c * dd * dd * D2; g.N = c; g.K = c * D2;
-        g.A = X; g.lda = c * D2; g.B = ea.T; g.ldb = c;
-        g.C = Left; g.map = OutMap::plain(g.M, g.N, g.N);
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    // Lp[(s,s'), (w,R,v)]
-    {
-        const long long dims[5] = {c, dd, dd, D2, c};
-        const int axes[5] = {1, 2, 0, 3, 4};
-        QRCTM_TRY(permute(Left, Lp, 5, dims, axes, st));
-    }
-    // rho = Lp Lp^T
-    {
-        GemmDesc g;
-        g.trans_b = 1;
-        g.M = dd * dd; g.N = dd * dd; g.K = c * D2 * c;
-        g.A = Lp; g.lda = g.K; g.B = Lp; g.ldb = g.K;
-        g.C = rho; g.map = OutMap::plain(g.M, g.N, g.N);
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    QRCTM_HIP(hipMemcpyAsync(hd, h_nn, sizeof(double) * d * d * d * d, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, rho, hd, d, 2.0, sc, 0);
+    const size_t skb = L.splitk_bytes;
+    QRCTM_TRY(nn_rho_forward(ea, L, st));
+    QRCTM_HIP(hipMemcpyAsync(P(L.h), h_nn, sizeof(double) * d * d * d * d, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, 2.0,
+                       P(L.scal), 0);
     QRCTM_TRY(launch_check("bond_energy_kernel"));
-    double h = NAN;
-    QRCTM_HIP(hipMemcpyAsync(&h, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(rho_bar_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, P(L.rhob));
+    QRCTM_TRY(launch_check("rho_bar_kernel"));
+    const long long K = c * D2 * c;
+    // Lpb = rhob_sym Lp
+    QRCTM_TRY(gemm_f64(gd(0, 0, dd * dd, K, dd * dd, P(L.rhob), dd * dd, P(L.Lp), K, P(L.Lpb),
+                          plain(dd * dd, K)), sk, skb, st));
+    {   // Leftb[w][s][s'][R][v] from Lpb[(s,s'),(w,R,v)]
+        const long long dims[5] = {dd, dd, c, D2, c};
+        const int axes[5] = {2, 0, 1, 3, 4};
+        QRCTM_TRY(permute(P(L.Lpb), P(L.Leftb), 5, dims, axes, st));
+    }
+    const long long Mleft = c * dd * dd * D2;
+    // E4pb = Leftb T^T  (into E4);  Tb = E4p^T Leftb
+    QRCTM_TRY(gemm_f64(gd(0, 1, Mleft, c * D2, c, P(L.Leftb), c, ea.T, c, P(L.E4),
+                          plain(Mleft, c * D2)), sk, skb, st));
+    QRCTM_TRY(gemm_f64(gd(1, 0, c * D2, c, Mleft, P(L.E4p), c * D2, P(L.Leftb), c, Tb,
+                          plain(c * D2, c)), sk, skb, st));
+    {   // E4b [w][t][s][d][r][s'][d'][r'] from E4pb [w][s][s'][r][r'][t][d][d']  (into E4p)
+        const long long dims[8] = {c, dd, dd, DD, DD, c, DD, DD};
+        const int axes[8] = {0, 5, 1, 6, 3, 2, 7, 4};
+        QRCTM_TRY(permute(P(L.E4), P(L.E4p), 8, dims, axes, st));
+    }
+    // bra reverse: E3b (ket-GEMM layout [(w,t,u',l'),(s,d,r)]) into E4; Akb = E3^T E4b
+    QRCTM_TRY(gemm_f64(gd(0, 1, c * c * dd * D2, D2, dd * D2, P(L.E4p), dd * D2, P(L.Ak), dd * D2,
+                          P(L.E4), OutMap{dd * D2, D2 * dd * D2, 1, D2, 0, dd * D2}), sk, skb, st));
+    QRCTM_TRY(gemm_f64(gd(1, 0, D2, dd * D2, c * c * dd * D2, P(L.E3), D2, P(L.E4p), dd * D2,
+                          P(L.Akb), plain(D2, dd * D2)), sk, skb, st));
+    // ket reverse: Ybb = E3b Ak^T (into E2);  Akb += Yb^T E3b
+    QRCTM_TRY(gemm_f64(gd(0, 1, c * c * D2, D2, dd * D2, P(L.E4), dd * D2, P(L.Ak), dd * D2,
+                          P(L.E2), plain(c * c * D2, D2)), sk, skb, st));
+    QRCTM_TRY(gemm_f64(gd(1, 0, D2, dd * D2, c * c * D2, P(L.Yb), D2, P(L.E4), dd * D2, P(L.Akb),
+                          plain(D2, dd * D2), 1.0), sk, skb, st));
+    {   // E2b [u][u'][w][l][l'][t] from Ybb [w][t][u'][l'][u][l]  (into E3)
+        const long long dims[6] = {c, c, DD, DD, DD, DD};
+        const int axes[6] = {4, 2, 0, 5, 3, 1};
+        QRCTM_TRY(permute(P(L.E2), P(L.E3), 6, dims, axes, st));
+    }
+    // E2 = T^T-contract E1: Tb += E1 E2b^T ; E1b = T E2b
+    QRCTM_TRY(gemm_f64(gd(0, 1, c, D2 * c, D2 * c, P(L.E1), D2 * c, P(L.E3), D2 * c, Tb,
+                          plain(c, D2 * c), 1.0), sk, skb, st));
+    QRCTM_TRY(gemm_f64(gd(0, 0, c, D2 * c, D2 * c, ea.T, D2 * c, P(L.E3), D2 * c, P(L.E1b),
+                          plain(c, D2 * c)), sk, skb, st));
+    // E1 = F C: Fb = E1b C^T ; Cb = F^T E1b
+    QRCTM_TRY(gemm_f64(gd(0, 1, c * D2, c, c, P(L.E1b), c, ea.C, c, P(L.Fb), plain(c * D2, c)), sk,
+                       skb, st));
+    QRCTM_TRY(gemm_f64(gd(1, 0, c, c, c * D2, P(L.F), c, P(L.E1b), c, Cb, plain(c, c)), sk, skb, st));
+    // F = C T: Cb += Fb T^T ; Tb += C^T Fb
+    QRCTM_TRY(gemm_f64(gd(0, 1, c, c, D2 * c, P(L.Fb), D2 * c, ea.T, D2 * c, Cb, plain(c, c), 1.0),
+                       sk, skb, st));
+    QRCTM_TRY(gemm_f64(gd(1, 0, c, D2 * c, c, ea.C, c, P(L.Fb), D2 * c, Tb, plain(c, D2 * c), 1.0),
+                       sk, skb, st));
+    {   // Asb[s][u][l][d][r] from Akb[u][l][s][d][r]
+        const long long dims[5] = {DD, DD, dd, DD, DD};
+        const int axes[5] = {2, 0, 1, 3, 4};
+        QRCTM_TRY(permute(P(L.Akb), Asb, 5, dims, axes, st));
+    }
+    double hv = NAN;
+    QRCTM_HIP(hipMemcpyAsync(&hv, P(L.scal), sizeof(double), hipMemcpyDeviceToHost, st));
     QRCTM_HIP(hipStreamSynchronize(st));
-    *E = h;
-    (void)J2;
+    *E = hv;
     return s;
 }
 

@@ -141,7 +141,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
         buf ^= 1;
     }
 
-    // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
+    // epilogue: with A fed as A[lane%16][lane/16] and B as B[lane/16][lane%16],
+    // accumulator element r of a lane is D[4*r + lane/16][lane%16] (measured
+    // lane layout of v_mfma_f64_16x16x4_f64 on gfx950)
     const long long MN = p.M * p.N;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -151,7 +153,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
             if (n >= p.N) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const long long m = m0 + wm * WM + i * 16 + 4 * lk + r;
+                const long long m = m0 + wm * WM + i * 16 + 4 * r + lk;
                 if (m >= p.M) continue;
                 const double v = acc[i][j][r];
                 if (p.partial) {

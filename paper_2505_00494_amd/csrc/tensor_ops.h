@@ -4,10 +4,11 @@
 
 namespace qrctm {
 
-// As = P(A) / max|P(A)|; scale_out (device, may be null) receives max|P(A)|;
-// bad (device int) is or-ed with 1 on a non-finite or all-zero tensor.
+// As = P(A) / max|P(A)|; scale_out (device, may be null) receives max|P(A)| and
+// imax_out (device, may be null) the first flat index attaining it; bad (device
+// int) is or-ed with 1 on a non-finite or all-zero tensor.
 Status c4v_prepare(const double* A, int d, int D, double* As, double* scale_out, int* bad,
-                   hipStream_t st);
+                   int* imax_out, hipStream_t st);
 // a_int[U][L][R][Dn] = sum_s As[s,u,l,d,r] As[s,u',l',d',r'], bond D^2.
 Status double_layer(const double* As, int d, int D, double* a_int, hipStream_t st);
 // user layout a[U][L][Dn][R] -> a_int[U][L][R][Dn]

@@ -18,11 +18,13 @@ __device__ __forceinline__ int c4v_pos(int g, int i) {
 
 __global__ __launch_bounds__(1024) void c4v_prepare_kernel(const double* __restrict__ A, int d,
                                                            int D, double* As, double* scale_out,
-                                                           int* bad) {
+                                                           int* bad, int* imax_out) {
     __shared__ double red[1024];
+    __shared__ int redi[1024];
     const int n = d * D * D * D * D;
     const int D4 = D * D * D * D;
-    double mx = 0.0;
+    double mx = -1.0;
+    int mi = 0;
     int nonfinite = 0;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int s = e / D4;
@@ -38,15 +40,24 @@ __global__ __launch_bounds__(1024) void c4v_prepare_kernel(const double* __restr
         acc *= 0.125;
         As[e] = acc;
         if (!isfinite(acc)) nonfinite = 1;
-        mx = fmax(mx, fabs(acc));
+        if (fabs(acc) > mx) { mx = fabs(acc); mi = e; }  // first maximiser of this thread
     }
     red[threadIdx.x] = mx;
+    redi[threadIdx.x] = mi;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        if (threadIdx.x < w) {
+            const double o = red[threadIdx.x + w];
+            const int oi = redi[threadIdx.x + w];
+            if (o > red[threadIdx.x] || (o == red[threadIdx.x] && oi < redi[threadIdx.x])) {
+                red[threadIdx.x] = o;
+                redi[threadIdx.x] = oi;
+            }
+        }
         __syncthreads();
     }
     const double m = red[0];
+    if (threadIdx.x == 0 && imax_out) *imax_out = redi[0];
     if (nonfinite) atomicOr(bad, 1);
     if (m == 0.0 || !isfinite(m)) {
         if (threadIdx.x == 0) atomicOr(bad, 1);
@@ -204,8 +215,9 @@ int grid_for(long long n, int threads, int cap) {
 }  // namespace
 
 Status c4v_prepare(const double* A, int d, int D, double* As, double* scale_out, int* bad,
-                   hipStream_t st) {
-    hipLaunchKernelGGL(c4v_prepare_kernel, dim3(1), dim3(1024), 0, st, A, d, D, As, scale_out, bad);
+                   int* imax_out, hipStream_t st) {
+    hipLaunchKernelGGL(c4v_prepare_kernel, dim3(1), dim3(1024), 0, st, A, d, D, As, scale_out, bad,
+                       imax_out);
     return launch_check("c4v_prepare_kernel");
 }
 
