@@ -16,8 +16,8 @@ Readings of points the paper leaves open (each also listed in the design notes):
   * the QR is made unique by forcing diag(R) >= 0 (zero counts as +);
   * C and T are symmetrised and divided by their Frobenius norm after every step;
   * eigenvectors of the standard step are ordered by |lambda| descending (ties
-    keep LAPACK's ascending order) and sign-fixed so that their largest-|.|
-    component is positive;
+    keep LAPACK's ascending order) and sign-fixed so that their first component
+    with |v_i| >= max|v|/2 is positive;
   * convergence: s = sort(|eig C|) descending / sum, delta = ||s_k - s_{k-1}||_2
     (shorter spectra are padded with zeros).
 """
@@ -200,7 +200,12 @@ def enlarged_corner(C, T, a):
 
 
 def _sign_fix_columns(V: np.ndarray) -> np.ndarray:
-    idx = np.argmax(np.abs(V), axis=0)
+    """Sign of each eigenvector: its first component with |v_i| >= max|v| / 2 is
+    made positive (a rule that does not depend on which of several components
+    of equal magnitude is the largest)."""
+    A = np.abs(V)
+    big = A >= 0.5 * A.max(axis=0, keepdims=True)
+    idx = np.argmax(big, axis=0)
     s = np.sign(V[idx, np.arange(V.shape[1])])
     s[s == 0] = 1.0
     return V * s[None, :]

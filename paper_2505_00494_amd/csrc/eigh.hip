@@ -12,8 +12,9 @@
 //                         pairs, in place, disjoint) and V <- V J.
 // A sweep without any rotation ends the iteration (host reads one counter per
 // sweep).  Then the kept eigenpairs are ranked by |lambda| (descending; ties by
-// lambda ascending, then index), sign-fixed (largest-|.| component positive)
-// and written out as U (n x k, row-major) and diag(lambda).
+// lambda ascending, then index), sign-fixed (first component with
+// |v_i| >= max|v|/2 positive) and written out as U (n x k, row-major) and
+// diag(lambda).
 #include "common.h"
 #include "eigh.h"
 
@@ -148,6 +149,18 @@ __global__ void select_kernel(const double* __restrict__ V, int n, int k,
                 bi[threadIdx.x] = oi;
             }
         }
+        __syncthreads();
+    }
+    // sign: the first component with |v_i| >= max|v| / 2 is made positive
+    const double half = 0.5 * bv[0];
+    __syncthreads();
+    int first = n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (fabs(V[(size_t)i * n + col]) >= half) { first = i; break; }
+    bi[threadIdx.x] = first;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) bi[threadIdx.x] = min(bi[threadIdx.x], bi[threadIdx.x + w]);
         __syncthreads();
     }
     const double sg = V[(size_t)bi[0] * n + col] < 0.0 ? -1.0 : 1.0;
