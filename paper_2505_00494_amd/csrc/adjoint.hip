@@ -50,14 +50,27 @@ __global__ __launch_bounds__(kThreads) void sym_norm_bwd_kernel(
     const double* __restrict__ Cn, const double* __restrict__ Cb, const double* __restrict__ Tn,
     const double* __restrict__ Tb, int chi, int Dab, double* Cpb, double* Tpb) {
     __shared__ double s[2];
-    if (threadIdx.x == 0) {
+    __shared__ double ra[kThreads], rb[kThreads];
+    {
         double a = 0.0, b = 0.0;
-        for (int q = 0; q < nparts; ++q) {
+        for (int q = threadIdx.x; q < nparts; q += kThreads) {
             a += part[2 * q];
             b += part[2 * q + 1];
         }
-        s[0] = a;
-        s[1] = b;
+        ra[threadIdx.x] = a;
+        rb[threadIdx.x] = b;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                ra[threadIdx.x] += ra[threadIdx.x + w];
+                rb[threadIdx.x] += rb[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        s[0] = ra[0];
+        s[1] = rb[0];
     }
     __syncthreads();
     const double dc = s[0], dt = s[1];

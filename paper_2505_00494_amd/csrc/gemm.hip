@@ -66,6 +66,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
 
     double ra[LA], rb[LB];
 
+    // Out-of-range elements are loaded from a clamped (valid) address and
+    // replaced by zero, so the loads carry no branches.
     auto load = [&](long long k0) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
@@ -73,9 +75,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
             int mm, kk;
             if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
             const long long gm = m0 + mm, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < p.M && gk < kend) v = TA ? p.A[gk * p.lda + gm] : p.A[gm * p.lda + gk];
-            ra[i] = v;
+            const bool in = gm < p.M && gk < kend;
+            const long long cm = in ? gm : 0, ck = in ? gk : kbeg;
+            const double v = TA ? p.A[ck * p.lda + cm] : p.A[cm * p.lda + ck];
+            ra[i] = in ? v : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
@@ -83,9 +86,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
             int nn, kk;
             if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
             const long long gn = n0 + nn, gk = k0 + kk;
-            double v = 0.0;
-            if (gn < p.N && gk < kend) v = TB ? p.B[gn * p.ldb + gk] : p.B[gk * p.ldb + gn];
-            rb[i] = v;
+            const bool in = gn < p.N && gk < kend;
+            const long long cn = in ? gn : 0, ck = in ? gk : kbeg;
+            const double v = TB ? p.B[cn * p.ldb + ck] : p.B[ck * p.ldb + cn];
+            rb[i] = in ? v : 0.0;
         }
     };
     auto store = [&](int buf) {
@@ -144,24 +148,32 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
     // epilogue: with A fed as A[lane%16][lane/16] and B as B[lane/16][lane%16],
     // accumulator element r of a lane is D[4*r + lane/16][lane%16] (measured
     // lane layout of v_mfma_f64_16x16x4_f64 on gfx950)
+    // Row and column offsets are computed once per accumulator row / column.
     const long long MN = p.M * p.N;
+    long long noff[FN];
+    bool nok[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const long long n = n0 + wn * WN + j * 16 + lrow;
+        nok[j] = n < p.N;
+        noff[j] = p.partial ? n : (n / p.map.ndiv) * p.map.ns1 + (n % p.map.ndiv) * p.map.ns2;
+    }
+    double* Cb = p.partial ? p.C + (long long)blockIdx.y * MN : p.C;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const long long n = n0 + wn * WN + j * 16 + lrow;
-            if (n >= p.N) continue;
+        for (int r = 0; r < 4; ++r) {
+            const long long m = m0 + wm * WM + i * 16 + 4 * r + lk;
+            if (m >= p.M) continue;
+            const long long moff =
+                p.partial ? m * p.N : (m / p.map.mdiv) * p.map.ms1 + (m % p.map.mdiv) * p.map.ms2;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const long long m = m0 + wm * WM + i * 16 + 4 * r + lk;
-                if (m >= p.M) continue;
+            for (int j = 0; j < FN; ++j) {
+                if (!nok[j]) continue;
                 const double v = acc[i][j][r];
-                if (p.partial) {
-                    p.C[(long long)blockIdx.y * MN + m * p.N + n] = v;
-                } else {
-                    const long long o = out_index(p.map, m, n);
-                    p.C[o] = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * p.C[o];
-                }
+                double* o = Cb + moff + noff[j];
+                if (p.partial) *o = v;
+                else *o = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *o;
             }
         }
 }
@@ -197,7 +209,7 @@ void launch_t(const KArgs& a, int ta, int tb, int splits, hipStream_t st) {
 }
 
 struct Plan {
-    int cfg;      // 0: 128x128, 1: 64x64
+    int cfg;      // 0: 128x128 (8 waves of 64x32), 1: 64x64 (4 waves of 32x32)
     int bm, bn;
     int splits;
     long long kchunk;
@@ -270,7 +282,7 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
         a.C = g.C;
         a.partial = 0;
     }
-    if (pl.cfg == 0) launch_t<128, 128, 16, 64, 64>(a, g.trans_a, g.trans_b, pl.splits, st);
+    if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32>(a, g.trans_a, g.trans_b, pl.splits, st);
     else launch_t<64, 64, 16, 32, 32>(a, g.trans_a, g.trans_b, pl.splits, st);
     QRCTM_TRY(launch_check("gemm_f64_kernel"));
     if (pl.splits > 1) {

@@ -96,13 +96,33 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
         const double* pp = part + (size_t)(j & 1) * pstride;
         const double* row = rowbuf + (size_t)(j & 1) * n;
         const int nslots = n - j;
-        // combine partials in a fixed order (deterministic)
-        for (int s = tid; s < nslots; s += kQrThreads) {
-            double acc = 0.0;
-            for (int q = 0; q < P; ++q) acc += pp[(size_t)q * (n + 1) + s];
-            wv[j + s] = acc;  // wv[j] = sigma^2, wv[k] = dot_k (k > j)
+        // combine partials in a fixed order (deterministic): 64 slot lanes x 4
+        // workgroup groups, four independent running sums per thread so that
+        // many loads are in flight, then the 4 groups through LDS.
+        {
+            const int sl = tid % kColGroup, qg = tid / kColGroup;
+            for (int s0 = 0; s0 < nslots; s0 += kColGroup) {
+                const int sidx = s0 + sl;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                if (sidx < nslots) {
+                    const double* col = pp + sidx;
+                    int q = qg;
+                    for (; q + 3 * kRowGroups < P; q += 4 * kRowGroups) {
+                        a0 += col[(size_t)q * (n + 1)];
+                        a1 += col[(size_t)(q + kRowGroups) * (n + 1)];
+                        a2 += col[(size_t)(q + 2 * kRowGroups) * (n + 1)];
+                        a3 += col[(size_t)(q + 3 * kRowGroups) * (n + 1)];
+                    }
+                    for (; q < P; q += kRowGroups) a0 += col[(size_t)q * (n + 1)];
+                    red[qg * (n + 1) + sidx] = (a0 + a1) + (a2 + a3);
+                }
+            }
+            __syncthreads();
+            for (int sidx = tid; sidx < nslots; sidx += kQrThreads)
+                wv[j + sidx] = (red[sidx] + red[(n + 1) + sidx]) +
+                               (red[2 * (n + 1) + sidx] + red[3 * (n + 1) + sidx]);
+            __syncthreads();  // red is reused by column_partials below
         }
-        __syncthreads();
         if (tid == 0) {
             const double alpha = row[j];
             const double sigma2 = wv[j];
@@ -153,14 +173,15 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
             V[(size_t)gi * n + j] = v;
         }
         __syncthreads();
-        // apply H_j to the local rows strictly below j (row j is R's row)
+        // apply H_j to the local rows strictly below j (row j is R's row):
+        // 64 column lanes x 4 row groups, no index division
         if (mode != 0) {
             const int istart = max(0, j + 1 - r0);
-            const int ncol = n - j - 1;
-            const int rows = nr - istart;
-            for (int e = tid; e < rows * ncol; e += kQrThreads) {
-                const int i = istart + e / ncol, k = j + 1 + e % ncol;
-                Ab[i * n + k] -= t * vloc[i] * wv[k];
+            const int cl = tid % kColGroup, rg = tid / kColGroup;
+            for (int i = istart + rg; i < nr; i += kRowGroups) {
+                const double tv = t * vloc[i];
+                double* row_i = Ab + i * n;
+                for (int k = j + 1 + cl; k < n; k += kColGroup) row_i[k] -= tv * wv[k];
             }
         }
         __syncthreads();
@@ -176,27 +197,52 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
     }
 }
 
-// T[i][j] (i <= j): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j].
-// Also the diagonal ratio min|R_ii| / max|R_ii| into diag_ratio.
+// T[i][j] (i <= j): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j]
+// (the forward compact-WY recurrence), in column blocks of kTb: the part of the
+// triangular product over columns left of the block is one parallel pass over
+// the whole block (partial results in LDS); the in-block part is sequential
+// over the kTb columns.  Also min|R_ii| / max|R_ii| into diag_ratio.
+constexpr int kTb = 16;
+constexpr int kTMaxN = 512;
+
 __global__ __launch_bounds__(1024) void qr_tfactor_kernel(const double* __restrict__ G,
                                                           const double* __restrict__ tau, int n,
                                                           double* T, const double* R,
                                                           double* diag_ratio) {
+    __shared__ double W1[kTMaxN * kTb];  // W1[i*kTb + c] = sum_{l<b0} T[i][l] G[l][b0+c]
+    __shared__ double Tb[kTMaxN * kTb];  // current block's columns of T: Tb[i*kTb + c]
     const int tid = threadIdx.x;
     for (int e = tid; e < n * n; e += blockDim.x) T[e] = 0.0;
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double tj = tau[j];
-        double val = 0.0;
-        const int i = tid;
-        if (i < j) {
+    for (int b0 = 0; b0 < n; b0 += kTb) {
+        const int nb = min(kTb, n - b0);
+        for (int e = tid; e < b0 * nb; e += blockDim.x) {
+            const int i = e / nb, c = e % nb;
             double acc = 0.0;
-            for (int l = i; l < j; ++l) acc += T[(size_t)i * n + l] * G[(size_t)l * n + j];
-            val = -tj * acc;
+            for (int l = i; l < b0; ++l) acc += T[(size_t)i * n + l] * G[(size_t)l * n + b0 + c];
+            W1[i * kTb + c] = acc;
         }
+        for (int e = tid; e < (b0 + nb) * kTb; e += blockDim.x) Tb[e] = 0.0;
         __syncthreads();
-        if (i < j) T[(size_t)i * n + j] = val;
-        if (i == j) T[(size_t)j * n + j] = tj;
+        for (int c = 0; c < nb; ++c) {
+            const int jj = b0 + c;
+            const double tj = tau[jj];
+            double val = 0.0;
+            const int i = tid;
+            if (i < jj) {
+                double acc = i < b0 ? W1[i * kTb + c] : 0.0;
+                for (int l = max(i, b0); l < jj; ++l) acc += Tb[i * kTb + (l - b0)] * G[(size_t)l * n + jj];
+                val = -tj * acc;
+            }
+            __syncthreads();
+            if (i < jj) Tb[i * kTb + c] = val;
+            if (i == jj) Tb[i * kTb + c] = tj;
+            __syncthreads();
+        }
+        for (int e = tid; e < (b0 + nb) * nb; e += blockDim.x) {
+            const int i = e / nb, c = e % nb;
+            T[(size_t)i * n + b0 + c] = Tb[i * kTb + c];
+        }
         __syncthreads();
     }
     if (tid == 0 && diag_ratio != nullptr) {
@@ -264,7 +310,7 @@ QrScratch qr_scratch_layout(int m, int n) {
 bool qr_fits(int m, int n) {
     if (m < n || n < 1) return false;
     const QrLayout L = plan_qr(m, n);
-    return L.lds_bytes <= kQrLdsBudget + 8192 && n <= 1024;
+    return L.lds_bytes <= kQrLdsBudget + 8192 && n <= kTMaxN;
 }
 
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
@@ -272,7 +318,7 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     Status s;
     if (!qr_fits(m, n)) {
         s.code = -1;
-        s.msg = "qr: shape not supported (need m >= n, n <= 1024, row blocks within LDS)";
+        s.msg = "qr: shape not supported (need m >= n, n <= 512, row blocks within LDS)";
         return s;
     }
     const QrScratch L = qr_scratch_layout(m, n);

@@ -3,8 +3,9 @@
 // normalised corner spectrum is the measure used here).
 //
 // One workgroup of 1024 threads: Householder tridiagonalisation of the
-// symmetric chi x chi corner (matrix in global scratch, L2 resident, both
-// triangles kept so every access is a coalesced row access), eigenvalues of the
+// symmetric chi x chi corner (packed lower triangle in LDS up to chi = 176;
+// beyond that in global scratch, L2 resident, both triangles kept so every
+// access is a coalesced row access), eigenvalues of the
 // tridiagonal matrix by Sturm-sequence bisection (one eigenvalue per thread),
 // |lambda| ranked in descending order (ties by index), normalised by their sum,
 // and delta = || s - s_prev ||_2 with the shorter spectrum padded by zeros.
@@ -42,27 +43,56 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
     return c;
 }
 
+// Symmetric matrix storage: full rows in global scratch (any n), or the packed
+// lower triangle in LDS (n <= kLdsMaxN), index i(i+1)/2 + j for i >= j.
+struct GlobalSym {
+    double* S;
+    int n;
+    __device__ double get(int i, int j) const { return S[(size_t)i * n + j]; }
+    __device__ void sub(int i, int j, double v) { S[(size_t)i * n + j] -= v; }
+    __device__ void set(int i, int j, double v) { S[(size_t)i * n + j] = v; }
+    static constexpr bool kBothTriangles = true;
+};
+struct LdsSym {
+    double* S;
+    int n;
+    __device__ static int idx(int i, int j) { return i * (i + 1) / 2 + j; }
+    __device__ double get(int i, int j) const { return i >= j ? S[idx(i, j)] : S[idx(j, i)]; }
+    __device__ void sub(int i, int j, double v) { S[idx(i, j)] -= v; }
+    __device__ void set(int i, int j, double v) { S[idx(i, j)] = v; }
+    static constexpr bool kBothTriangles = false;
+};
+
+constexpr int kLdsMaxN = 176;
+
+template <class Store, int MAXN>
 __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __restrict__ C, int n,
-                                                                double* S, const double* s_prev,
+                                                                double* Sg, const double* s_prev,
                                                                 int n_prev, double* s_out,
                                                                 double* delta_out) {
-    __shared__ double v[kMaxN], p[kMaxN], dd[kMaxN], ee[kMaxN], lam[kMaxN], red[kSpecThreads];
-    __shared__ double sc[4];
+    __shared__ double v[MAXN], p[MAXN], dd[MAXN], ee[MAXN], lam[MAXN], red[kSpecThreads];
+    extern __shared__ double dyn[];
+    Store A;
+    A.S = Store::kBothTriangles ? Sg : dyn;
+    A.n = n;
     const int t = threadIdx.x;
     for (long long q = t; q < (long long)n * n; q += kSpecThreads) {
-        const long long i = q / n, j = q % n;
-        S[q] = 0.5 * (C[q] + C[j * n + i]);
+        const int i = (int)(q / n), j = (int)(q % n);
+        if (Store::kBothTriangles || i >= j) A.set(i, j, 0.5 * (C[q] + C[(size_t)j * n + i]));
     }
     __syncthreads();
 
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
-        const double* rowk = S + (size_t)k * n + (k + 1);  // x = S[k][k+1 .. n-1]
+        // x = column k below the diagonal (rows k+1 .. n-1)
         double part = 0.0;
-        for (int i = 1 + t; i < m; i += kSpecThreads) part += rowk[i] * rowk[i];
+        for (int i = 1 + t; i < m; i += kSpecThreads) {
+            const double xi = A.get(k + 1 + i, k);
+            part += xi * xi;
+        }
         const double sigma2 = block_sum(part, red);
-        const double alpha = rowk[0];
-        if (t == 0) dd[k] = S[(size_t)k * n + k];
+        const double alpha = A.get(k + 1, k);
+        if (t == 0) dd[k] = A.get(k, k);
         if (sigma2 == 0.0) {
             if (t == 0) ee[k] = alpha;
             __syncthreads();
@@ -71,14 +101,13 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
         const double beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
         const double tau = (beta - alpha) / beta;
         const double scal = 1.0 / (alpha - beta);
-        for (int i = t; i < m; i += kSpecThreads) v[i] = (i == 0) ? 1.0 : rowk[i] * scal;
+        for (int i = t; i < m; i += kSpecThreads) v[i] = (i == 0) ? 1.0 : A.get(k + 1 + i, k) * scal;
         if (t == 0) ee[k] = beta;
         __syncthreads();
-        // p = tau * A22 v  (A22 symmetric: read column i as row i)
-        const double* A22 = S + (size_t)(k + 1) * n + (k + 1);
+        // p = tau * A22 v  (A22 symmetric; the global store reads column i as row i)
         for (int i = t; i < m; i += kSpecThreads) {
             double acc = 0.0;
-            for (int j = 0; j < m; ++j) acc += A22[(size_t)j * n + i] * v[j];
+            for (int jx = 0; jx < m; ++jx) acc += A.get(k + 1 + jx, k + 1 + i) * v[jx];
             p[i] = tau * acc;
         }
         __syncthreads();
@@ -87,24 +116,24 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
         const double K = 0.5 * tau * block_sum(pv, red);
         for (int i = t; i < m; i += kSpecThreads) p[i] -= K * v[i];  // w
         __syncthreads();
-        double* B22 = S + (size_t)(k + 1) * n + (k + 1);
         for (long long q = t; q < (long long)m * m; q += kSpecThreads) {
-            const int i = (int)(q / m), j = (int)(q % m);
-            B22[(size_t)i * n + j] -= v[i] * p[j] + p[i] * v[j];
+            const int i = (int)(q / m), jx = (int)(q % m);
+            if (Store::kBothTriangles || i >= jx)
+                A.sub(k + 1 + i, k + 1 + jx, v[i] * p[jx] + p[i] * v[jx]);
         }
         __syncthreads();
     }
     if (t == 0) {
         if (n >= 2) {
-            dd[n - 2] = S[(size_t)(n - 2) * n + (n - 2)];
-            dd[n - 1] = S[(size_t)(n - 1) * n + (n - 1)];
-            ee[n - 2] = S[(size_t)(n - 2) * n + (n - 1)];
+            dd[n - 2] = A.get(n - 2, n - 2);
+            dd[n - 1] = A.get(n - 1, n - 1);
+            ee[n - 2] = A.get(n - 1, n - 2);
         } else {
-            dd[0] = S[0];
+            dd[0] = A.get(0, 0);
         }
     }
     __syncthreads();
-    // e^2 in place, Gershgorin interval
+    // Gershgorin interval
     double lo = INFINITY, hi = -INFINITY, me2 = 0.0;
     for (int i = 0; i < n; ++i) {
         const double el = i > 0 ? fabs(ee[i - 1]) : 0.0;
@@ -137,9 +166,9 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
     int rank = 0;
     if (t < n) {
         mine = lam[t];
-        for (int j = 0; j < n; ++j) {
-            const double o = lam[j];
-            rank += (o > mine) || (o == mine && j < t);
+        for (int jx = 0; jx < n; ++jx) {
+            const double o = lam[jx];
+            rank += (o > mine) || (o == mine && jx < t);
         }
     }
     __syncthreads();
@@ -159,7 +188,6 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
     }
     const double dsum = block_sum(dl, red);
     if (t == 0) *delta_out = sqrt(dsum);
-    (void)sc;
 }
 
 }  // namespace
@@ -174,8 +202,17 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
         s.msg = "spectrum: chi must be in [1, 1024]";
         return s;
     }
-    hipLaunchKernelGGL(spectrum_kernel, dim3(1), dim3(kSpecThreads), 0, st, C, n, S, s_prev, n_prev,
-                       s_out, delta_out);
+    if (n <= kLdsMaxN) {
+        const size_t lds = sizeof(double) * (size_t)n * (n + 1) / 2;
+        auto kern = spectrum_kernel<LdsSym, kLdsMaxN>;
+        QRCTM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), lds, st, C, n, S, s_prev, n_prev, s_out,
+                           delta_out);
+    } else {
+        hipLaunchKernelGGL((spectrum_kernel<GlobalSym, kMaxN>), dim3(1), dim3(kSpecThreads), 0, st, C, n,
+                           S, s_prev, n_prev, s_out, delta_out);
+    }
     return launch_check("spectrum_kernel");
 }
 

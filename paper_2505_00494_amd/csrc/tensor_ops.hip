@@ -180,14 +180,27 @@ __global__ __launch_bounds__(kNormThreads) void normalize_kernel(const double* _
                                                                  double* Cn, double* Tn,
                                                                  double* norms, int* bad) {
     __shared__ double s[2];
-    if (threadIdx.x == 0) {
+    __shared__ double ra[kNormThreads], rb[kNormThreads];
+    {
         double a = 0.0, b = 0.0;
-        for (int q = 0; q < nparts; ++q) {
+        for (int q = threadIdx.x; q < nparts; q += kNormThreads) {
             a += part[2 * q];
             b += part[2 * q + 1];
         }
-        s[0] = sqrt(a);
-        s[1] = sqrt(b);
+        ra[threadIdx.x] = a;
+        rb[threadIdx.x] = b;
+        __syncthreads();
+        for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                ra[threadIdx.x] += ra[threadIdx.x + w];
+                rb[threadIdx.x] += rb[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        s[0] = sqrt(ra[0]);
+        s[1] = sqrt(rb[0]);
         if (blockIdx.x == 0 && norms) {
             norms[0] = s[0];
             norms[1] = s[1];
