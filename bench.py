@@ -14,6 +14,10 @@ launch with HIP events on the library's stream in a second pass, for the
 roofline figure.  The CPU baseline is the FP64 oracle on the host cores on a
 bounded sample of the same workload.
 
+Also reported (same tensor): the mixed form (bulk contractions on the FP32
+matrix cores) with its speed-up and energy error against the FP64 path, and
+the time of one dE/dA (k tracked steps, energy and the reverse pass).
+
 Prints ONE JSON line.
 """
 from __future__ import annotations
@@ -79,6 +83,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--acc-steps", type=int, default=20)
+    ap.add_argument("--k", type=int, default=10, help="tracked steps of the gradient")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -146,6 +154,55 @@ def main():
                      "traffic": None, "kernel": "double-layer contraction Z = Y a (3b)",
                      "flops_per_launch": flops_3b(chi, D), "ms_per_launch": ms_3b},
     }
+    # mixed form: same tensor, bulk contractions on FP32 matrix cores
+    if not args.no_mixed:
+        C0, T0 = ctx.get_env()
+        mctx = P.Context(A, chi, precision=P.PREC_FP32_MFMA, n_warmup=0)
+        mctx.set_env(C0, T0)
+        mctx.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mctx.step(args.steps)
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - t0
+        mctx.set_timing(True)
+        mctx.step(nt)
+        mst = mctx.stats()
+        mctx.set_timing(False)
+        ms_m = {k: v / mst["timed_steps"] for k, v in mst["ms_phase"].items()}
+        # accuracy: the same number of steps from the same environment, energy
+        # from the FP64 energy contraction
+        h = inp.heisenberg_bond_rotated()
+        nacc = args.acc_steps
+        ctx.set_env(C0, T0)
+        ctx.step(nacc)
+        e64 = ctx.energy(h)
+        mctx.set_env(C0, T0)
+        mctx.step(nacc)
+        e32 = mctx.energy(h)
+        out["mixed"] = {"precision": "fp32 matrix cores (FP32 products and accumulation); "
+                                     "QR, normalisation, spectrum FP64",
+                        "steps_per_s": args.steps / el_m, "ms_per_step": 1e3 * el_m / args.steps,
+                        "speedup_vs_fp64": (args.steps / el_m) / steps_per_s,
+                        "ms_per_phase": ms_m,
+                        "energy_fp64": e64, "energy_mixed": e32,
+                        "energy_rel_err_vs_fp64": abs(e32 - e64) / abs(e64),
+                        "accuracy_steps": nacc}
+        mctx.close()
+    # dE/dA: k tracked steps + energy + reverse pass from the current environment
+    if not args.no_grad:
+        gctx = P.Context(A, chi, n_warmup=0, k_tracked=args.k)
+        C0, T0 = ctx.get_env()
+        gctx.set_env(C0, T0)
+        h = inp.heisenberg_bond_rotated()
+        gctx.energy_grad(h)                       # warm-up call
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, g = gctx.energy_grad(h)
+        torch.cuda.synchronize()
+        out["grad"] = {"ms": 1e3 * (time.perf_counter() - t0), "k_tracked": args.k,
+                       "energy": e, "grad_norm": float(g.norm())}
+        gctx.close()
     ctx.close()
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)

@@ -69,6 +69,7 @@ struct GemmDesc {
     double* C = nullptr;
     OutMap map{};
     double alpha = 1.0, beta = 0.0;
+    int prec = 0;  // 0: FP64 matrix cores; 1: FP32 products and accumulation
 };
 
 // Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the

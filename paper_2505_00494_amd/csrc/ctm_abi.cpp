@@ -18,6 +18,7 @@
 #include "eigh.h"
 #include "energy.h"
 #include "qr.h"
+#include "step_gemms.h"
 #include "spectrum.h"
 #include "tensor_ops.h"
 
@@ -45,62 +46,6 @@ struct Shape {
 };
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
-
-// GEMM descriptors of one QR step at (chi_in -> chi_out) -----------------------
-struct StepPtrs {
-    const double *C, *T, *a;
-    double *Q, *R, *Y, *Z, *Tp, *W, *Cp;
-};
-
-GemmDesc g_reduced_corner(const StepPtrs& p, int chi, int Dab) {
-    GemmDesc g;  // ct[(y,m), c] = sum_x C[y,x] T[x,m,c]
-    g.M = chi; g.N = (long long)Dab * chi; g.K = chi;
-    g.A = p.C; g.lda = chi; g.B = p.T; g.ldb = (long long)Dab * chi;
-    g.C = p.Q; g.map = OutMap::plain(g.M, g.N, g.N);
-    return g;
-}
-GemmDesc g_edge_a(const StepPtrs& p, const double* Q, int chi, int chio, int Dab) {
-    GemmDesc g;  // Y[al,f,u,l] = sum_e Q[(e,u),al] T[f,l,e]   (T[x,m,y] = T[y,m,x])
-    g.trans_a = 1; g.trans_b = 1;
-    g.M = (long long)Dab * chio; g.N = (long long)chi * Dab; g.K = chi;
-    g.A = Q; g.lda = (long long)Dab * chio;
-    g.B = p.T; g.ldb = chi;
-    g.C = p.Y;
-    const long long D2 = (long long)Dab * Dab;
-    g.map = OutMap{chio, Dab, (long long)chi * D2, Dab, D2, 1};
-    return g;
-}
-GemmDesc g_edge_b(const StepPtrs& p, int chi, int chio, int Dab) {
-    GemmDesc g;  // Z[al,r,f,d] = sum_{u,l} Y[al,f,u,l] a[u,l,r,d]
-    const long long D2 = (long long)Dab * Dab;
-    g.M = (long long)chio * chi; g.N = D2; g.K = D2;
-    g.A = p.Y; g.lda = D2; g.B = p.a; g.ldb = D2;
-    g.C = p.Z;
-    g.map = OutMap{chi, (long long)chi * D2, Dab, Dab, (long long)chi * Dab, 1};
-    return g;
-}
-GemmDesc g_edge_c(const StepPtrs& p, const double* Q, int chi, int chio, int Dab) {
-    GemmDesc g;  // T'[al,r,be] = sum_{f,d} Z[al,r,f,d] Q[(f,d),be]
-    g.M = (long long)chio * Dab; g.N = chio; g.K = (long long)chi * Dab;
-    g.A = p.Z; g.lda = (long long)chi * Dab; g.B = Q; g.ldb = chio;
-    g.C = p.Tp; g.map = OutMap::plain(g.M, g.N, g.N);
-    return g;
-}
-GemmDesc g_corner_w(const StepPtrs& p, int chi, int Dab) {
-    GemmDesc g;  // W[g,r,b] = sum_c R[g,c] Q[(c,r),b]
-    g.M = chi; g.N = (long long)Dab * chi; g.K = chi;
-    g.A = p.R; g.lda = chi; g.B = p.Q; g.ldb = (long long)Dab * chi;
-    g.C = p.W; g.map = OutMap::plain(g.M, g.N, g.N);
-    return g;
-}
-GemmDesc g_corner_c(const StepPtrs& p, int chi, int Dab) {
-    GemmDesc g;  // C'[a,b] = sum_{g,r} T'[g,r,a] W[g,r,b]
-    g.trans_a = 1;
-    g.M = chi; g.N = chi; g.K = (long long)chi * Dab;
-    g.A = p.Tp; g.lda = chi; g.B = p.W; g.ldb = chi;
-    g.C = p.Cp; g.map = OutMap::plain(chi, chi, chi);
-    return g;
-}
 
 size_t step_splitk_bytes(int chi, int Dab) {
     StepPtrs p{};
@@ -278,7 +223,11 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
 constexpr int kPhases = 8;  // reduced corner, QR, 3a, 3b, 3c, corner, sym/norm, spectrum
 
 // small-scalar slots (doubles) inside Plan::small
-enum { SL_DELTA = 0, SL_NORMS = 2, SL_RATIO = 4, SL_SCALE = 5, SL_BAD = 8, SL_IMAX = 10, SL_E = 16 };
+// SL_DELTA: ring of kDeltaSlots deltas (one per QR step, written on the
+// auxiliary stream); SL_DELTA_SCRATCH: delta of spectra computed outside the loop.
+constexpr int kDeltaSlots = 8;
+enum { SL_NORMS = 2, SL_RATIO = 4, SL_SCALE = 5, SL_BAD = 8, SL_IMAX = 10, SL_E = 16,
+       SL_DELTA = 32, SL_DELTA_SCRATCH = 48 };
 
 }  // namespace
 
@@ -300,11 +249,30 @@ struct ctm_ctx {
     // optional per-phase timing of QR steps (hipEvents on the context stream)
     bool timing = false;
     hipEvent_t ev[kPhases + 1] = {};
+    hipEvent_t ev_sp[2] = {};
     double ms_phase[kPhases] = {};
     long long timed_steps = 0;
+    // The corner spectrum of step i runs on an auxiliary stream, concurrently
+    // with step i+1 on the main stream.  ev_specdone[b] marks the end of the
+    // spectrum that reads environment buffer b; the main stream waits on it
+    // before overwriting b two steps later.
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_normed = nullptr, ev_join = nullptr, ev_specdone[2] = {};
+    bool spec_pending[2] = {false, false};
+    int last_slot = 0;
     ~ctm_ctx() {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto& e : ev_sp)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : ev_specdone)
+            if (e) (void)hipEventDestroy(e);
+        if (ev_normed) (void)hipEventDestroy(ev_normed);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
     }
 
     template <class T = double>
@@ -337,6 +305,14 @@ int fail(ctm_ctx* c, int code, const std::string& msg) {
 }
 
 Status sync(hipStream_t st) { return hip_status(hipStreamSynchronize(st), "hipStreamSynchronize"); }
+
+// Make the main stream wait for all work queued on the auxiliary stream.
+Status join_aux(ctm_ctx* c) {
+    QRCTM_HIP(hipEventRecord(c->ev_join, c->aux));
+    QRCTM_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
+    c->spec_pending[0] = c->spec_pending[1] = false;
+    return Status{};
+}
 
 Status read_bad(ctm_ctx* c, bool* bad) {
     int h = 0;
@@ -390,20 +366,27 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     };
     void* sk = c->ptr<void>(c->plan.splitk);
     const size_t skb = c->plan.splitk_bytes;
+    // mixed form: the bulk contractions on FP32 matrix cores; QR, normalisation
+    // and the spectrum stay FP64
+    const int prec = c->opts.precision == CTM_PREC_FP32_MFMA ? 1 : 0;
+    auto G = [&](GemmDesc g) {
+        g.prec = prec;
+        return gemm_f64(g, sk, skb, c->st);
+    };
     QRCTM_TRY(mark(0));
-    QRCTM_TRY(gemm_f64(g_reduced_corner(p, chi, Dab), sk, skb, c->st));               // a5
+    QRCTM_TRY(G(g_reduced_corner(p, chi, Dab)));                                       // a5
     QRCTM_TRY(mark(1));
     QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
-                     c->st, c->small() + SL_RATIO));                                 // a6
+                     c->st, c->small() + SL_RATIO, c->bad()));                      // a6
     QRCTM_TRY(mark(2));
-    QRCTM_TRY(gemm_f64(g_edge_a(p, p.Q, chi, chi, Dab), sk, skb, c->st));             // a7 3a
+    QRCTM_TRY(G(g_edge_a(p, p.Q, chi, chi, Dab)));                                     // a7 3a
     QRCTM_TRY(mark(3));
-    QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chi, Dab), sk, skb, c->st));                  // a7 3b
+    QRCTM_TRY(G(g_edge_b(p, chi, chi, Dab)));                                          // a7 3b
     QRCTM_TRY(mark(4));
-    QRCTM_TRY(gemm_f64(g_edge_c(p, p.Q, chi, chi, Dab), sk, skb, c->st));             // a7 3c
+    QRCTM_TRY(G(g_edge_c(p, p.Q, chi, chi, Dab)));                                     // a7 3c
     QRCTM_TRY(mark(5));
-    QRCTM_TRY(gemm_f64(g_corner_w(p, chi, Dab), sk, skb, c->st));                     // a8
-    QRCTM_TRY(gemm_f64(g_corner_c(p, chi, Dab), sk, skb, c->st));
+    QRCTM_TRY(G(g_corner_w(p, chi, Dab)));                                             // a8
+    QRCTM_TRY(G(g_corner_c(p, chi, Dab)));
     QRCTM_TRY(mark(6));
     QRCTM_TRY(sym_norm(p.Cp, p.Tp, chi, Dab, Cout, Tout, c->ptr(c->plan.normpart),
                        c->small() + SL_NORMS, c->bad(), c->st));                     // a9
@@ -411,19 +394,33 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
 }
 
 // a5-a10 once; environment moves to the other buffer; spectrum likewise.
+// a10 (the corner spectrum) is queued on the auxiliary stream.
 Status qr_step_once(ctm_ctx* c) {
     const int chi = c->chi_cur;
+    const int target = c->cur ^ 1;  // environment buffer this step writes
+    if (c->spec_pending[target]) QRCTM_HIP(hipStreamWaitEvent(c->st, c->ev_specdone[target], 0));
     QRCTM_TRY(qr_step_core(c, c->C(), c->T(), c->Cn(), c->Tn(), true));
+    QRCTM_HIP(hipEventRecord(c->ev_normed, c->st));
+    QRCTM_HIP(hipStreamWaitEvent(c->aux, c->ev_normed, 0));
+    const int slot = (int)(c->steps % kDeltaSlots);
+    if (c->timing) QRCTM_HIP(hipEventRecord(c->ev_sp[0], c->aux));
     QRCTM_TRY(corner_spectrum(c->Cn(), chi, c->ptr(c->plan.S), c->spec(), c->n_spec,
-                              c->spec_next(), c->small() + SL_DELTA, c->st));        // a10
-    QRCTM_TRY(mark(c, 8));
+                              c->spec_next(), c->small() + SL_DELTA + slot, c->aux));  // a10
+    if (c->timing) QRCTM_HIP(hipEventRecord(c->ev_sp[1], c->aux));
+    QRCTM_HIP(hipEventRecord(c->ev_specdone[target], c->aux));
+    c->spec_pending[target] = true;
+    c->last_slot = slot;
     if (c->timing) {
-        QRCTM_HIP(hipEventSynchronize(c->ev[kPhases]));
-        for (int i = 0; i < kPhases; ++i) {
+        QRCTM_HIP(hipEventSynchronize(c->ev[kPhases - 1]));
+        QRCTM_HIP(hipEventSynchronize(c->ev_sp[1]));
+        for (int i = 0; i < kPhases - 1; ++i) {
             float ms = 0.f;
             QRCTM_HIP(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
             c->ms_phase[i] += ms;
         }
+        float ms = 0.f;
+        QRCTM_HIP(hipEventElapsedTime(&ms, c->ev_sp[0], c->ev_sp[1]));
+        c->ms_phase[kPhases - 1] += ms;
         c->timed_steps++;
     }
     c->cur ^= 1;
@@ -436,6 +433,7 @@ Status qr_step_once(ctm_ctx* c) {
 // Standard step (warm-up): eigh of the enlarged corner, chi grows to
 // min(chi_target, chi_cur * Dab).
 Status eigh_step_once(ctm_ctx* c) {
+    QRCTM_TRY(join_aux(c));
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     const int n = chi * Dab;
     const int chio = std::min(c->sh.chi, n);
@@ -453,7 +451,7 @@ Status eigh_step_once(ctm_ctx* c) {
     QRCTM_TRY(sym_norm(p.Cp, p.Tp, chio, Dab, c->Cn(), c->Tn(), c->ptr(c->plan.normpart),
                        c->small() + SL_NORMS, c->bad(), c->st));
     QRCTM_TRY(corner_spectrum(c->Cn(), chio, c->ptr(c->plan.S), c->spec(), c->n_spec,
-                              c->spec_next(), c->small() + SL_DELTA, c->st));
+                              c->spec_next(), c->small() + SL_DELTA_SCRATCH, c->st));
     c->cur ^= 1;
     c->spec_cur ^= 1;
     c->n_spec = chio;
@@ -521,6 +519,7 @@ __global__ void zero_kernel(double* x, long long n) {
 }
 
 Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA) {
+    QRCTM_TRY(join_aux(c));
     const int k = c->opts.k_tracked;
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     const size_t nC = (size_t)chi * chi, nT = nC * Dab;
@@ -587,8 +586,9 @@ int warmup_needed(int chi0, int Dab, int chi) {
 }
 
 Status fresh_spectrum(ctm_ctx* c) {
+    QRCTM_TRY(join_aux(c));
     QRCTM_TRY(corner_spectrum(c->C(), c->chi_cur, c->ptr(c->plan.S), nullptr, 0, c->spec(),
-                              c->small() + SL_DELTA, c->st));
+                              c->small() + SL_DELTA_SCRATCH, c->st));
     c->n_spec = c->chi_cur;
     return Status{};
 }
@@ -642,6 +642,15 @@ int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_
     c->ws = static_cast<char*>(ws);
     c->ws_bytes = ws_bytes;
     c->plan = P;
+    bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_normed, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_specdone[0], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_specdone[1], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        delete c;
+        return fail(nullptr, CTM_EHIP, "could not create the auxiliary stream / events");
+    }
     *made = c;
     return 0;
 }
@@ -758,6 +767,7 @@ int ctm_set_tensor(ctm_ctx* c, const double* A) {
     if (!c || !A) return fail(c, CTM_EINVAL, "NULL argument");
     if (!c->sh.quantum) return fail(c, CTM_ESTATE, "context was built from a double-layer tensor");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         QRCTM_TRY(clear_bad(c));
         QRCTM_TRY(c4v_prepare(A, c->sh.d, c->sh.D, c->ptr(c->plan.As), c->small() + SL_SCALE,
                               c->bad(), c->imax(), c->st));
@@ -780,8 +790,13 @@ int ctm_step(ctm_ctx* c, int nsteps, double* delta) {
         QRCTM_TRY(clear_bad(c));
         for (int i = 0; i < nsteps; ++i) QRCTM_TRY(qr_step_once(c));
         double h[2] = {NAN, NAN};
-        QRCTM_HIP(hipMemcpyAsync(h, c->small() + SL_DELTA, sizeof(double), hipMemcpyDeviceToHost,
-                                 c->st));
+        if (nsteps > 0) {
+            QRCTM_HIP(hipMemcpyAsync(h, c->small() + SL_DELTA + c->last_slot, sizeof(double),
+                                     hipMemcpyDeviceToHost, c->aux));
+            QRCTM_HIP(hipStreamSynchronize(c->aux));
+        } else {
+            h[0] = c->last_delta;
+        }
         bool bad = false;
         QRCTM_TRY(read_bad(c, &bad));
         c->last_delta = h[0];
@@ -802,14 +817,33 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delt
     double dl = NAN;
     int rc = guarded(c, [&]() -> Status {
         QRCTM_TRY(clear_bad(c));
-        while (taken < max_steps) {
+        // Step i+1 is queued before delta_i is read, so the GPU never waits
+        // for the host; if step i has converged, step i+1 is discarded (its
+        // outputs live in the other environment / spectrum buffers).
+        if (max_steps > 0) {
             QRCTM_TRY(qr_step_once(c));
-            ++taken;
-            QRCTM_HIP(hipMemcpyAsync(&dl, c->small() + SL_DELTA, sizeof(double),
-                                     hipMemcpyDeviceToHost, c->st));
-            QRCTM_TRY(sync(c->st));
-            if (!std::isfinite(dl)) break;
-            if (dl < tol) break;
+            taken = 1;
+            while (true) {
+                const int slot = c->last_slot;
+                const bool speculate = taken < max_steps;
+                if (speculate) QRCTM_TRY(qr_step_once(c));
+                QRCTM_HIP(hipMemcpyAsync(&dl, c->small() + SL_DELTA + slot, sizeof(double),
+                                         hipMemcpyDeviceToHost, c->aux));
+                QRCTM_TRY(hip_status(hipStreamSynchronize(c->aux), "hipStreamSynchronize"));
+                if (!std::isfinite(dl) || dl < tol) {
+                    if (speculate) {
+                        QRCTM_TRY(join_aux(c));
+                        QRCTM_TRY(sync(c->st));
+                        c->cur ^= 1;
+                        c->spec_cur ^= 1;
+                        c->steps--;
+                        c->last_slot = slot;
+                    }
+                    break;
+                }
+                if (!speculate) break;
+                ++taken;
+            }
         }
         bool bad = false;
         QRCTM_TRY(read_bad(c, &bad));
@@ -831,6 +865,7 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delt
 int ctm_get_env(ctm_ctx* c, double* C, double* T, int* chi_cur) {
     if (!c) return fail(c, CTM_EINVAL, "NULL context");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         const size_t nC = (size_t)c->chi_cur * c->chi_cur;
         if (C) QRCTM_HIP(hipMemcpyAsync(C, c->C(), nC * 8, hipMemcpyDeviceToDevice, c->st));
         if (T) QRCTM_HIP(hipMemcpyAsync(T, c->T(), nC * c->sh.Dab * 8, hipMemcpyDeviceToDevice, c->st));
@@ -843,6 +878,7 @@ int ctm_set_env(ctm_ctx* c, const double* C, const double* T, int chi_cur) {
     if (!c || !C || !T) return fail(c, CTM_EINVAL, "NULL argument");
     if (chi_cur < 1 || chi_cur > c->sh.chi) return fail(c, CTM_EINVAL, "chi_cur out of range");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         const size_t nC = (size_t)chi_cur * chi_cur;
         QRCTM_HIP(hipMemcpyAsync(c->C(), C, nC * 8, hipMemcpyDeviceToDevice, c->st));
         QRCTM_HIP(hipMemcpyAsync(c->T(), T, nC * c->sh.Dab * 8, hipMemcpyDeviceToDevice, c->st));
@@ -855,6 +891,7 @@ int ctm_set_env(ctm_ctx* c, const double* C, const double* T, int chi_cur) {
 int ctm_spectrum(ctm_ctx* c, double* s) {
     if (!c || !s) return fail(c, CTM_EINVAL, "NULL argument");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         QRCTM_HIP(hipMemcpyAsync(s, c->spec(), sizeof(double) * c->n_spec, hipMemcpyDeviceToHost,
                                  c->st));
         return sync(c->st);
@@ -865,9 +902,12 @@ int ctm_energy(ctm_ctx* c, const double* h_nn, const double* h_nnn, double J2, d
     if (!c || !h_nn || !E) return fail(c, CTM_EINVAL, "NULL argument");
     if (!c->sh.quantum) return fail(c, CTM_ESTATE, "energy needs a site tensor (ctm_init)");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         EnergyArgs ea{};
         ea.d = c->sh.d; ea.D = c->sh.D; ea.chi = c->chi_cur;
         ea.C = c->C(); ea.T = c->T(); ea.As = c->ptr(c->plan.As);
+        ea.a = c->ptr(c->plan.a);
+        ea.Qbuf = c->ptr(c->plan.Q); ea.Ybuf = c->ptr(c->plan.Y); ea.Zbuf = c->ptr(c->plan.Z);
         ea.ws = c->ptr<char>(c->plan.energy); ea.ws_bytes = c->plan.energy_bytes;
         ea.splitk = c->ptr<void>(c->plan.splitk); ea.splitk_bytes = c->plan.splitk_bytes;
         return energy_eval(ea, h_nn, h_nnn, J2, E, c->st);
@@ -886,6 +926,7 @@ int ctm_energy_grad(ctm_ctx* c, const double* h_nn, const double* h_nnn, double 
 int ctm_lnz_per_site(ctm_ctx* c, double* lnk) {
     if (!c || !lnk) return fail(c, CTM_EINVAL, "NULL argument");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         ClassicalArgs ca{};
         ca.Dab = c->sh.Dab; ca.chi = c->chi_cur;
         ca.C = c->C(); ca.T = c->T(); ca.a = c->ptr(c->plan.a);
@@ -897,6 +938,7 @@ int ctm_lnz_per_site(ctm_ctx* c, double* lnk) {
 int ctm_expect_site(ctm_ctx* c, const double* imp, double* v) {
     if (!c || !imp || !v) return fail(c, CTM_EINVAL, "NULL argument");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         ClassicalArgs ca{};
         ca.Dab = c->sh.Dab; ca.chi = c->chi_cur;
         ca.C = c->C(); ca.T = c->T(); ca.a = c->ptr(c->plan.a);
@@ -908,6 +950,7 @@ int ctm_expect_site(ctm_ctx* c, const double* imp, double* v) {
 int ctm_stats(ctm_ctx* c, ctm_stats_t* st) {
     if (!c || !st) return fail(c, CTM_EINVAL, "NULL argument");
     return guarded(c, [&]() -> Status {
+        QRCTM_TRY(join_aux(c));
         double r = NAN;
         QRCTM_HIP(hipMemcpyAsync(&r, c->small() + SL_RATIO, sizeof(double), hipMemcpyDeviceToHost,
                                  c->st));
@@ -928,8 +971,11 @@ int ctm_stats(ctm_ctx* c, ctm_stats_t* st) {
 int ctm_set_timing(ctm_ctx* c, int on) {
     if (!c) return fail(c, CTM_EINVAL, "NULL context");
     return guarded(c, [&]() -> Status {
-        if (on && !c->ev[0])
+        if (on && !c->ev[0]) {
             for (auto& e : c->ev) QRCTM_HIP(hipEventCreate(&e));
+            for (auto& e : c->ev_sp) QRCTM_HIP(hipEventCreate(&e));
+        }
+        QRCTM_TRY(join_aux(c));
         c->timing = on != 0;
         for (double& m : c->ms_phase) m = 0.0;
         c->timed_steps = 0;
@@ -954,8 +1000,20 @@ int ctm_qr(const double* M, double* Q, double* R, int m, int n, void* ws, size_t
     if (m < n || n < 1) return fail(nullptr, CTM_EINVAL, "need m >= n >= 1");
     return guarded(nullptr, [&]() -> Status {
         hipStream_t st = static_cast<hipStream_t>(stream);
-        QRCTM_TRY(qr_pos(M, Q, R, m, n, ws, ws_bytes, st, nullptr));
-        return sync(st);
+        const QrScratch L = qr_scratch_layout(m, n);
+        int* err = reinterpret_cast<int*>(static_cast<char*>(ws) + L.off_err);
+        if (ws_bytes >= L.total) QRCTM_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+        QRCTM_TRY(qr_pos(M, Q, R, m, n, ws, ws_bytes, st, nullptr, err));
+        int h = 0;
+        QRCTM_HIP(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, st));
+        QRCTM_TRY(sync(st));
+        if (h != 0) {
+            Status s;
+            s.code = CTM_EHIP;
+            s.msg = "qr: a grid barrier of the cooperative factorisation timed out";
+            return s;
+        }
+        return Status{};
     });
 }
 

@@ -7,6 +7,8 @@ namespace qrctm {
 struct EnergyArgs {
     int d, D, chi;
     const double *C, *T, *As;  // As: C4v-averaged, max-normalised site tensor
+    const double* a;           // double layer a[U][L][R][Dn] (next-nearest-neighbour term)
+    double *Qbuf, *Ybuf, *Zbuf;  // step buffers reused by the next-nearest-neighbour term
     char* ws;
     size_t ws_bytes;
     void* splitk;

@@ -12,13 +12,15 @@
 //   Left[w,s,s',R,v] = sum_{t,Dn} (...) T[t,Dn,v]     (bottom edge)
 //   rho[(s1 s1'),(s2 s2')] = sum Left[..,s1,s1',..] Left[..,s2,s2',..]
 // (the right half equals the left half by the mirror symmetry of the C4v
-// network).  Each contraction is one FP64 MFMA GEMM; the index reorders between
+// network).  The J1-J2 paragraph adds a diagonal pair from the 2x2 plaquette
+// (nnn_rho).  Each contraction is one FP64 MFMA GEMM; the index reorders between
 // them are HBM-bound permutes or are folded into the GEMM output map.
 //
 // Classical (Discussion paragraph: classical partition functions): ln kappa =
 // ln Z33 + ln Z22 - 2 ln Z32 and <O> = Z33(impurity) / Z33(a).
 #include "common.h"
 #include "energy.h"
+#include "step_gemms.h"
 #include "tensor_ops.h"
 
 namespace qrctm {
@@ -127,7 +129,7 @@ __global__ void bond_energy_kernel(const double* __restrict__ rho, const double*
 
 struct ELayout {
     size_t E1, F, E2, Yb, E3, E4, E4p, Left, Lp, Ak, rho, h, scal;
-    size_t Lpb, Leftb, E1b, Fb, Akb, rhob;
+    size_t Lpb, Leftb, E1b, Fb, Akb, rhob, rho2, red;
     size_t splitk, total;
     size_t splitk_bytes;
 };
@@ -152,7 +154,7 @@ ELayout e_layout(int d, int D, int chi) {
     L.Lp = take(c * dd * dd * D2 * c);
     L.Ak = take(dd * D4);
     L.rho = take(dd * dd * dd * dd);
-    L.h = take(dd * dd * dd * dd);
+    L.h = take(2 * dd * dd * dd * dd);
     L.scal = take(16);
     L.Lpb = take(c * dd * dd * D2 * c);
     L.Leftb = take(c * dd * dd * D2 * c);
@@ -160,6 +162,8 @@ ELayout e_layout(int d, int D, int chi) {
     L.Fb = take(c * D2 * c);
     L.Akb = take(dd * D4);
     L.rhob = take(dd * dd * dd * dd);
+    L.rho2 = take(dd * dd * dd * dd);
+    L.red = take(kRedBlocks);
     // split-K partials: the largest of the reductions over chi^2 D^2 or chi^2 d D^2
     size_t sk = 0;
     {
@@ -411,16 +415,94 @@ __global__ void rho_bar_kernel(const double* __restrict__ rho, const double* __r
         }
 }
 
+// a_open[U][L][R][Dn] = As[s,u,l,d,r] As[t,u',l',d',r'] (ket s, bra t)
+__global__ void open_layer_kernel(const double* __restrict__ As, int D, int s, int t, double* a) {
+    const long long D2 = (long long)D * D;
+    const long long n = D2 * D2 * D2 * D2;
+    const int D4 = D * D * D * D;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        long long rem = e;
+        const int Dn = (int)(rem % D2); rem /= D2;
+        const int R = (int)(rem % D2); rem /= D2;
+        const int L = (int)(rem % D2); rem /= D2;
+        const int U = (int)rem;
+        const int ik = (((U / D) * D + L / D) * D + Dn / D) * D + R / D;
+        const int ib = (((U % D) * D + L % D) * D + Dn % D) * D + R % D;
+        a[e] = As[(size_t)s * D4 + ik] * As[(size_t)t * D4 + ib];
+    }
+}
+
+__global__ void sym_square_kernel(const double* __restrict__ Z, long long n, double* out) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n * n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / n, j = e % n;
+        out[e] = 0.5 * (Z[e] + Z[j * n + i]);
+    }
+}
+
+// rho[(s1 s1'),(s2 s2')] of a diagonal (next-nearest-neighbour) pair from the
+// 2x2 plaquette (J1-J2 paragraph): the cyclic product of four enlarged
+// corners, two of them with the site open.  By C4v every enlarged corner is
+// the same symmetric matrix Cc, so rho = Tr(Co_{s1 s1'} Cc Co_{s2 s2'} Cc).
+// The enlarged corners are built with the step's own contractions (reduced
+// corner, 3a, 3b with the closed or the open double layer).
+Status nnn_rho(const EnergyArgs& ea, const ELayout& L, hipStream_t st) {
+    Status s;
+    const int d = ea.d, D = ea.D, chi = ea.chi, Dab = D * D;
+    const long long n = (long long)chi * Dab, nn = n * n, D8 = (long long)Dab * Dab * Dab * Dab;
+    if (nn < D8) {
+        s.code = -1;
+        s.msg = "energy: the next-nearest-neighbour term needs chi >= D^2";
+        return s;
+    }
+    char* b = ea.ws;
+    auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    void* sk = b + L.splitk;
+    const size_t skb = L.splitk_bytes;
+    StepPtrs sp{};
+    sp.C = ea.C; sp.T = ea.T; sp.a = ea.a;
+    sp.Q = ea.Qbuf; sp.Y = ea.Ybuf; sp.Z = ea.Zbuf;
+    QRCTM_TRY(gemm_f64(g_reduced_corner(sp, chi, Dab), sk, skb, st));
+    QRCTM_TRY(gemm_f64(g_edge_a(sp, sp.Q, chi, chi, Dab), sk, skb, st));
+    QRCTM_TRY(gemm_f64(g_edge_b(sp, chi, chi, Dab), sk, skb, st));
+    const int blocks = (int)std::min<long long>(ceil_div(nn, 256), 65536);
+    double* Cc = P(L.E2);
+    hipLaunchKernelGGL(sym_square_kernel, dim3(blocks), dim3(256), 0, st, sp.Z, n, Cc);
+    QRCTM_TRY(launch_check("sym_square_kernel"));
+    const int d2 = d * d;
+    double* aop = P(L.Yb);
+    for (int q = 0; q < d2; ++q) {
+        hipLaunchKernelGGL(open_layer_kernel, dim3((int)std::min<long long>(ceil_div(D8, 256), 65536)),
+                           dim3(256), 0, st, ea.As, D, q / d, q % d, aop);
+        QRCTM_TRY(launch_check("open_layer_kernel"));
+        StepPtrs so = sp;
+        so.a = aop;
+        so.Z = P(L.E3);
+        QRCTM_TRY(gemm_f64(g_edge_b(so, chi, chi, Dab), sk, skb, st));
+        hipLaunchKernelGGL(sym_square_kernel, dim3(blocks), dim3(256), 0, st, so.Z, n,
+                           P(L.E4) + (size_t)q * nn);
+        QRCTM_TRY(launch_check("sym_square_kernel"));
+    }
+    for (int q = 0; q < d2; ++q) {
+        GemmDesc g;  // X_q = Co_q Cc
+        g.M = n; g.N = n; g.K = n;
+        g.A = P(L.E4) + (size_t)q * nn; g.lda = n; g.B = Cc; g.ldb = n;
+        g.C = P(L.E4p) + (size_t)q * nn; g.map = OutMap::plain(n, n, n);
+        QRCTM_TRY(gemm_f64(g, sk, skb, st));
+    }
+    for (int q1 = 0; q1 < d2; ++q1)
+        for (int q2 = 0; q2 < d2; ++q2)
+            QRCTM_TRY(dot(P(L.E4p) + (size_t)q1 * nn, P(L.E4p) + (size_t)q2 * nn, nn, n, n, 1,
+                          P(L.red), P(L.rho2) + q1 * d2 + q2, st));
+    return s;
+}
+
 }  // namespace
 
 Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
                    double* E, hipStream_t st) {
     Status s;
-    if (h_nnn != nullptr && J2 != 0.0) {
-        s.code = -1;
-        s.msg = "energy: the next-nearest-neighbour term is not available in this build";
-        return s;
-    }
     const int d = ea.d;
     const ELayout L = e_layout(d, ea.D, ea.chi);
     if (ea.ws_bytes < L.total) {
@@ -430,11 +512,20 @@ Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn
     }
     char* b = ea.ws;
     auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    const int d4 = d * d * d * d;
     QRCTM_TRY(nn_rho_forward(ea, L, st));
-    QRCTM_HIP(hipMemcpyAsync(P(L.h), h_nn, sizeof(double) * d * d * d * d, hipMemcpyHostToDevice, st));
+    QRCTM_HIP(hipMemcpyAsync(P(L.h), h_nn, sizeof(double) * d4, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, 2.0,
                        P(L.scal), 0);
     QRCTM_TRY(launch_check("bond_energy_kernel"));
+    if (h_nnn != nullptr && J2 != 0.0) {
+        // 2 J2 <h_nnn>: two diagonal pairs per site
+        QRCTM_TRY(nnn_rho(ea, L, st));
+        QRCTM_HIP(hipMemcpyAsync(P(L.h) + d4, h_nnn, sizeof(double) * d4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, P(L.rho2), P(L.h) + d4, d,
+                           2.0 * J2, P(L.scal), 1);
+        QRCTM_TRY(launch_check("bond_energy_kernel"));
+    }
     double hv = NAN;
     QRCTM_HIP(hipMemcpyAsync(&hv, P(L.scal), sizeof(double), hipMemcpyDeviceToHost, st));
     QRCTM_HIP(hipStreamSynchronize(st));

@@ -1,4 +1,6 @@
-// FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64), gfx950.
+// GEMM on the CDNA4 matrix cores, gfx950: FP64 (v_mfma_f64_16x16x4_f64) or, for
+// the mixed-precision form, FP32 products with FP32 accumulation
+// (v_mfma_f32_16x16x4_f32) on FP64 operands converted while they are staged.
 //
 // Every contraction of the QR-CTMRG step is one call of this kernel: the index
 // permutations of the tensor network are absorbed into the operand strides
@@ -11,6 +13,10 @@
 // slab), stored k-major so that every MFMA operand fetch is 16 consecutive
 // doubles per quarter-wave.
 #include "common.h"
+
+#ifndef MMA_F32_ROW
+#define MMA_F32_ROW(r, q) (4 * (q) + (r))
+#endif
 
 namespace qrctm {
 namespace {
@@ -29,21 +35,45 @@ struct KArgs {
     int partial;       // 1: write raw sums to C + split*M*N (plain M x N)
 };
 
+// Matrix-core operation per compute type.  FP64: v_mfma_f64_16x16x4_f64; FP32:
+// v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation).  Operands are fed
+// as A[lane%16][lane/16] and B[lane/16][lane%16]; row_of(r, q) gives the row of
+// accumulator element r held by a lane of quarter q = lane/16 (measured lane
+// layouts on gfx950).
+template <class CT>
+struct Mma;
+template <>
+struct Mma<double> {
+    typedef dbl4 acc_t;
+    __device__ static acc_t run(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row_of(int r, int q) { return 4 * r + q; }
+};
+template <>
+struct Mma<float> {
+    typedef flt4 acc_t;
+    __device__ static acc_t run(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row_of(int r, int q) { return MMA_F32_ROW(r, q); }
+};
+
 __device__ __forceinline__ long long out_index(const OutMap& mp, long long m, long long n) {
     return (m / mp.mdiv) * mp.ms1 + (m % mp.mdiv) * mp.ms2 + (n / mp.ndiv) * mp.ns1 +
            (n % mp.ndiv) * mp.ns2;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KArgs p) {
+template <class CT, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs p) {
+    typedef typename Mma<CT>::acc_t acc_t;
     constexpr int NWN = BN / WN;
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     constexpr int FM = WM / 16, FN = WN / 16;
-    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;
-    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile/thread mismatch");
+    constexpr int LA = (BM * BK + NT - 1) / NT, LB = (BN * BK + NT - 1) / NT;
     constexpr int PAD = 2;  // doubles; breaks the power-of-two row stride
-    __shared__ double As[2][BK][BM + PAD];
-    __shared__ double Bs[2][BK][BN + PAD];
+    __shared__ CT As[2][BK][BM + PAD];
+    __shared__ CT Bs[2][BK][BN + PAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -64,7 +94,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
     const long long kbeg = (long long)blockIdx.y * p.kchunk;
     const long long kend = min(p.K, kbeg + p.kchunk);
 
-    double ra[LA], rb[LB];
+    CT ra[LA], rb[LB];
 
     // Out-of-range elements are loaded from a clamped (valid) address and
     // replaced by zero, so the loads carry no branches.
@@ -75,10 +105,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
             int mm, kk;
             if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
             const long long gm = m0 + mm, gk = k0 + kk;
-            const bool in = gm < p.M && gk < kend;
+            const bool in = (BM * BK % NT == 0 || e < BM * BK) && gm < p.M && gk < kend;
             const long long cm = in ? gm : 0, ck = in ? gk : kbeg;
             const double v = TA ? p.A[ck * p.lda + cm] : p.A[cm * p.lda + ck];
-            ra[i] = in ? v : 0.0;
+            ra[i] = in ? (CT)v : (CT)0;
         }
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
@@ -86,16 +116,17 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
             int nn, kk;
             if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
             const long long gn = n0 + nn, gk = k0 + kk;
-            const bool in = gn < p.N && gk < kend;
+            const bool in = (BN * BK % NT == 0 || e < BN * BK) && gn < p.N && gk < kend;
             const long long cn = in ? gn : 0, ck = in ? gk : kbeg;
             const double v = TB ? p.B[cn * p.ldb + ck] : p.B[ck * p.ldb + cn];
-            rb[i] = in ? v : 0.0;
+            rb[i] = in ? (CT)v : (CT)0;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int e = tid + i * NT;
+            if (BM * BK % NT != 0 && e >= BM * BK) break;
             int mm, kk;
             if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
             As[buf][kk][mm] = ra[i];
@@ -103,17 +134,18 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
             const int e = tid + i * NT;
+            if (BN * BK % NT != 0 && e >= BN * BK) break;
             int nn, kk;
             if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
             Bs[buf][kk][nn] = rb[i];
         }
     };
 
-    dbl4 acc[FM][FN];
+    acc_t acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     const int lrow = lane & 15;  // operand row/col within a 16-block
     const int lk = lane >> 4;    // k within a 4-slab
@@ -129,7 +161,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
         if (more) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
-            double af[FM], bf[FN];
+            CT af[FM], bf[FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i) af[i] = As[buf][kk * 4 + lk][wm * WM + i * 16 + lrow];
 #pragma unroll
@@ -138,16 +170,14 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = Mma<CT>::run(af[i], bf[j], acc[i][j]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
 
-    // epilogue: with A fed as A[lane%16][lane/16] and B as B[lane/16][lane%16],
-    // accumulator element r of a lane is D[4*r + lane/16][lane%16] (measured
-    // lane layout of v_mfma_f64_16x16x4_f64 on gfx950)
+    // epilogue: accumulator element r of a lane is D[row_of(r, lane/16)][lane%16]
     // Row and column offsets are computed once per accumulator row / column.
     const long long MN = p.M * p.N;
     long long noff[FN];
@@ -163,14 +193,14 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_f64_kernel(KA
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const long long m = m0 + wm * WM + i * 16 + 4 * r + lk;
+            const long long m = m0 + wm * WM + i * 16 + Mma<CT>::row_of(r, lk);
             if (m >= p.M) continue;
             const long long moff =
                 p.partial ? m * p.N : (m / p.map.mdiv) * p.map.ms1 + (m % p.map.mdiv) * p.map.ms2;
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 if (!nok[j]) continue;
-                const double v = acc[i][j][r];
+                const double v = (double)acc[i][j][r];
                 double* o = Cb + moff + noff[j];
                 if (p.partial) *o = v;
                 else *o = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *o;
@@ -193,19 +223,19 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits
     }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, class CT = double>
 void launch_cfg(const KArgs& a, int splits, hipStream_t st) {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     dim3 grid(a.tiles_m * a.tiles_n, splits);
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, TA, TB>), grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((gemm_kernel<CT, BM, BN, BK, WM, WN, TA, TB>), grid, dim3(NT), 0, st, a);
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, class CT>
 void launch_t(const KArgs& a, int ta, int tb, int splits, hipStream_t st) {
-    if (!ta && !tb) launch_cfg<BM, BN, BK, WM, WN, false, false>(a, splits, st);
-    else if (!ta && tb) launch_cfg<BM, BN, BK, WM, WN, false, true>(a, splits, st);
-    else if (ta && !tb) launch_cfg<BM, BN, BK, WM, WN, true, false>(a, splits, st);
-    else launch_cfg<BM, BN, BK, WM, WN, true, true>(a, splits, st);
+    if (!ta && !tb) launch_cfg<BM, BN, BK, WM, WN, false, false, CT>(a, splits, st);
+    else if (!ta && tb) launch_cfg<BM, BN, BK, WM, WN, false, true, CT>(a, splits, st);
+    else if (ta && !tb) launch_cfg<BM, BN, BK, WM, WN, true, false, CT>(a, splits, st);
+    else launch_cfg<BM, BN, BK, WM, WN, true, true, CT>(a, splits, st);
 }
 
 struct Plan {
@@ -282,9 +312,14 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
         a.C = g.C;
         a.partial = 0;
     }
-    if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32>(a, g.trans_a, g.trans_b, pl.splits, st);
-    else launch_t<64, 64, 16, 32, 32>(a, g.trans_a, g.trans_b, pl.splits, st);
-    QRCTM_TRY(launch_check("gemm_f64_kernel"));
+    if (g.prec == 1) {
+        if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32, float>(a, g.trans_a, g.trans_b, pl.splits, st);
+        else launch_t<64, 64, 16, 32, 32, float>(a, g.trans_a, g.trans_b, pl.splits, st);
+    } else {
+        if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32, double>(a, g.trans_a, g.trans_b, pl.splits, st);
+        else launch_t<64, 64, 16, 32, 32, double>(a, g.trans_a, g.trans_b, pl.splits, st);
+    }
+    QRCTM_TRY(launch_check("gemm_kernel"));
     if (pl.splits > 1) {
         const long long MN = g.M * g.N;
         const int blocks = (int)std::min<long long>(ceil_div(MN, 256), 4096);

@@ -4,34 +4,33 @@
 // reduced corner (QR-CTMRG paragraph, Fig. 1e).  The factorisation here is the
 // Householder one, organised for a machine with 256 compute units:
 //
-//  1. qr_factor_kernel (cooperative launch, one workgroup per compute unit):
-//     every workgroup keeps a contiguous block of rows of M in LDS for the
-//     whole factorisation.  Column j needs, over all rows below j, the sum of
-//     squares of column j and its dot products with every later column; each
-//     workgroup reduces its rows (wavefront-parallel over columns, LDS over
-//     row groups), publishes the partial sums, and after ONE grid barrier every
-//     workgroup combines them in a fixed order, forms the reflector and updates
-//     its own rows.  The reflector is generated with beta = +||x|| (the
+//  1. qr_factor_kernel (cooperative launch, at most one workgroup per compute
+//     unit): every workgroup keeps a contiguous block of rows of M in LDS for
+//     the whole factorisation, using as few workgroups as LDS allows.  Column j
+//     needs, over all rows below j, the sum of squares of column j and its dot
+//     products with every later column; each workgroup reduces its rows
+//     (wavefront-parallel over columns, LDS over row groups) in the same pass
+//     that applies the previous reflector, publishes the partial sums, and after
+//     ONE grid barrier (an atomic arrival counter) every workgroup combines
+//     them in a fixed order, forms the reflector and updates its own rows.  The reflector is generated with beta = +||x|| (the
 //     non-negative-diagonal variant, cancellation-free gamma = alpha - beta), so
 //     R has diag(R) >= 0 without a sign fix.
 //  2. the compact-WY factor T of H_0 ... H_{n-1} = I - V T V^T from the Gram
 //     matrix G = V^T V (an FP64 MFMA GEMM) and tau (qr_tfactor_kernel);
 //  3. the explicit thin factor Q = [I; 0] - V (T V1^T) by two more MFMA GEMMs
 //     (V1 = first n rows of V).
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.h"
 #include "qr.h"
-
-namespace cg = cooperative_groups;
 
 namespace qrctm {
 namespace {
 
-constexpr int kQrThreads = 256;
-constexpr int kColGroup = 64;  // columns handled in parallel by one row group
-constexpr int kRowGroups = kQrThreads / kColGroup;
-constexpr size_t kQrLdsBudget = 150 * 1024;
+constexpr int kQrThreads = 512;
+constexpr int kColGroup = 64;                      // column lanes of a row group
+constexpr int kRowGroups = kQrThreads / kColGroup;  // row groups
+constexpr int kMaxColsPerLane = 8;                  // n <= 512
+constexpr size_t kQrLdsBudget = 155 * 1024;
+constexpr unsigned kSpinLimit = 1u << 22;
 
 struct QrLayout {
     int P;   // workgroups
@@ -40,29 +39,78 @@ struct QrLayout {
 };
 
 size_t lds_for(int rb, int n) {
-    // row block + v (rb) + w (n) + row-group partials (kRowGroups x (n+1)) + scalars
-    return sizeof(double) * ((size_t)rb * n + rb + n + (size_t)kRowGroups * (n + 1) + 8);
+    // row block + v (rb) + w (n) + row j (n) + row-group partials + scalars
+    return sizeof(double) * ((size_t)rb * n + rb + 2 * (size_t)n + (size_t)kRowGroups * (n + 1) + 8);
 }
 
-// Partial sums of column jc over the rows of this block that lie strictly below jc:
-// slot 0 = sum x_i^2, slot 1 + (k - jc - 1) = sum x_i a_ik for k > jc.
-__device__ void column_partials(const double* Ab, int nr, int r0, int n, int jc, double* red,
-                                double* out) {
-    const int tid = threadIdx.x;
-    const int cg_ = tid % kColGroup, rg = tid / kColGroup;
-    const int nslots = n - jc;  // slot s: s == 0 -> column jc itself, else column jc + s
-    const int istart = max(0, jc + 1 - r0);
-    for (int s = cg_; s < nslots; s += kColGroup) {
-        const int k = jc + s;
-        double acc = 0.0;
-        for (int i = istart + rg; i < nr; i += kRowGroups) acc += Ab[i * n + jc] * Ab[i * n + k];
-        red[rg * (n + 1) + s] = acc;
+// Grid-wide barrier of a cooperative launch: every wave makes its global writes
+// visible at device scope, one thread per workgroup arrives on a counter and
+// waits for target arrivals.  The wait is bounded: on timeout *err is set and
+// the kernel runs to its end (the result is then discarded by the host).
+__device__ void grid_barrier(unsigned* cnt, unsigned target, int* err) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(cnt, 1u);
+        unsigned spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpinLimit) {
+                atomicOr(err, 2);
+                break;
+            }
+        }
     }
     __syncthreads();
-    for (int s = tid; s < nslots; s += kQrThreads) {
-        double acc = 0.0;
-        for (int g = 0; g < kRowGroups; ++g) acc += red[g * (n + 1) + s];
-        out[s] = acc;
+    __threadfence();
+}
+
+// Apply H_{jc-1} = I - t v w^T to the local rows below jc-1 (t == 0: no
+// update) and write the partial sums of column jc over the local rows strictly
+// below jc: slot 0 = sum x_i^2, slot s = sum x_i a_i,jc+s.  Column jc is updated
+// first (its new values are the next reflector's x); the other columns are
+// updated and accumulated in the same pass (64 column lanes x row groups).
+__device__ void update_and_partials(double* Ab, int nr, int r0, int n, int jc, double t,
+                                    const double* vloc, const double* wv, double* red,
+                                    double* out) {
+    const int tid = threadIdx.x, cl = tid % kColGroup, rg = tid / kColGroup;
+    const int iupd = max(0, jc - r0);  // first local row with global index > jc - 1
+    if (t != 0.0) {
+        const double wj = wv[jc];
+        for (int i = iupd + tid; i < nr; i += kQrThreads) Ab[i * n + jc] -= t * vloc[i] * wj;
+    }
+    __syncthreads();
+    const int nsl = n - jc;
+    const int ncl = (nsl + kColGroup - 1) / kColGroup;
+    double acc[kMaxColsPerLane];
+#pragma unroll
+    for (int c = 0; c < kMaxColsPerLane; ++c) acc[c] = 0.0;
+    for (int i = iupd + rg; i < nr; i += kRowGroups) {
+        double* row = Ab + i * n;
+        const double x = (r0 + i > jc) ? row[jc] : 0.0;
+        const double tv = t * vloc[i];
+#pragma unroll
+        for (int c = 0; c < kMaxColsPerLane; ++c) {
+            const int s = cl + kColGroup * c;
+            if (c < ncl && s < nsl) {
+                double a = row[jc + s];
+                if (s > 0 && t != 0.0) {
+                    a -= tv * wv[jc + s];
+                    row[jc + s] = a;
+                }
+                acc[c] += x * a;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxColsPerLane; ++c) {
+        const int s = cl + kColGroup * c;
+        if (c < ncl && s < nsl) red[rg * (n + 1) + s] = acc[c];
+    }
+    __syncthreads();
+    for (int s = tid; s < nsl; s += kQrThreads) {
+        double a = 0.0;
+        for (int g = 0; g < kRowGroups; ++g) a += red[g * (n + 1) + s];
+        out[s] = a;
     }
     __syncthreads();
 }
@@ -70,16 +118,17 @@ __device__ void column_partials(const double* Ab, int nr, int r0, int n, int jc,
 __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __restrict__ M, int m,
                                                                int n, int rb, double* V, double* R,
                                                                double* tau, double* part,
-                                                               double* rowbuf) {
+                                                               double* rowbuf, unsigned* cnt,
+                                                               int* err) {
     extern __shared__ double lds[];
-    cg::grid_group grid = cg::this_grid();
     const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
     const int r0 = p * rb;
     const int nr = max(0, min(rb, m - r0));
     double* Ab = lds;
     double* vloc = Ab + (size_t)rb * n;
     double* wv = vloc + rb;
-    double* red = wv + n;
+    double* rowj = wv + n;
+    double* red = rowj + n;
     double* sc = red + kRowGroups * (n + 1);
     const size_t pstride = (size_t)P * (n + 1);
 
@@ -87,25 +136,24 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
     __syncthreads();
 
     // column 0 partials and row 0
-    column_partials(Ab, nr, r0, n, 0, red, part + (size_t)p * (n + 1));
+    update_and_partials(Ab, nr, r0, n, 0, 0.0, vloc, wv, red, part + (size_t)p * (n + 1));
     if (r0 <= 0 && 0 < r0 + nr)
-        for (int k = tid; k < n; k += kQrThreads) rowbuf[k] = Ab[(0 - r0) * n + k];
+        for (int k = tid; k < n; k += kQrThreads) rowbuf[k] = Ab[k];
 
     for (int j = 0; j < n; ++j) {
-        grid.sync();
+        grid_barrier(cnt, (unsigned)(j + 1) * (unsigned)P, err);
         const double* pp = part + (size_t)(j & 1) * pstride;
         const double* row = rowbuf + (size_t)(j & 1) * n;
         const int nslots = n - j;
-        // combine partials in a fixed order (deterministic): 64 slot lanes x 4
-        // workgroup groups, four independent running sums per thread so that
-        // many loads are in flight, then the 4 groups through LDS.
+        // combine partials in a fixed order: 64 slot lanes x 8 workgroup groups,
+        // four independent running sums, then the groups through LDS
         {
             const int sl = tid % kColGroup, qg = tid / kColGroup;
             for (int s0 = 0; s0 < nslots; s0 += kColGroup) {
                 const int sidx = s0 + sl;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 if (sidx < nslots) {
                     const double* col = pp + sidx;
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                     int q = qg;
                     for (; q + 3 * kRowGroups < P; q += 4 * kRowGroups) {
                         a0 += col[(size_t)q * (n + 1)];
@@ -117,14 +165,17 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
                     red[qg * (n + 1) + sidx] = (a0 + a1) + (a2 + a3);
                 }
             }
+            for (int k = j + tid; k < n; k += kQrThreads) rowj[k] = row[k];
             __syncthreads();
-            for (int sidx = tid; sidx < nslots; sidx += kQrThreads)
-                wv[j + sidx] = (red[sidx] + red[(n + 1) + sidx]) +
-                               (red[2 * (n + 1) + sidx] + red[3 * (n + 1) + sidx]);
-            __syncthreads();  // red is reused by column_partials below
+            for (int sidx = tid; sidx < nslots; sidx += kQrThreads) {
+                double a = 0.0;
+                for (int g = 0; g < kRowGroups; ++g) a += red[g * (n + 1) + sidx];
+                wv[j + sidx] = a;  // wv[j] = sigma^2, wv[k] = x^T a_k over rows > j
+            }
+            __syncthreads();
         }
         if (tid == 0) {
-            const double alpha = row[j];
+            const double alpha = rowj[j];
             const double sigma2 = wv[j];
             double beta, t, gamma;
             int mode;  // 0: H = I, 1: sign flip e_j, 2: general reflector
@@ -137,32 +188,15 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
                 gamma = alpha <= 0.0 ? alpha - beta : -sigma2 / (alpha + beta);
                 t = -gamma / beta;
             }
-            sc[0] = beta; sc[1] = t; sc[2] = gamma; sc[3] = (double)mode; sc[4] = alpha;
+            sc[0] = beta; sc[1] = t; sc[2] = gamma; sc[3] = (double)mode;
         }
         __syncthreads();
-        const double beta = sc[0], t = sc[1], gamma = sc[2], alpha = sc[4];
+        const double beta = sc[0], t = sc[1], gamma = sc[2];
         const int mode = (int)sc[3];
         // w_k = v^T a_k over rows >= j (v_j = 1)
-        for (int k = j + 1 + tid; k < n; k += kQrThreads) {
-            const double ajk = row[k];
-            double w;
-            if (mode == 2) w = wv[k] / gamma + ajk;
-            else w = ajk;  // v = e_j
-            wv[k] = w;
-        }
-        (void)alpha;
-        __syncthreads();
-        if (p == 0) {
-            for (int k = tid; k < n; k += kQrThreads) {
-                double r;
-                if (k < j) r = 0.0;
-                else if (k == j) r = beta;
-                else r = row[k] - t * wv[k];
-                R[(size_t)j * n + k] = r;
-            }
-            if (tid == 0) tau[j] = t;
-        }
-        // v for local rows
+        for (int k = j + 1 + tid; k < n; k += kQrThreads)
+            wv[k] = (mode == 2) ? wv[k] / gamma + rowj[k] : rowj[k];
+        // v for the local rows
         for (int i = tid; i < nr; i += kQrThreads) {
             const int gi = r0 + i;
             double v;
@@ -173,28 +207,30 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
             V[(size_t)gi * n + j] = v;
         }
         __syncthreads();
-        // apply H_j to the local rows strictly below j (row j is R's row):
-        // 64 column lanes x 4 row groups, no index division
-        if (mode != 0) {
-            const int istart = max(0, j + 1 - r0);
-            const int cl = tid % kColGroup, rg = tid / kColGroup;
-            for (int i = istart + rg; i < nr; i += kRowGroups) {
-                const double tv = t * vloc[i];
-                double* row_i = Ab + i * n;
-                for (int k = j + 1 + cl; k < n; k += kColGroup) row_i[k] -= tv * wv[k];
+        if (p == 0) {
+            for (int k = tid; k < n; k += kQrThreads) {
+                double r;
+                if (k < j) r = 0.0;
+                else if (k == j) r = beta;
+                else r = rowj[k] - t * wv[k];
+                R[(size_t)j * n + k] = r;
             }
+            if (tid == 0) tau[j] = t;
         }
-        __syncthreads();
         if (j + 1 < n) {
-            column_partials(Ab, nr, r0, n, j + 1, red,
-                            part + (size_t)((j + 1) & 1) * pstride + (size_t)p * (n + 1));
-            // publish row j+1 (already final in columns > j)
+            update_and_partials(Ab, nr, r0, n, j + 1, t, vloc, wv, red,
+                                part + (size_t)((j + 1) & 1) * pstride + (size_t)p * (n + 1));
+            // publish row j+1 (final in columns > j)
             if (r0 <= j + 1 && j + 1 < r0 + nr) {
                 double* nrow = rowbuf + (size_t)((j + 1) & 1) * n;
                 for (int k = tid; k < n; k += kQrThreads) nrow[k] = Ab[(j + 1 - r0) * n + k];
             }
         }
     }
+}
+
+__global__ void zero_counter_kernel(unsigned* cnt) {
+    if (threadIdx.x == 0) *cnt = 0u;
 }
 
 // T[i][j] (i <= j): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j]
@@ -266,13 +302,14 @@ __global__ void eye_kernel(double* Q, long long m, int n) {
 
 QrLayout plan_qr(int m, int n) {
     QrLayout L{};
-    // fewest workgroups whose row blocks fit in LDS (fewer partial sums to combine)
-    int P = 1;
-    while (P < 256 && lds_for((int)ceil_div(m, P), n) > kQrLdsBudget) P *= 2;
-    // at most 128 rows per workgroup to spread the O(m n^2) updates
-    while (P < 256 && ceil_div(m, P) > 128) P *= 2;
-    if (P > 256) P = 256;
-    L.P = P;
+    // fewest workgroups whose row blocks fit in LDS: fewer partial sums to
+    // combine and a cheaper grid barrier
+    const size_t fixed = lds_for(0, n);
+    const size_t per_row = sizeof(double) * (size_t)(n + 1);
+    long long rb_max = fixed < kQrLdsBudget ? (long long)((kQrLdsBudget - fixed) / per_row) : 0;
+    if (rb_max < 1) rb_max = 1;
+    long long P = ceil_div(m, rb_max);
+    if (P < 1) P = 1;
     L.rb = (int)ceil_div(m, P);
     L.P = (int)ceil_div(m, L.rb);
     L.lds_bytes = lds_for(L.rb, n);
@@ -298,6 +335,8 @@ QrScratch qr_scratch_layout(int m, int n) {
     s.off_T = take((size_t)n * n);
     s.off_MT = take((size_t)n * n);
     s.off_ratio = take(1);
+    s.off_cnt = take(1);
+    s.off_err = take(1);
     GemmDesc gg;
     gg.M = n; gg.N = n; gg.K = m;
     const size_t sk = gemm_splitk_bytes(gg);
@@ -308,17 +347,17 @@ QrScratch qr_scratch_layout(int m, int n) {
 }
 
 bool qr_fits(int m, int n) {
-    if (m < n || n < 1) return false;
+    if (m < n || n < 1 || n > kTMaxN) return false;
     const QrLayout L = plan_qr(m, n);
-    return L.lds_bytes <= kQrLdsBudget + 8192 && n <= kTMaxN;
+    return L.lds_bytes <= kQrLdsBudget && L.P <= 256;
 }
 
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
-              hipStream_t st, double* diag_ratio_dev) {
+              hipStream_t st, double* diag_ratio_dev, int* err_dev) {
     Status s;
     if (!qr_fits(m, n)) {
         s.code = -1;
-        s.msg = "qr: shape not supported (need m >= n, n <= 512, row blocks within LDS)";
+        s.msg = "qr: shape not supported (need m >= n, n <= 512, at most 256 row blocks in LDS)";
         return s;
     }
     const QrScratch L = qr_scratch_layout(m, n);
@@ -339,6 +378,8 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     void* sk = base + L.off_splitk;
 
     const QrLayout ql = plan_qr(m, n);
+    unsigned* cnt = reinterpret_cast<unsigned*>(base + L.off_cnt);
+    int* err = err_dev ? err_dev : reinterpret_cast<int*>(base + L.off_err);
     {
         int dev = 0;
         QRCTM_HIP(hipGetDevice(&dev));
@@ -355,10 +396,13 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
             s.msg = "qr: cooperative grid does not fit on the device";
             return s;
         }
+        hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, st, cnt);
+        QRCTM_TRY(launch_check("zero_counter_kernel"));
         const double* Mp = M;
         int mm = m, nn = n, rbb = ql.rb;
-        void* args[] = {(void*)&Mp, (void*)&mm, (void*)&nn, (void*)&rbb, (void*)&V,
-                        (void*)&R,  (void*)&tau, (void*)&part, (void*)&rowbuf};
+        void* args[] = {(void*)&Mp,  (void*)&mm,   (void*)&nn,     (void*)&rbb,
+                        (void*)&V,   (void*)&R,    (void*)&tau,    (void*)&part,
+                        (void*)&rowbuf, (void*)&cnt, (void*)&err};
         QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_factor_kernel, dim3(ql.P),
                                              dim3(kQrThreads), args, ql.lds_bytes, st));
     }

@@ -104,22 +104,40 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
         for (int i = t; i < m; i += kSpecThreads) v[i] = (i == 0) ? 1.0 : A.get(k + 1 + i, k) * scal;
         if (t == 0) ee[k] = beta;
         __syncthreads();
-        // p = tau * A22 v  (A22 symmetric; the global store reads column i as row i)
-        for (int i = t; i < m; i += kSpecThreads) {
-            double acc = 0.0;
-            for (int jx = 0; jx < m; ++jx) acc += A.get(k + 1 + jx, k + 1 + i) * v[jx];
-            p[i] = tau * acc;
+        // p = tau * A22 v (A22 symmetric; the global store reads column i as row i):
+        // row i is split into nc chunks handled by different threads, the
+        // chunk sums are combined through LDS in a fixed order
+        {
+            const int nc = max(1, min(kSpecThreads / m, 32));
+            const int len = (m + nc - 1) / nc;
+            const int i = t % m, c = t / m;
+            if (c < nc) {
+                const int j0 = c * len, j1 = min(m, j0 + len);
+                double acc = 0.0;
+                for (int jx = j0; jx < j1; ++jx) acc += A.get(k + 1 + jx, k + 1 + i) * v[jx];
+                red[c * m + i] = acc;
+            }
+            __syncthreads();
+            for (int ii = t; ii < m; ii += kSpecThreads) {
+                double acc = 0.0;
+                for (int cc = 0; cc < nc; ++cc) acc += red[cc * m + ii];
+                p[ii] = tau * acc;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         double pv = 0.0;
         for (int i = t; i < m; i += kSpecThreads) pv += p[i] * v[i];
         const double K = 0.5 * tau * block_sum(pv, red);
         for (int i = t; i < m; i += kSpecThreads) p[i] -= K * v[i];  // w
         __syncthreads();
-        for (long long q = t; q < (long long)m * m; q += kSpecThreads) {
-            const int i = (int)(q / m), jx = (int)(q % m);
-            if (Store::kBothTriangles || i >= jx)
-                A.sub(k + 1 + i, k + 1 + jx, v[i] * p[jx] + p[i] * v[jx]);
+        {   // rank-2 update, 32 column lanes x 32 row groups
+            const int cl = t % 32, rg = t / 32;
+            for (int i = rg; i < m; i += kSpecThreads / 32) {
+                const int jend = Store::kBothTriangles ? m : i + 1;
+                const double vi = v[i], pi = p[i];
+                for (int jx = cl; jx < jend; jx += 32)
+                    A.sub(k + 1 + i, k + 1 + jx, vi * p[jx] + pi * v[jx]);
+            }
         }
         __syncthreads();
     }

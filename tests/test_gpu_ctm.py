@@ -153,3 +153,20 @@ def test_nonfinite_tensor_is_reported():
     with pytest.raises(P.CTMError) as e:
         P.Context(_dev(A), 16)
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("d,D,chi", [(2, 2, 16), (2, 3, 27)])
+def test_j1j2_energy_matches_oracle(d, D, chi):
+    A, As, a, C, T = _oracle_setup(d, D, chi, seed=3)
+    for _ in range(3):
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+    ctx = P.Context(_dev(A), chi, n_warmup=0)
+    ctx.set_env(_dev(C), _dev(T))
+    h1, h2, J2 = inp.heisenberg_bond_rotated(), inp.heisenberg_bond(), 0.5
+    e_ref = obs.energy_j1j2(C, T, As, h1, h2, J2)
+    e = ctx.energy(h1, h2, J2)
+    assert abs(e - e_ref) < 1e-12 * abs(e_ref)
+    # the NNN term alone (J2 only, through the difference with the NN energy)
+    e_nn = ctx.energy(h1)
+    assert abs((e - e_nn) - 2 * J2 * obs.bond_expectation(obs.rdm_nnn(C, T, As), h2)) < 1e-12
+    ctx.close()
