@@ -239,7 +239,8 @@ void launch_t(const KArgs& a, int ta, int tb, int splits, hipStream_t st) {
 }
 
 struct Plan {
-    int cfg;      // 0: 128x128 (8 waves of 64x32), 1: 64x64 (4 waves of 32x32)
+    int cfg;  // 0: 128x128 (8 waves of 64x32); 1: 64x64 (8 waves of 32x16);
+              // 2: 128x48 (12 waves of 32x16) for skinny N
     int bm, bn;
     int splits;
     long long kchunk;
@@ -247,11 +248,15 @@ struct Plan {
 
 constexpr int kTargetBlocks = 512;
 
+// Tile choice measured on the step's shapes: large M and N take 128x128; a
+// skinny N (the edge contraction 3c, N = chi) takes 128x48 tiles with split-K;
+// everything else 64x64.  Split-K brings small grids to about 2 blocks per CU.
 Plan make_plan(const GemmDesc& g) {
     Plan pl{};
-    const long long t128 = ceil_div(g.M, 128) * ceil_div(g.N, 128);
-    if (t128 >= 256) {
+    if (ceil_div(g.M, 128) * ceil_div(g.N, 128) >= 256) {
         pl.cfg = 0; pl.bm = 128; pl.bn = 128;
+    } else if (g.N <= 256 && g.M >= 1024) {
+        pl.cfg = 2; pl.bm = 128; pl.bn = 48;
     } else {
         pl.cfg = 1; pl.bm = 64; pl.bn = 64;
     }
@@ -259,7 +264,7 @@ Plan make_plan(const GemmDesc& g) {
     pl.splits = 1;
     pl.kchunk = g.K > 0 ? g.K : 1;
     if (tiles < kTargetBlocks / 2 && g.K >= 512) {
-        long long s = kTargetBlocks / tiles;
+        long long s = ceil_div(kTargetBlocks, tiles);
         const long long max_s = g.K / 256;  // keep >= 256 of K per split
         if (s > max_s) s = max_s;
         if (s > 64) s = 64;
@@ -314,10 +319,12 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
     }
     if (g.prec == 1) {
         if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32, float>(a, g.trans_a, g.trans_b, pl.splits, st);
-        else launch_t<64, 64, 16, 32, 32, float>(a, g.trans_a, g.trans_b, pl.splits, st);
+        else if (pl.cfg == 2) launch_t<128, 48, 16, 32, 16, float>(a, g.trans_a, g.trans_b, pl.splits, st);
+        else launch_t<64, 64, 16, 32, 16, float>(a, g.trans_a, g.trans_b, pl.splits, st);
     } else {
         if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32, double>(a, g.trans_a, g.trans_b, pl.splits, st);
-        else launch_t<64, 64, 16, 32, 32, double>(a, g.trans_a, g.trans_b, pl.splits, st);
+        else if (pl.cfg == 2) launch_t<128, 48, 16, 32, 16, double>(a, g.trans_a, g.trans_b, pl.splits, st);
+        else launch_t<64, 64, 16, 32, 16, double>(a, g.trans_a, g.trans_b, pl.splits, st);
     }
     QRCTM_TRY(launch_check("gemm_kernel"));
     if (pl.splits > 1) {

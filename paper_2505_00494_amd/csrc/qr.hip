@@ -43,25 +43,26 @@ size_t lds_for(int rb, int n) {
     return sizeof(double) * ((size_t)rb * n + rb + 2 * (size_t)n + (size_t)kRowGroups * (n + 1) + 8);
 }
 
-// Grid-wide barrier of a cooperative launch: every wave makes its global writes
-// visible at device scope, one thread per workgroup arrives on a counter and
-// waits for target arrivals.  The wait is bounded: on timeout *err is set and
-// the kernel runs to its end (the result is then discarded by the host).
+// Grid-wide barrier of a cooperative launch.  After a workgroup barrier, one
+// thread per workgroup arrives on a counter with release semantics (one L2
+// write-back for the whole workgroup), polls it with relaxed loads, and
+// issues a single acquire fence once target arrivals are seen.  The wait is
+// bounded: on timeout *err is set and the kernel runs to its end (the result is
+// then discarded by the host).
 __device__ void grid_barrier(unsigned* cnt, unsigned target, int* err) {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(cnt, 1u);
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (++spins > kSpinLimit) {
                 atomicOr(err, 2);
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __threadfence();
 }
 
 // Apply H_{jc-1} = I - t v w^T to the local rows below jc-1 (t == 0: no
