@@ -37,9 +37,64 @@ if ROOT not in sys.path:
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
+# Sources whose change makes a stored traffic measurement of the 3b GEMM stale:
+# the GEMM kernel and its tile plans, and the operand maps of the step.
+TRAFFIC_SOURCES = ("paper_2505_00494_amd/csrc/gemm.hip", "paper_2505_00494_amd/csrc/common.h",
+                   "paper_2505_00494_amd/csrc/step_gemms.h")
+
 
 def flops_3b(chi: int, D: int) -> float:
     return 2.0 * chi * chi * float(D) ** 8
+
+
+def traffic_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(d, D, chi):
+    """HBM bytes per launch of the 3b GEMM from the committed counter summary.
+
+    The summary (profiles/gemm_3b_traffic_d{d}_D{D}_chi{chi}.md) holds the
+    FETCH_SIZE and WRITE_SIZE readings per dispatch, each already scaled by
+    what the same counter reads for a plain copy of known size, and the hash
+    of the kernel sources they were taken with.  Returns None when there is no
+    summary or the kernel has changed since.
+    """
+    path = os.path.join(ROOT, "profiles", f"gemm_3b_traffic_d{d}_D{D}_chi{chi}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            m = line.strip().lstrip("-* ").split(":", 1)
+            if len(m) == 2:
+                vals[m[0].strip()] = m[1].strip().strip("`")
+    try:
+        if vals["kernel_source_sha256"] != traffic_source_hash():
+            return None
+        return {"bytes": float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]),
+                "fetch_bytes": float(vals["fetch_bytes_per_launch"]),
+                "write_bytes": float(vals["write_bytes_per_launch"]),
+                "algorithmic_bytes": float(vals["algorithmic_bytes_per_launch"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib: int):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)      # one elementwise kernel: reads n bytes, writes n bytes
+    torch.cuda.synchronize()
+    print(f"# copy calibration: 3 elementwise copies of {n} bytes", file=sys.stderr, flush=True)
 
 
 def cpu_baseline(d, D, chi, seed, budget_s=20.0):
@@ -87,6 +142,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--acc-steps", type=int, default=20)
     ap.add_argument("--k", type=int, default=10, help="tracked steps of the gradient")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -127,6 +184,7 @@ def main():
     ms = {k: v / st2["timed_steps"] for k, v in st2["ms_phase"].items()}
     ms_3b = ms["edge_3b"]
     achieved = flops_3b(chi, D) / (ms_3b * 1e-3) / 1e12
+    traffic = measured_traffic(d, D, chi)
 
     out = {
         "metric": f"QR-CTMRG steps/s (d={d}, D={D}, chi={chi}, FP64)",
@@ -151,7 +209,8 @@ def main():
         "ms_per_phase": ms,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "double-layer contraction Z = Y a (3b)",
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "kernel": "double-layer contraction Z = Y a (3b)",
                      "flops_per_launch": flops_3b(chi, D), "ms_per_launch": ms_3b},
     }
     # mixed form: same tensor, bulk contractions on FP32 matrix cores
@@ -204,6 +263,10 @@ def main():
                        "energy": e, "grad_norm": float(g.norm())}
         gctx.close()
     ctx.close()
+    if traffic:
+        out["roofline"]["traffic_detail"] = traffic
+    if args.calibrate_copy:
+        copy_calibration(args.calibrate_copy)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(d, D, chi, args.seed, args.cpu_budget)
