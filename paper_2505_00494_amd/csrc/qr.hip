@@ -1,24 +1,35 @@
 // Thin Householder QR of a tall matrix M (m x n, m >= n) with diag(R) >= 0.
 //
 // QR-CTMRG replaces the eigen/SVD decomposition by an unpivoted QR of the
-// reduced corner (QR-CTMRG paragraph, Fig. 1e).  The factorisation here is the
-// Householder one, organised for a machine with 256 compute units:
+// reduced corner (QR-CTMRG paragraph, Fig. 1e).  The factorisation here is a
+// blocked Householder QR organised for a machine with 256 compute units, all
+// in ONE cooperative kernel:
 //
-//  1. qr_factor_kernel (cooperative launch, at most one workgroup per compute
-//     unit): every workgroup keeps a contiguous block of rows of M in LDS for
-//     the whole factorisation, using as few workgroups as LDS allows.  Column j
-//     needs, over all rows below j, the sum of squares of column j and its dot
-//     products with every later column; each workgroup reduces its rows
-//     (wavefront-parallel over columns, LDS over row groups) in the same pass
-//     that applies the previous reflector, publishes the partial sums, and after
-//     ONE grid barrier (an atomic arrival counter) every workgroup combines
-//     them in a fixed order, forms the reflector and updates its own rows.  The reflector is generated with beta = +||x|| (the
-//     non-negative-diagonal variant, cancellation-free gamma = alpha - beta), so
-//     R has diag(R) >= 0 without a sign fix.
-//  2. the compact-WY factor T of H_0 ... H_{n-1} = I - V T V^T from the Gram
-//     matrix G = V^T V (an FP64 MFMA GEMM) and tau (qr_tfactor_kernel);
-//  3. the explicit thin factor Q = [I; 0] - V (T V1^T) by two more MFMA GEMMs
-//     (V1 = first n rows of V).
+//  * rows are dealt cyclically to P workgroups (row g to workgroup g mod P), so
+//    every workgroup keeps the same number of active rows as the elimination
+//    moves down; each workgroup's rows live in a private working copy in HBM,
+//    touched by no other workgroup;
+//  * the columns are taken in panels of 16.  For column j of a panel every
+//    workgroup reduces, over its rows below j, the squared norm of column j and
+//    its dot products with the later panel columns, publishes these 16 partial
+//    sums and arrives on a per-workgroup flag; after seeing every flag, all
+//    workgroups combine the partial sums in one fixed order (bitwise identical
+//    everywhere), form the reflector with beta = +||x|| (the non-negative
+//    diagonal variant, cancellation-free gamma) and update the panel rows they
+//    hold in LDS.  One flag barrier per column, and it carries 16 numbers per
+//    workgroup, not n - j;
+//  * after a panel, the trailing columns get the panel's reflectors in compact
+//    WY form, I - V T V^T: V^T [V | A_trail] is reduced over all rows (FP64
+//    matrix-core tiles per workgroup, then a reduction of the partial products
+//    spread over the workgroups, two flag barriers), T follows from V^T V and
+//    the tau's by the forward recurrence, and A_trail -= V (T^T (V^T A_trail))
+//    is a matrix-core update of each workgroup's own rows;
+//  * the explicit thin factor Q = H_0 ... H_{n-1} [I; 0] is formed in the same
+//    kernel by applying the panels in reverse order to [I; 0], with the same
+//    reduction pattern.
+//
+// The reflectors are the textbook ones (column by column, in order), so R and Q
+// agree with any other Householder QR with diag(R) >= 0 up to rounding.
 #include "common.h"
 #include "qr.h"
 
@@ -26,38 +37,61 @@ namespace qrctm {
 namespace {
 
 constexpr int kQrThreads = 512;
-constexpr int kColGroup = 64;                      // column lanes of a row group
-constexpr int kRowGroups = kQrThreads / kColGroup;  // row groups
-constexpr int kMaxColsPerLane = 8;                  // n <= 512
-constexpr size_t kQrLdsBudget = 155 * 1024;
+constexpr int kWaves = kQrThreads / 64;
+constexpr int kPb = 16;                        // panel width (one MFMA tile)
+constexpr int kRowGroups = kQrThreads / kPb;   // 32 row groups x 16 column lanes
+constexpr int kRowsPerWg = 64;                 // target rows per workgroup
+constexpr int kMaxWg = 256;
+constexpr int kMaxN = 512;
+constexpr int kFlagStride = 32;                // one 128-byte line per flag
 constexpr unsigned kSpinLimit = 1u << 22;
+constexpr size_t kQrLdsBudget = 150 * 1024;
 
-struct QrLayout {
+struct QrPlan {
     int P;   // workgroups
-    int rb;  // rows per workgroup
+    int rb;  // rows held by workgroup 0 (the most)
     size_t lds_bytes;
 };
 
-size_t lds_for(int rb, int n) {
-    // row block + v (rb) + w (n) + row j (n) + row-group partials + scalars
-    return sizeof(double) * ((size_t)rb * n + rb + 2 * (size_t)n + (size_t)kRowGroups * (n + 1) + 8);
+size_t lds_doubles(int rb, int n) {
+    // panel rows + Y (16 x n) + G, T (16 x 16 each) + reduction scratch
+    // (32 x 16) + w, pivot row (16 each) + tau (n) + scalars
+    return (size_t)rb * kPb + (size_t)kPb * n + 2 * kPb * kPb + kRowGroups * kPb + 2 * kPb +
+           (size_t)n + 8;
 }
 
-// Grid-wide barrier of a cooperative launch.  After a workgroup barrier, one
-// thread per workgroup arrives on a counter with release semantics (one L2
-// write-back for the whole workgroup), polls it with relaxed loads, and
-// issues a single acquire fence once target arrivals are seen.  The wait is
-// bounded: on timeout *err is set and the kernel runs to its end (the result is
-// then discarded by the host).
-__device__ void grid_barrier(unsigned* cnt, unsigned target, int* err) {
+QrPlan plan_qr(int m, int n) {
+    QrPlan L{};
+    long long P = ceil_div(m, kRowsPerWg);
+    if (P > kMaxWg) P = kMaxWg;
+    if (P < 1) P = 1;
+    L.P = (int)P;
+    L.rb = (int)ceil_div(m, P);
+    L.lds_bytes = sizeof(double) * lds_doubles(L.rb, n);
+    return L;
+}
+
+// Grid-wide barrier of the cooperative launch on per-workgroup flags.  After a
+// workgroup barrier, thread 0 stores the epoch into its own flag with release
+// semantics; the first wave polls all P flags (lane q the flags q, q+64, ...)
+// with relaxed loads until each holds at least the epoch, then issues one
+// acquire fence.  No location is written by two workgroups.  The wait is
+// bounded: on timeout *err is set and the kernel runs to its end (the host then
+// discards the result).
+__device__ void flag_barrier(unsigned* flags, int P, unsigned epoch, int* err) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > kSpinLimit) {
-                atomicOr(err, 2);
-                break;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flags + (size_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {
+        for (int q = threadIdx.x; q < P; q += 64) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(flags + (size_t)q * kFlagStride, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(err, 2);
+                    break;
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -65,121 +99,253 @@ __device__ void grid_barrier(unsigned* cnt, unsigned target, int* err) {
     __syncthreads();
 }
 
-// Apply H_{jc-1} = I - t v w^T to the local rows below jc-1 (t == 0: no
-// update) and write the partial sums of column jc over the local rows strictly
-// below jc: slot 0 = sum x_i^2, slot s = sum x_i a_i,jc+s.  Column jc is updated
-// first (its new values are the next reflector's x); the other columns are
-// updated and accumulated in the same pass (64 column lanes x row groups).
-__device__ void update_and_partials(double* Ab, int nr, int r0, int n, int jc, double t,
-                                    const double* vloc, const double* wv, double* red,
-                                    double* out) {
-    const int tid = threadIdx.x, cl = tid % kColGroup, rg = tid / kColGroup;
-    const int iupd = max(0, jc - r0);  // first local row with global index > jc - 1
-    if (t != 0.0) {
-        const double wj = wv[jc];
-        for (int i = iupd + tid; i < nr; i += kQrThreads) Ab[i * n + jc] -= t * vloc[i] * wj;
+// Everything a workgroup needs to address its rows.
+struct Rows {
+    int p, P, nr;  // workgroup, workgroups, rows held (local i <-> global p + i P)
+    __device__ int global(int i) const { return p + i * P; }
+    // first local row with global index >= g
+    __device__ int first_at_or_after(int g) const {
+        if (g <= p) return 0;
+        return (g - p + P - 1) / P;
     }
-    __syncthreads();
-    const int nsl = n - jc;
-    const int ncl = (nsl + kColGroup - 1) / kColGroup;
-    double acc[kMaxColsPerLane];
-#pragma unroll
-    for (int c = 0; c < kMaxColsPerLane; ++c) acc[c] = 0.0;
-    for (int i = iupd + rg; i < nr; i += kRowGroups) {
-        double* row = Ab + i * n;
-        const double x = (r0 + i > jc) ? row[jc] : 0.0;
-        const double tv = t * vloc[i];
-#pragma unroll
-        for (int c = 0; c < kMaxColsPerLane; ++c) {
-            const int s = cl + kColGroup * c;
-            if (c < ncl && s < nsl) {
-                double a = row[jc + s];
-                if (s > 0 && t != 0.0) {
-                    a -= tv * wv[jc + s];
-                    row[jc + s] = a;
-                }
-                acc[c] += x * a;
+};
+
+// Householder vector entry of local row i for panel column q (global column
+// c0 + q): the stored value below the diagonal, 1 on it, 0 above it and for
+// columns past the panel's width nb.
+struct PanelV {
+    const double* base;  // element (i, q) at base[i * ld + q]
+    long long ld;
+    Rows rows;
+    int c0, nb;
+    __device__ double operator()(int i, int q) const {
+        if (i >= rows.nr || q >= nb) return 0.0;
+        const int gi = rows.global(i), jq = c0 + q;
+        if (gi > jq) return base[(size_t)i * ld + q];
+        return gi == jq ? 1.0 : 0.0;
+    }
+};
+
+// The same for Householder vectors read from the working copy (row g of the
+// matrix at A + g * n): panel columns c0 .. c0 + nb - 1.
+struct GlobalV {
+    const double* A;
+    int n;
+    Rows rows;
+    int c0, nb;
+    __device__ double operator()(int i, int q) const {
+        if (i >= rows.nr || q >= nb) return 0.0;
+        const int gi = rows.global(i), jq = c0 + q;
+        if (gi > jq) return A[(size_t)gi * n + jq];
+        return gi == jq ? 1.0 : 0.0;
+    }
+};
+
+// out[r][c] (16 x (16 + nx), row stride 16 + nx) = sum over local rows i >= ilo
+// of V(i, r) * X(i, c), X = [V | X_g(:, xc0 : xc0 + nx)], on the FP64 matrix
+// cores: one 16 x 16 output tile per wave at a time, 4 rows per MFMA.
+template <class VF>
+__device__ void panel_vt_x(const VF& V, const Rows& rows, int ilo, const double* Xg, int ldx,
+                           int xc0, int nx, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int L = kPb + nx;
+    const int ntile = (L + 15) / 16;
+    const int col_l = lane & 15, k_l = lane >> 4;
+    for (int tile = wave; tile < ntile; tile += kWaves) {
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int c = tile * 16 + col_l;
+        for (int i4 = ilo; i4 < rows.nr; i4 += 4) {
+            const int i = i4 + k_l;
+            const double a = V(i, col_l);
+            double b = 0.0;
+            if (c < kPb) {
+                b = V(i, c);
+            } else if (c < L && i < rows.nr) {
+                b = Xg[(size_t)rows.global(i) * ldx + xc0 + (c - kPb)];
             }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        if (c < L) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[(size_t)(4 * r + k_l) * L + c] = acc[r];
         }
     }
-#pragma unroll
-    for (int c = 0; c < kMaxColsPerLane; ++c) {
-        const int s = cl + kColGroup * c;
-        if (c < ncl && s < nsl) red[rg * (n + 1) + s] = acc[c];
-    }
-    __syncthreads();
-    for (int s = tid; s < nsl; s += kQrThreads) {
-        double a = 0.0;
-        for (int g = 0; g < kRowGroups; ++g) a += red[g * (n + 1) + s];
-        out[s] = a;
-    }
-    __syncthreads();
 }
 
-__global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __restrict__ M, int m,
-                                                               int n, int rb, double* V, double* R,
-                                                               double* tau, double* part,
-                                                               double* rowbuf, unsigned* cnt,
-                                                               int* err) {
-    extern __shared__ double lds[];
-    const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
-    const int r0 = p * rb;
-    const int nr = max(0, min(rb, m - r0));
-    double* Ab = lds;
-    double* vloc = Ab + (size_t)rb * n;
-    double* wv = vloc + rb;
-    double* rowj = wv + n;
-    double* red = rowj + n;
-    double* sc = red + kRowGroups * (n + 1);
-    const size_t pstride = (size_t)P * (n + 1);
+// X_g(row, xc0 + c) -= sum_q V(i, q) Y[q][c] for local rows i >= ilo and c < nx
+// (Y is 16 x nx in LDS, row stride nx), on the FP64 matrix cores: 16 x 16
+// tiles, K = 16 in four steps.
+template <class VF>
+__device__ void panel_update(const VF& V, const Rows& rows, int ilo, double* Xg, int ldx, int xc0,
+                             int nx, const double* Y) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nrt = (rows.nr - ilo + 15) / 16, nct = (nx + 15) / 16;
+    const int col_l = lane & 15, k_l = lane >> 4;
+    for (int t = wave; t < nrt * nct; t += kWaves) {
+        const int i0 = ilo + (t / nct) * 16, ct = (t % nct) * 16;
+        const int c = ct + col_l;
+        dbl4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 4 * r + k_l;
+            acc[r] = (i < rows.nr && c < nx) ? Xg[(size_t)rows.global(i) * ldx + xc0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int q = 4 * kq + k_l;
+            const double a = -V(i0 + col_l, q);
+            const double b = (c < nx) ? Y[(size_t)q * nx + c] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 4 * r + k_l;
+            if (i < rows.nr && c < nx) Xg[(size_t)rows.global(i) * ldx + xc0 + c] = acc[r];
+        }
+    }
+}
 
-    for (int e = tid; e < nr * n; e += kQrThreads) Ab[e] = M[(size_t)r0 * n + e];
-    __syncthreads();
+// Sum of the P partial products part[q][0:E] (q = 0..P-1, fixed order) for the
+// entries owned by this workgroup (a contiguous chunk of E / P), into sum.
+__device__ void reduce_chunk(const double* part, double* sum, int P, int p, int E, double* red) {
+    const int tid = threadIdx.x;
+    const int chunk = (E + P - 1) / P;
+    const int e0 = p * chunk, e1 = min(E, e0 + chunk);
+    const int el = tid & 63, g = tid >> 6;
+    for (int base = e0; base < e1; base += 64) {
+        const int e = base + el;
+        double a = 0.0;
+        if (e < e1)
+            for (int q = g; q < P; q += kWaves) a += part[(size_t)q * E + e];
+        red[g * 64 + el] = a;
+        __syncthreads();
+        if (tid < 64 && e < e1) {
+            double s = 0.0;
+            for (int gg = 0; gg < kWaves; ++gg) s += red[gg * 64 + tid];
+            sum[e] = s;
+        }
+        __syncthreads();
+    }
+}
 
-    // column 0 partials and row 0
-    update_and_partials(Ab, nr, r0, n, 0, 0.0, vloc, wv, red, part + (size_t)p * (n + 1));
-    if (r0 <= 0 && 0 < r0 + nr)
-        for (int k = tid; k < n; k += kQrThreads) rowbuf[k] = Ab[k];
-
-    for (int j = 0; j < n; ++j) {
-        grid_barrier(cnt, (unsigned)(j + 1) * (unsigned)P, err);
-        const double* pp = part + (size_t)(j & 1) * pstride;
-        const double* row = rowbuf + (size_t)(j & 1) * n;
-        const int nslots = n - j;
-        // combine partials in a fixed order: 64 slot lanes x 8 workgroup groups,
-        // four independent running sums, then the groups through LDS
-        {
-            const int sl = tid % kColGroup, qg = tid / kColGroup;
-            for (int s0 = 0; s0 < nslots; s0 += kColGroup) {
-                const int sidx = s0 + sl;
-                if (sidx < nslots) {
-                    const double* col = pp + sidx;
-                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                    int q = qg;
-                    for (; q + 3 * kRowGroups < P; q += 4 * kRowGroups) {
-                        a0 += col[(size_t)q * (n + 1)];
-                        a1 += col[(size_t)(q + kRowGroups) * (n + 1)];
-                        a2 += col[(size_t)(q + 2 * kRowGroups) * (n + 1)];
-                        a3 += col[(size_t)(q + 3 * kRowGroups) * (n + 1)];
-                    }
-                    for (; q < P; q += kRowGroups) a0 += col[(size_t)q * (n + 1)];
-                    red[qg * (n + 1) + sidx] = (a0 + a1) + (a2 + a3);
+// Upper-triangular T of H_{c0} ... H_{c0+nb-1} = I - V T V^T from G = V^T V
+// (16 x 16 in LDS) and tau: T[q][q] = tau_q, T[r][q] = -tau_q sum_l T[r][l] G[l][q]
+// (the forward recurrence).  Lane r of the first wave computes row r alone.
+__device__ void form_t(const double* G, const double* tau, int nb, double* T) {
+    const int r = threadIdx.x;
+    if (r < kPb) {
+        double tr[kPb];
+#pragma unroll
+        for (int q = 0; q < kPb; ++q) {
+            double v = 0.0;
+            if (q < nb) {
+                if (r == q) {
+                    v = tau[q];
+                } else if (r < q) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int l = 0; l < q; ++l)
+                        if (l >= r) s += tr[l] * G[l * kPb + q];
+                    v = -tau[q] * s;
                 }
             }
-            for (int k = j + tid; k < n; k += kQrThreads) rowj[k] = row[k];
-            __syncthreads();
-            for (int sidx = tid; sidx < nslots; sidx += kQrThreads) {
-                double a = 0.0;
-                for (int g = 0; g < kRowGroups; ++g) a += red[g * (n + 1) + sidx];
-                wv[j + sidx] = a;  // wv[j] = sigma^2, wv[k] = x^T a_k over rows > j
-            }
-            __syncthreads();
+            tr[q] = v;
         }
-        if (tid == 0) {
-            const double alpha = rowj[j];
-            const double sigma2 = wv[j];
+#pragma unroll
+        for (int q = 0; q < kPb; ++q) T[r * kPb + q] = tr[q];
+    }
+}
+
+struct QrArgs {
+    const double* M;
+    int m, n;
+    double* A;       // m x n working copy (rows owned cyclically)
+    double* Q;       // m x n output (may alias M)
+    double* R;       // n x n output
+    double* part;    // 2 x P x 16 column partial sums
+    double* rowbuf;  // 2 x 16 pivot-row entries
+    double* red;     // P x 16 x (16 + n) partial products
+    double* redsum;  // 16 x (16 + n) reduced products
+    unsigned* flags; // P x kFlagStride
+    double* ratio;   // min |R_ii| / max |R_ii|
+    int* err;
+};
+
+__global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
+    extern __shared__ double lds[];
+    const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
+    const int m = a.m, n = a.n;
+    Rows rows{p, P, (m - p + P - 1) / P};
+    const int rbmax = (m + P - 1) / P;
+    double* Pn = lds;                          // rbmax x 16 panel rows
+    double* Ys = Pn + (size_t)rbmax * kPb;     // 16 x n
+    double* Gs = Ys + (size_t)kPb * n;         // 16 x 16
+    double* Ts = Gs + kPb * kPb;               // 16 x 16
+    double* red = Ts + kPb * kPb;              // 32 x 16
+    double* wv = red + kRowGroups * kPb;       // 16
+    double* rowj = wv + kPb;                   // 16
+    double* tau = rowj + kPb;                  // n
+    unsigned ep = 0;
+    double bmin = INFINITY, bmax = 0.0;
+
+    // working copy of this workgroup's rows
+    for (int e = tid; e < rows.nr * n; e += kQrThreads) {
+        const int i = e / n, c = e - i * n;
+        a.A[(size_t)rows.global(i) * n + c] = a.M[(size_t)rows.global(i) * n + c];
+    }
+    __syncthreads();
+
+    const int cl = tid % kPb, rg = tid / kPb;
+    const int npanel = (n + kPb - 1) / kPb;
+    for (int pk = 0; pk < npanel; ++pk) {
+        const int c0 = pk * kPb, nb = min(kPb, n - c0), c1 = c0 + nb;
+        const int ilo = rows.first_at_or_after(c0);
+        // panel rows into LDS; partial sums of column c0 and pivot row c0
+        for (int e = tid; e < (rows.nr - ilo) * kPb; e += kQrThreads) {
+            const int i = ilo + e / kPb, q = e % kPb;
+            Pn[i * kPb + q] = q < nb ? a.A[(size_t)rows.global(i) * n + c0 + q] : 0.0;
+        }
+        __syncthreads();
+        {
+            double acc = 0.0;
+            for (int i = ilo + rg; i < rows.nr; i += kRowGroups) {
+                const int gi = rows.global(i);
+                const double x = Pn[i * kPb];
+                const double v = Pn[i * kPb + cl];
+                if (gi > c0) acc += x * v;
+                if (gi == c0) a.rowbuf[(size_t)(c0 & 1) * kPb + cl] = v;
+            }
+            red[rg * kPb + cl] = acc;
+            __syncthreads();
+            if (tid < kPb)  {
+                double s = 0.0;
+                for (int g = 0; g < kRowGroups; ++g) s += red[g * kPb + tid];
+                a.part[((size_t)(c0 & 1) * P + p) * kPb + tid] = s;
+            }
+        }
+        for (int q = 0; q < nb; ++q) {
+            const int j = c0 + q;
+            const int buf = j & 1;
+            flag_barrier(a.flags, P, ++ep, a.err);
+            // combine: slot s = column j + s (slot 0: squared norm below j)
+            {
+                const int s = tid % kPb, g = tid / kPb;
+                double acc = 0.0;
+                for (int w = g; w < P; w += kRowGroups) acc += a.part[((size_t)buf * P + w) * kPb + s];
+                red[g * kPb + s] = acc;
+                if (tid < kPb) rowj[tid] = a.rowbuf[(size_t)buf * kPb + tid];
+                __syncthreads();
+                if (tid < kPb) {
+                    double t = 0.0;
+                    for (int gg = 0; gg < kRowGroups; ++gg) t += red[gg * kPb + tid];
+                    wv[tid] = t;
+                }
+                __syncthreads();
+            }
+            // reflector (every thread, same values)
+            const double alpha = rowj[q], sigma2 = wv[0];
             double beta, t, gamma;
-            int mode;  // 0: H = I, 1: sign flip e_j, 2: general reflector
+            int mode;  // 0: H = I, 1: sign flip of e_j, 2: general reflector
             if (sigma2 == 0.0) {
                 if (alpha >= 0.0) { mode = 0; beta = alpha; t = 0.0; gamma = 1.0; }
                 else { mode = 1; beta = -alpha; t = 2.0; gamma = 1.0; }
@@ -189,168 +355,175 @@ __global__ __launch_bounds__(kQrThreads) void qr_factor_kernel(const double* __r
                 gamma = alpha <= 0.0 ? alpha - beta : -sigma2 / (alpha + beta);
                 t = -gamma / beta;
             }
-            sc[0] = beta; sc[1] = t; sc[2] = gamma; sc[3] = (double)mode;
-        }
-        __syncthreads();
-        const double beta = sc[0], t = sc[1], gamma = sc[2];
-        const int mode = (int)sc[3];
-        // w_k = v^T a_k over rows >= j (v_j = 1)
-        for (int k = j + 1 + tid; k < n; k += kQrThreads)
-            wv[k] = (mode == 2) ? wv[k] / gamma + rowj[k] : rowj[k];
-        // v for the local rows
-        for (int i = tid; i < nr; i += kQrThreads) {
-            const int gi = r0 + i;
-            double v;
-            if (gi < j) v = 0.0;
-            else if (gi == j) v = 1.0;
-            else v = (mode == 2) ? Ab[i * n + j] / gamma : 0.0;
-            vloc[i] = v;
-            V[(size_t)gi * n + j] = v;
-        }
-        __syncthreads();
-        if (p == 0) {
-            for (int k = tid; k < n; k += kQrThreads) {
-                double r;
-                if (k < j) r = 0.0;
-                else if (k == j) r = beta;
-                else r = rowj[k] - t * wv[k];
-                R[(size_t)j * n + k] = r;
+            // w_k = v^T a_k over rows >= j for the panel columns k > j
+            auto wcol = [&](int qq) {  // panel column qq > q
+                const double rj = rowj[qq];
+                return mode == 2 ? wv[qq - q] / gamma + rj : rj;
+            };
+            if (tid == 0) {
+                tau[j] = t;
+                bmin = fmin(bmin, fabs(beta));
+                bmax = fmax(bmax, fabs(beta));
             }
-            if (tid == 0) tau[j] = t;
-        }
-        if (j + 1 < n) {
-            update_and_partials(Ab, nr, r0, n, j + 1, t, vloc, wv, red,
-                                part + (size_t)((j + 1) & 1) * pstride + (size_t)p * (n + 1));
-            // publish row j+1 (final in columns > j)
-            if (r0 <= j + 1 && j + 1 < r0 + nr) {
-                double* nrow = rowbuf + (size_t)((j + 1) & 1) * n;
-                for (int k = tid; k < n; k += kQrThreads) nrow[k] = Ab[(j + 1 - r0) * n + k];
+            if (p == 0) {
+                for (int k = tid; k < c1; k += kQrThreads) {
+                    double r;
+                    if (k < j) r = 0.0;
+                    else if (k == j) r = beta;
+                    else r = rowj[k - c0] - t * wcol(k - c0);
+                    a.R[(size_t)j * n + k] = r;
+                }
             }
-        }
-    }
-}
-
-__global__ void zero_counter_kernel(unsigned* cnt) {
-    if (threadIdx.x == 0) *cnt = 0u;
-}
-
-// T[i][j] (i <= j): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j]
-// (the forward compact-WY recurrence), in column blocks of kTb: the part of the
-// triangular product over columns left of the block is one parallel pass over
-// the whole block (partial results in LDS); the in-block part is sequential
-// over the kTb columns.  Also min|R_ii| / max|R_ii| into diag_ratio.
-constexpr int kTb = 16;
-constexpr int kTMaxN = 512;
-
-__global__ __launch_bounds__(1024) void qr_tfactor_kernel(const double* __restrict__ G,
-                                                          const double* __restrict__ tau, int n,
-                                                          double* T, const double* R,
-                                                          double* diag_ratio) {
-    __shared__ double W1[kTMaxN * kTb];  // W1[i*kTb + c] = sum_{l<b0} T[i][l] G[l][b0+c]
-    __shared__ double Tb[kTMaxN * kTb];  // current block's columns of T: Tb[i*kTb + c]
-    const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += blockDim.x) T[e] = 0.0;
-    __syncthreads();
-    for (int b0 = 0; b0 < n; b0 += kTb) {
-        const int nb = min(kTb, n - b0);
-        for (int e = tid; e < b0 * nb; e += blockDim.x) {
-            const int i = e / nb, c = e % nb;
+            // apply H_j to the panel rows >= j, store v in column q, and
+            // reduce column j+1 against the later panel columns (rows > j+1)
+            const bool next = q + 1 < nb;
+            const double w1 = next ? wcol(q + 1) : 0.0;
+            const double wc = (cl > q && cl < nb) ? wcol(cl) : 0.0;
+            const int ij = rows.first_at_or_after(j);
             double acc = 0.0;
-            for (int l = i; l < b0; ++l) acc += T[(size_t)i * n + l] * G[(size_t)l * n + b0 + c];
-            W1[i * kTb + c] = acc;
+            for (int i = ij + rg; i < rows.nr; i += kRowGroups) {
+                const int gi = rows.global(i);
+                double* row = Pn + i * kPb;
+                const double xj = row[q];
+                const double v = gi > j ? (mode == 2 ? xj / gamma : 0.0) : 1.0;
+                const double tv = t * v;
+                const double x1 = next ? row[q + 1] - tv * w1 : 0.0;
+                if (cl == q && gi > j) row[q] = v;
+                if (cl > q && cl < nb) {
+                    const double u = row[cl] - tv * wc;
+                    row[cl] = u;
+                    if (gi > j + 1) acc += x1 * u;
+                    if (gi == j + 1) a.rowbuf[(size_t)((j + 1) & 1) * kPb + cl] = u;
+                }
+            }
+            if (next) {
+                red[rg * kPb + cl] = acc;
+                __syncthreads();
+                if (tid < kPb) {
+                    double s = 0.0;
+                    if (tid > q) for (int g = 0; g < kRowGroups; ++g) s += red[g * kPb + tid];
+                    // slot tid - (q + 1) for column j + 1 + (tid - q - 1)
+                    if (tid > q) a.part[((size_t)((j + 1) & 1) * P + p) * kPb + (tid - q - 1)] = s;
+                }
+            }
         }
-        for (int e = tid; e < (b0 + nb) * kTb; e += blockDim.x) Tb[e] = 0.0;
         __syncthreads();
-        for (int c = 0; c < nb; ++c) {
-            const int jj = b0 + c;
-            const double tj = tau[jj];
-            double val = 0.0;
-            const int i = tid;
-            if (i < jj) {
-                double acc = i < b0 ? W1[i * kTb + c] : 0.0;
-                for (int l = max(i, b0); l < jj; ++l) acc += Tb[i * kTb + (l - b0)] * G[(size_t)l * n + jj];
-                val = -tj * acc;
+        // Householder vectors of the panel back to the working copy
+        for (int e = tid; e < (rows.nr - ilo) * kPb; e += kQrThreads) {
+            const int i = ilo + e / kPb, q = e % kPb;
+            if (q < nb) a.A[(size_t)rows.global(i) * n + c0 + q] = Pn[i * kPb + q];
+        }
+        if (c1 < n) {
+            const int nt = n - c1, L = kPb + nt;
+            PanelV V{Pn, kPb, rows, c0, nb};
+            panel_vt_x(V, rows, ilo, a.A, n, c1, nt, a.red + (size_t)p * kPb * L);
+            flag_barrier(a.flags, P, ++ep, a.err);
+            reduce_chunk(a.red, a.redsum, P, p, kPb * L, red);
+            flag_barrier(a.flags, P, ++ep, a.err);
+            for (int e = tid; e < kPb * kPb; e += kQrThreads)
+                Gs[e] = a.redsum[(size_t)(e / kPb) * L + (e % kPb)];
+            __syncthreads();
+            form_t(Gs, tau + c0, nb, Ts);
+            __syncthreads();
+            // Y = T^T W, W = V^T A_trail (columns kPb.. of the reduced product)
+            for (int c = tid; c < nt; c += kQrThreads) {
+                double w[kPb];
+#pragma unroll
+                for (int r = 0; r < kPb; ++r) w[r] = a.redsum[(size_t)r * L + kPb + c];
+#pragma unroll
+                for (int q = 0; q < kPb; ++q) {
+                    double y = 0.0;
+#pragma unroll
+                    for (int r = 0; r <= q; ++r) y += Ts[r * kPb + q] * w[r];
+                    Ys[(size_t)q * nt + c] = y;
+                }
             }
             __syncthreads();
-            if (i < jj) Tb[i * kTb + c] = val;
-            if (i == jj) Tb[i * kTb + c] = tj;
+            panel_update(V, rows, ilo, a.A, n, c1, nt, Ys);
             __syncthreads();
+            // rows c0..c1-1 are final beyond the panel: they are R's rows there
+            for (int e = tid; e < nb * nt; e += kQrThreads) {
+                const int j = c0 + e / nt, c = c1 + e % nt;
+                if (j % P == p) a.R[(size_t)j * n + c] = a.A[(size_t)j * n + c];
+            }
         }
-        for (int e = tid; e < (b0 + nb) * nb; e += blockDim.x) {
-            const int i = e / nb, c = e % nb;
-            T[(size_t)i * n + b0 + c] = Tb[i * kTb + c];
+    }
+    if (p == 0 && tid == 0) *a.ratio = bmax > 0.0 ? bmin / bmax : 0.0;
+
+    // explicit Q: [I; 0], then the panels in reverse order
+    __syncthreads();
+    for (int e = tid; e < rows.nr * n; e += kQrThreads) {
+        const int i = e / n, c = e - i * n;
+        const int gi = rows.global(i);
+        a.Q[(size_t)gi * n + c] = gi == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int pk = npanel - 1; pk >= 0; --pk) {
+        const int c0 = pk * kPb, nb = min(kPb, n - c0);
+        const int nq = n - c0, L = kPb + nq;
+        const int ilo = rows.first_at_or_after(c0);
+        GlobalV VG{a.A, n, rows, c0, nb};
+        panel_vt_x(VG, rows, ilo, a.Q, n, c0, nq, a.red + (size_t)p * kPb * L);
+        flag_barrier(a.flags, P, ++ep, a.err);
+        reduce_chunk(a.red, a.redsum, P, p, kPb * L, red);
+        flag_barrier(a.flags, P, ++ep, a.err);
+        for (int e = tid; e < kPb * kPb; e += kQrThreads)
+            Gs[e] = a.redsum[(size_t)(e / kPb) * L + (e % kPb)];
+        __syncthreads();
+        form_t(Gs, tau + c0, nb, Ts);
+        __syncthreads();
+        // Y = T W
+        for (int c = tid; c < nq; c += kQrThreads) {
+            double w[kPb];
+#pragma unroll
+            for (int r = 0; r < kPb; ++r) w[r] = a.redsum[(size_t)r * L + kPb + c];
+#pragma unroll
+            for (int q = 0; q < kPb; ++q) {
+                double y = 0.0;
+#pragma unroll
+                for (int r = q; r < kPb; ++r) y += Ts[q * kPb + r] * w[r];
+                Ys[(size_t)q * nq + c] = y;
+            }
         }
         __syncthreads();
-    }
-    if (tid == 0 && diag_ratio != nullptr) {
-        double mn = INFINITY, mx = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double d = fabs(R[(size_t)k * n + k]);
-            mn = fmin(mn, d);
-            mx = fmax(mx, d);
-        }
-        *diag_ratio = mx > 0.0 ? mn / mx : 0.0;
+        panel_update(VG, rows, ilo, a.Q, n, c0, nq, Ys);
+        __syncthreads();
     }
 }
 
-__global__ void eye_kernel(double* Q, long long m, int n) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < m * n;
-         e += (long long)gridDim.x * blockDim.x) {
-        const long long i = e / n, c = e % n;
-        Q[e] = (i == c) ? 1.0 : 0.0;
-    }
-}
-
-QrLayout plan_qr(int m, int n) {
-    QrLayout L{};
-    // fewest workgroups whose row blocks fit in LDS: fewer partial sums to
-    // combine and a cheaper grid barrier
-    const size_t fixed = lds_for(0, n);
-    const size_t per_row = sizeof(double) * (size_t)(n + 1);
-    long long rb_max = fixed < kQrLdsBudget ? (long long)((kQrLdsBudget - fixed) / per_row) : 0;
-    if (rb_max < 1) rb_max = 1;
-    long long P = ceil_div(m, rb_max);
-    if (P < 1) P = 1;
-    L.rb = (int)ceil_div(m, P);
-    L.P = (int)ceil_div(m, L.rb);
-    L.lds_bytes = lds_for(L.rb, n);
-    return L;
+__global__ void zero_flags_kernel(unsigned* flags, int count) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x)
+        flags[e] = 0u;
 }
 
 }  // namespace
 
 QrScratch qr_scratch_layout(int m, int n) {
     QrScratch s{};
-    const QrLayout L = plan_qr(m, n);
+    const QrPlan L = plan_qr(m, n);
     size_t off = 0;
-    auto take = [&](size_t count) {
+    auto take = [&](size_t bytes) {
         const size_t o = off;
-        off += ((count * sizeof(double) + 255) / 256) * 256;
+        off += ((bytes + 255) / 256) * 256;
         return o;
     };
-    s.off_V = take((size_t)m * n);
-    s.off_tau = take(n);
-    s.off_part = take(2 * (size_t)L.P * (n + 1));
-    s.off_rowbuf = take(2 * (size_t)n);
-    s.off_G = take((size_t)n * n);
-    s.off_T = take((size_t)n * n);
-    s.off_MT = take((size_t)n * n);
-    s.off_ratio = take(1);
-    s.off_cnt = take(1);
-    s.off_err = take(1);
-    GemmDesc gg;
-    gg.M = n; gg.N = n; gg.K = m;
-    const size_t sk = gemm_splitk_bytes(gg);
-    s.off_splitk = take(sk / sizeof(double) + 1);
-    s.splitk_bytes = sk;
+    const size_t w = kPb + (size_t)n;
+    s.off_A = take(sizeof(double) * (size_t)m * n);
+    s.off_part = take(sizeof(double) * 2 * (size_t)L.P * kPb);
+    s.off_rowbuf = take(sizeof(double) * 2 * kPb);
+    s.off_red = take(sizeof(double) * (size_t)L.P * kPb * w);
+    s.off_redsum = take(sizeof(double) * kPb * w);
+    s.off_flags = take(sizeof(unsigned) * (size_t)L.P * kFlagStride);
+    s.off_ratio = take(sizeof(double));
+    s.off_err = take(sizeof(int));
     s.total = off;
     return s;
 }
 
 bool qr_fits(int m, int n) {
-    if (m < n || n < 1 || n > kTMaxN) return false;
-    const QrLayout L = plan_qr(m, n);
-    return L.lds_bytes <= kQrLdsBudget && L.P <= 256;
+    if (m < n || n < 1 || n > kMaxN) return false;
+    const QrPlan L = plan_qr(m, n);
+    return L.lds_bytes <= kQrLdsBudget && L.P <= kMaxWg;
 }
 
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
@@ -358,91 +531,53 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     Status s;
     if (!qr_fits(m, n)) {
         s.code = -1;
-        s.msg = "qr: shape not supported (need m >= n, n <= 512, at most 256 row blocks in LDS)";
+        s.msg = "qr: shape not supported (need m >= n >= 1, n <= 512)";
         return s;
     }
-    const QrScratch L = qr_scratch_layout(m, n);
-    if (ws_bytes < L.total) {
+    const QrScratch S = qr_scratch_layout(m, n);
+    if (ws_bytes < S.total) {
         s.code = -2;
         s.msg = "qr: workspace too small";
         return s;
     }
+    const QrPlan L = plan_qr(m, n);
     char* base = static_cast<char*>(ws);
-    double* V = reinterpret_cast<double*>(base + L.off_V);
-    double* tau = reinterpret_cast<double*>(base + L.off_tau);
-    double* part = reinterpret_cast<double*>(base + L.off_part);
-    double* rowbuf = reinterpret_cast<double*>(base + L.off_rowbuf);
-    double* G = reinterpret_cast<double*>(base + L.off_G);
-    double* T = reinterpret_cast<double*>(base + L.off_T);
-    double* MT = reinterpret_cast<double*>(base + L.off_MT);
-    double* ratio = diag_ratio_dev ? diag_ratio_dev : reinterpret_cast<double*>(base + L.off_ratio);
-    void* sk = base + L.off_splitk;
+    QrArgs a;
+    a.M = M;
+    a.m = m;
+    a.n = n;
+    a.A = reinterpret_cast<double*>(base + S.off_A);
+    a.Q = Q;
+    a.R = R;
+    a.part = reinterpret_cast<double*>(base + S.off_part);
+    a.rowbuf = reinterpret_cast<double*>(base + S.off_rowbuf);
+    a.red = reinterpret_cast<double*>(base + S.off_red);
+    a.redsum = reinterpret_cast<double*>(base + S.off_redsum);
+    a.flags = reinterpret_cast<unsigned*>(base + S.off_flags);
+    a.ratio = diag_ratio_dev ? diag_ratio_dev : reinterpret_cast<double*>(base + S.off_ratio);
+    a.err = err_dev ? err_dev : reinterpret_cast<int*>(base + S.off_err);
 
-    const QrLayout ql = plan_qr(m, n);
-    unsigned* cnt = reinterpret_cast<unsigned*>(base + L.off_cnt);
-    int* err = err_dev ? err_dev : reinterpret_cast<int*>(base + L.off_err);
-    {
-        int dev = 0;
-        QRCTM_HIP(hipGetDevice(&dev));
-        QRCTM_HIP(hipFuncSetAttribute((const void*)qr_factor_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)ql.lds_bytes));
-        int nblk = 0;
-        QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, qr_factor_kernel, kQrThreads,
-                                                               ql.lds_bytes));
-        int ncu = 0;
-        QRCTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        if ((long long)nblk * ncu < ql.P) {
-            s.code = -1;
-            s.msg = "qr: cooperative grid does not fit on the device";
-            return s;
-        }
-        hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, st, cnt);
-        QRCTM_TRY(launch_check("zero_counter_kernel"));
-        const double* Mp = M;
-        int mm = m, nn = n, rbb = ql.rb;
-        void* args[] = {(void*)&Mp,  (void*)&mm,   (void*)&nn,     (void*)&rbb,
-                        (void*)&V,   (void*)&R,    (void*)&tau,    (void*)&part,
-                        (void*)&rowbuf, (void*)&cnt, (void*)&err};
-        QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_factor_kernel, dim3(ql.P),
-                                             dim3(kQrThreads), args, ql.lds_bytes, st));
+    int dev = 0;
+    QRCTM_HIP(hipGetDevice(&dev));
+    QRCTM_HIP(hipFuncSetAttribute((const void*)qr_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes));
+    int nblk = 0;
+    QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, qr_kernel, kQrThreads,
+                                                           L.lds_bytes));
+    int ncu = 0;
+    QRCTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if ((long long)nblk * ncu < L.P) {
+        s.code = -1;
+        s.msg = "qr: cooperative grid does not fit on the device";
+        return s;
     }
-    // G = V^T V
-    {
-        GemmDesc g;
-        g.trans_a = 1; g.trans_b = 0;
-        g.M = n; g.N = n; g.K = m;
-        g.A = V; g.lda = n; g.B = V; g.ldb = n;
-        g.C = G; g.map = OutMap::plain(n, n, n);
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    hipLaunchKernelGGL(qr_tfactor_kernel, dim3(1), dim3(1024), 0, st, G, tau, n, T, R, ratio);
-    QRCTM_TRY(launch_check("qr_tfactor_kernel"));
-    // MT = T V1^T
-    {
-        GemmDesc g;
-        g.trans_a = 0; g.trans_b = 1;
-        g.M = n; g.N = n; g.K = n;
-        g.A = T; g.lda = n; g.B = V; g.ldb = n;
-        g.C = MT; g.map = OutMap::plain(n, n, n);
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
-    {
-        const long long tot = (long long)m * n;
-        const int blocks = (int)std::min<long long>(ceil_div(tot, 256), 4096);
-        hipLaunchKernelGGL(eye_kernel, dim3(blocks), dim3(256), 0, st, Q, (long long)m, n);
-        QRCTM_TRY(launch_check("eye_kernel"));
-    }
-    // Q = E - V MT
-    {
-        GemmDesc g;
-        g.trans_a = 0; g.trans_b = 0;
-        g.M = m; g.N = n; g.K = n;
-        g.A = V; g.lda = n; g.B = MT; g.ldb = n;
-        g.C = Q; g.map = OutMap::plain(m, n, n);
-        g.alpha = -1.0; g.beta = 1.0;
-        QRCTM_TRY(gemm_f64(g, sk, L.splitk_bytes, st));
-    }
+    const int nflags = L.P * kFlagStride;
+    hipLaunchKernelGGL(zero_flags_kernel, dim3((nflags + 255) / 256), dim3(256), 0, st, a.flags,
+                       nflags);
+    QRCTM_TRY(launch_check("zero_flags_kernel"));
+    void* args[] = {(void*)&a};
+    QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_kernel, dim3(L.P), dim3(kQrThreads), args,
+                                         L.lds_bytes, st));
     return s;
 }
 

@@ -264,6 +264,49 @@ class Context:
         self._c(lib().ctm_set_timing(self._ctx, int(on)))
 
 
+_ENERGY_FN = None
+
+
+def _energy_function():
+    """torch.autograd.Function for E(A) with the library's hand-written adjoint.
+
+    forward: ctm_set_tensor (the context keeps its environment as the starting
+    point, as the AD paragraph reuses the previous environment), ctm_converge,
+    then ctm_energy_grad, whose dE/dA is saved; backward returns gE * dE/dA.
+    """
+    global _ENERGY_FN
+    if _ENERGY_FN is None:
+        torch = _torch()
+
+        class QRCTMEnergy(torch.autograd.Function):
+            @staticmethod
+            def forward(fctx, A, ctx, h_nn, h_nnn, J2, tol, max_steps):
+                ctx.set_tensor(A.detach())
+                ctx.converge(tol, max_steps)
+                e, dA = ctx.energy_grad(h_nn, h_nnn, J2)
+                fctx.save_for_backward(dA.to(A.dtype))
+                return torch.tensor(e, dtype=A.dtype, device=A.device)
+
+            @staticmethod
+            def backward(fctx, gE):
+                (dA,) = fctx.saved_tensors
+                return gE * dA, None, None, None, None, None, None
+
+        _ENERGY_FN = QRCTMEnergy
+    return _ENERGY_FN
+
+
+def energy(A, ctx: "Context", h_nn, h_nnn=None, J2: float = 0.0, tol: float = 1e-10,
+           max_steps: int = 200):
+    """Differentiable energy per site E(A) (a torch scalar on A's device).
+
+    The environment of ctx is converged for A (to tol, at most max_steps
+    steps), then E and dE/dA come from ctm_energy_grad: dE/dA is the derivative
+    of E_k(P(A); C*, T*), k = the context's tracked steps.
+    """
+    return _energy_function().apply(A, ctx, h_nn, h_nnn, J2, tol, max_steps)
+
+
 def qr(M):
     """Thin QR with diag(R) >= 0 of a device matrix (m x n, m >= n) via ctm_qr."""
     torch = _torch()

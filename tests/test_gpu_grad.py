@@ -88,3 +88,28 @@ def test_gradient_singular_reduced_corner_is_reported():
         ctx.energy_grad(inp.heisenberg_bond_rotated())
     assert e.value.code == -5
     ctx.close()
+
+
+def test_autograd_energy_function():
+    # E(A) as a torch scalar: converge the environment for A, then dE/dA from
+    # the library's adjoint flows back through .backward()
+    d, D, chi, k = 2, 2, 16, 3
+    A = inp.random_site_tensor(d, D, 5)
+    h = inp.heisenberg_bond_rotated()
+    ctx = P.Context(_dev(A), chi, k_tracked=k)
+    At = _dev(A).requires_grad_(True)
+    E = P.energy(At, ctx, h, tol=1e-12, max_steps=400)
+    (2.0 * E).backward()
+    C, T = [x.cpu().numpy() for x in ctx.get_env()]
+    e_ref, g_ref = adj.energy_grad_k(A, C, T, k, h)
+    assert abs(E.item() - e_ref) < 1e-12 * abs(e_ref)
+    g = At.grad.cpu().numpy()
+    assert np.linalg.norm(g - 2.0 * g_ref) / np.linalg.norm(2.0 * g_ref) < 1e-9
+    # a second evaluation starts from the environment left by the first
+    A2 = A + 1e-3 * inp.random_site_tensor(d, D, 6)
+    E2 = P.energy(_dev(A2), ctx, h, tol=1e-12, max_steps=400)
+    ctx2 = P.Context(_dev(A2), chi, k_tracked=k)
+    ctx2.converge(1e-12, 400)
+    assert abs(E2.item() - ctx2.energy(h)) < 1e-8
+    ctx.close()
+    ctx2.close()
