@@ -5,7 +5,7 @@
 namespace qrctm {
 
 struct QrScratch {
-    size_t off_A, off_part, off_rowbuf, off_red, off_redsum, off_flags, off_ratio, off_err;
+    size_t off_A, off_part, off_rowbuf, off_red, off_redsum, off_xend, off_ratio, off_err;
     size_t total;
 };
 
@@ -14,7 +14,7 @@ bool qr_fits(int m, int n);
 // Q (m x n) and R (n x n) from M (m x n), all device, row-major.  diag_ratio_dev
 // (device, may be null) receives min|R_ii| / max|R_ii|; err_dev (device int, may
 // be null) is or-ed with 2 if a grid barrier timed out.  Q may alias M.  One cooperative
-// kernel (plus a flag-clearing kernel); no other scratch than ws.
+// kernel (after a kernel that clears its exchange buffers); no scratch but ws.
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
               hipStream_t st, double* diag_ratio_dev, int* err_dev);
 

@@ -11,22 +11,35 @@
 //    touched by no other workgroup;
 //  * the columns are taken in panels of 16.  For column j of a panel every
 //    workgroup reduces, over its rows below j, the squared norm of column j and
-//    its dot products with the later panel columns, publishes these 16 partial
-//    sums and arrives on a per-workgroup flag; after seeing every flag, all
-//    workgroups combine the partial sums in one fixed order (bitwise identical
-//    everywhere), form the reflector with beta = +||x|| (the non-negative
-//    diagonal variant, cancellation-free gamma) and update the panel rows they
-//    hold in LDS.  One flag barrier per column, and it carries 16 numbers per
-//    workgroup, not n - j;
+//    its dot products with the later panel columns and publishes these 16
+//    partial sums; all workgroups then combine the partial sums in one fixed
+//    order (bitwise identical everywhere), form the reflector with
+//    beta = +||x|| (the non-negative diagonal variant, cancellation-free gamma)
+//    and update the panel rows they hold in LDS.  One exchange per column,
+//    of 16 numbers per workgroup, not n - j;
 //  * after a panel, the trailing columns get the panel's reflectors in compact
 //    WY form, I - V T V^T: V^T [V | A_trail] is reduced over all rows (FP64
 //    matrix-core tiles per workgroup, then a reduction of the partial products
-//    spread over the workgroups, two flag barriers), T follows from V^T V and
-//    the tau's by the forward recurrence, and A_trail -= V (T^T (V^T A_trail))
-//    is a matrix-core update of each workgroup's own rows;
+//    spread over the workgroups), T follows from V^T V and the tau's by the
+//    forward recurrence, and A_trail -= V (T^T (V^T A_trail)) is a matrix-core
+//    update of each workgroup's own rows;
 //  * the explicit thin factor Q = H_0 ... H_{n-1} [I; 0] is formed in the same
 //    kernel by applying the panels in reverse order to [I; 0], with the same
 //    reduction pattern.
+//
+// Workgroups exchange data without grid barriers or cache flushes: every
+// double sent to another workgroup travels as two 64-bit words, each holding
+// 32 bits of the value and a 32-bit tag naming the exchange it belongs to
+// (tags grow through the kernel; the buffers are cleared to tag 0 before the
+// launch).  Writers and readers use relaxed agent-scope atomics, so each word
+// is read whole; a reader polls its words until both carry the expected tag.
+// Every exchange only waits for data of the previous one, all workgroups are
+// co-resident (cooperative launch), and every wait is bounded (on timeout an
+// error bit is set and the kernel runs to its end).  Exchange buffers are
+// double-buffered where a fast workgroup could otherwise overwrite data a slow
+// one has not read: before a workgroup writes exchange t + 2 into a buffer it
+// has read exchange t + 1 from every workgroup, which each sent only after
+// reading exchange t.
 //
 // The reflectors are the textbook ones (column by column, in order), so R and Q
 // agree with any other Householder QR with diag(R) >= 0 up to rounding.
@@ -43,9 +56,10 @@ constexpr int kRowGroups = kQrThreads / kPb;   // 32 row groups x 16 column lane
 constexpr int kRowsPerWg = 64;                 // target rows per workgroup
 constexpr int kMaxWg = 256;
 constexpr int kMaxN = 512;
-constexpr int kFlagStride = 32;                // one 128-byte line per flag
-constexpr unsigned kSpinLimit = 1u << 22;
+constexpr unsigned kSpinLimit = 1u << 17;      // polls of about a microsecond: ~0.1 s
 constexpr size_t kQrLdsBudget = 150 * 1024;
+static_assert(kMaxWg == 8 * kRowGroups, "the combine sums eight workgroups per row group");
+static_assert(kMaxN <= kQrThreads, "form_y gives one column of W to each thread");
 
 struct QrPlan {
     int P;   // workgroups
@@ -71,32 +85,58 @@ QrPlan plan_qr(int m, int n) {
     return L;
 }
 
-// Grid-wide barrier of the cooperative launch on per-workgroup flags.  After a
-// workgroup barrier, thread 0 stores the epoch into its own flag with release
-// semantics; the first wave polls all P flags (lane q the flags q, q+64, ...)
-// with relaxed loads until each holds at least the epoch, then issues one
-// acquire fence.  No location is written by two workgroups.  The wait is
-// bounded: on timeout *err is set and the kernel runs to its end (the host then
-// discards the result).
-__device__ void flag_barrier(unsigned* flags, int P, unsigned epoch, int* err) {
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(flags + (size_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x < 64) {
-        for (int q = threadIdx.x; q < P; q += 64) {
-            unsigned spins = 0;
-            while (__hip_atomic_load(flags + (size_t)q * kFlagStride, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-                if (++spins > kSpinLimit) {
-                    atomicOr(err, 2);
-                    break;
-                }
+typedef unsigned long long u64;
+
+// A double sent to other workgroups: word 0 holds the low 32 bits, word 1 the
+// high 32 bits, each with the tag in its upper half.
+__device__ void ll_put(u64* w, double v, unsigned tag) {
+    const u64 b = (u64)__double_as_longlong(v);
+    const u64 t = (u64)tag << 32;
+    __hip_atomic_store(w, (b & 0xffffffffull) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, (b >> 32) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Receive n <= N doubles (word pairs at addr(k)) sent with the given tag: all
+// pending pairs are loaded in one round, those with both tags right are taken,
+// the rest polled again.  On timeout the missing values are 0 and err gets 2.
+template <int N, class Addr>
+__device__ void ll_get(const Addr& addr, int n, unsigned tag, double* out, int* err) {
+    unsigned pending = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+    unsigned spins = 0;
+    while (pending) {
+        u64 lo[N], hi[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if ((pending >> k) & 1u) {
+                const u64* w = addr(k);
+                lo[k] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                hi[k] = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (((pending >> k) & 1u) && (unsigned)(lo[k] >> 32) == tag &&
+                (unsigned)(hi[k] >> 32) == tag) {
+                out[k] = __longlong_as_double((long long)((hi[k] << 32) | (lo[k] & 0xffffffffull)));
+                pending &= ~(1u << k);
+            }
+        }
+        if (pending && ++spins > kSpinLimit) {
+            atomicOr(err, 2);
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                if ((pending >> k) & 1u) out[k] = 0.0;
+            break;
+        }
     }
-    __syncthreads();
+}
+
+// Sum of v over the four lanes of a wave that share lane % 16 (the four row
+// groups of a wave), in a fixed order; every lane gets the sum.
+__device__ double quarter_sum(double v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
 }
 
 // Everything a workgroup needs to address its rows.
@@ -141,12 +181,13 @@ struct GlobalV {
     }
 };
 
-// out[r][c] (16 x (16 + nx), row stride 16 + nx) = sum over local rows i >= ilo
+// out[r][c] (16 x (16 + nx), row stride 16 + nx, sent with tag) = sum over local rows i >= ilo
 // of V(i, r) * X(i, c), X = [V | X_g(:, xc0 : xc0 + nx)], on the FP64 matrix
-// cores: one 16 x 16 output tile per wave at a time, 4 rows per MFMA.
+// cores: one 16 x 16 output tile per wave at a time, 4 rows per MFMA, the
+// operands of 16 rows loaded before the four MFMAs that use them.
 template <class VF>
 __device__ void panel_vt_x(const VF& V, const Rows& rows, int ilo, const double* Xg, int ldx,
-                           int xc0, int nx, double* out) {
+                           int xc0, int nx, u64* out, unsigned tag) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int L = kPb + nx;
     const int ntile = (L + 15) / 16;
@@ -154,20 +195,22 @@ __device__ void panel_vt_x(const VF& V, const Rows& rows, int ilo, const double*
     for (int tile = wave; tile < ntile; tile += kWaves) {
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
         const int c = tile * 16 + col_l;
-        for (int i4 = ilo; i4 < rows.nr; i4 += 4) {
-            const int i = i4 + k_l;
-            const double a = V(i, col_l);
-            double b = 0.0;
-            if (c < kPb) {
-                b = V(i, c);
-            } else if (c < L && i < rows.nr) {
-                b = Xg[(size_t)rows.global(i) * ldx + xc0 + (c - kPb)];
+        for (int i16 = ilo; i16 < rows.nr; i16 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i16 + 4 * u + k_l;
+                av[u] = V(i, col_l);
+                if (c < kPb) bv[u] = V(i, c);
+                else if (c < L && i < rows.nr) bv[u] = Xg[(size_t)rows.global(i) * ldx + xc0 + (c - kPb)];
+                else bv[u] = 0.0;
             }
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
         }
         if (c < L) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) out[(size_t)(4 * r + k_l) * L + c] = acc[r];
+            for (int r = 0; r < 4; ++r) ll_put(out + 2 * ((size_t)(4 * r + k_l) * L + c), acc[r], tag);
         }
     }
 }
@@ -205,24 +248,37 @@ __device__ void panel_update(const VF& V, const Rows& rows, int ilo, double* Xg,
     }
 }
 
-// Sum of the P partial products part[q][0:E] (q = 0..P-1, fixed order) for the
-// entries owned by this workgroup (a contiguous chunk of E / P), into sum.
-__device__ void reduce_chunk(const double* part, double* sum, int P, int p, int E, double* red) {
+// Sum of the P partial products part[q][0:E] (q = 0..P-1, in that order) for
+// the entries owned by this workgroup (a contiguous chunk of E / P), sent on
+// to sum.  Entries are spread over ew lanes and the partial products over
+// 512 / ew thread groups (at most 32 per thread, received 16 at a time).
+__device__ void reduce_chunk(const u64* part, u64* sum, int P, int p, int E, unsigned tag_in,
+                             unsigned tag_out, double* red, int* err) {
     const int tid = threadIdx.x;
     const int chunk = (E + P - 1) / P;
     const int e0 = p * chunk, e1 = min(E, e0 + chunk);
-    const int el = tid & 63, g = tid >> 6;
-    for (int base = e0; base < e1; base += 64) {
+    const int ew = chunk <= 16 ? 16 : (chunk <= 32 ? 32 : 64);
+    const int ng = kQrThreads / ew;
+    const int el = tid % ew, g = tid / ew;
+    const int cnt = g < P ? (P - g + ng - 1) / ng : 0;
+    for (int base = e0; base < e1; base += ew) {
         const int e = base + el;
         double a = 0.0;
-        if (e < e1)
-            for (int q = g; q < P; q += kWaves) a += part[(size_t)q * E + e];
-        red[g * 64 + el] = a;
+        if (e < e1) {
+            for (int k0 = 0; k0 < cnt; k0 += 16) {
+                double v[16];
+                const int nk = min(16, cnt - k0);
+                ll_get<16>([&](int k) { return part + 2 * ((size_t)(g + (k0 + k) * ng) * E + e); },
+                           nk, tag_in, v, err);
+                for (int k = 0; k < nk; ++k) a += v[k];
+            }
+        }
+        red[g * ew + el] = a;
         __syncthreads();
-        if (tid < 64 && e < e1) {
+        if (tid < ew && base + tid < e1) {
             double s = 0.0;
-            for (int gg = 0; gg < kWaves; ++gg) s += red[gg * 64 + tid];
-            sum[e] = s;
+            for (int gg = 0; gg < ng; ++gg) s += red[gg * ew + tid];
+            ll_put(sum + 2 * (size_t)(base + tid), s, tag_out);
         }
         __syncthreads();
     }
@@ -256,17 +312,53 @@ __device__ void form_t(const double* G, const double* tau, int nb, double* T) {
     }
 }
 
+// From the reduced products redsum (16 x L, L = 16 + nx, sent with tag): G (the
+// first 16 columns) into LDS and column tid of W = redsum[:, 16:] into
+// registers in one round of loads, T by the first wave, then column tid of
+// Y = T^T W (trans) or Y = T W into Ys (16 x nx, row stride nx).  nx <= the
+// thread count.
+__device__ void form_y(const u64* redsum, int L, int nx, unsigned tag, const double* tau, int nb,
+                       bool trans, double* Gs, double* Ts, double* Ys, int* err) {
+    const int tid = threadIdx.x;
+    double w[kPb];
+    if (tid < kPb * kPb) {
+        ll_get<1>([&](int) { return redsum + 2 * ((size_t)(tid / kPb) * L + (tid % kPb)); }, 1, tag,
+                  w, err);
+        Gs[tid] = w[0];
+    }
+    if (tid < nx)
+        ll_get<kPb>([&](int r) { return redsum + 2 * ((size_t)r * L + kPb + tid); }, kPb, tag, w, err);
+    __syncthreads();
+    form_t(Gs, tau, nb, Ts);
+    __syncthreads();
+    if (tid < nx) {
+#pragma unroll
+        for (int q = 0; q < kPb; ++q) {
+            double y = 0.0;
+            if (trans) {
+#pragma unroll
+                for (int r = 0; r <= q; ++r) y += Ts[r * kPb + q] * w[r];
+            } else {
+#pragma unroll
+                for (int r = q; r < kPb; ++r) y += Ts[q * kPb + r] * w[r];
+            }
+            Ys[(size_t)q * nx + tid] = y;
+        }
+    }
+    __syncthreads();
+}
+
 struct QrArgs {
     const double* M;
     int m, n;
     double* A;       // m x n working copy (rows owned cyclically)
     double* Q;       // m x n output (may alias M)
     double* R;       // n x n output
-    double* part;    // 2 x P x 16 column partial sums
-    double* rowbuf;  // 2 x 16 pivot-row entries
-    double* red;     // P x 16 x (16 + n) partial products
-    double* redsum;  // 16 x (16 + n) reduced products
-    unsigned* flags; // P x kFlagStride
+    // exchange buffers (two words per double, see ll_put)
+    u64* part;       // 2 x P x 16 column partial sums
+    u64* rowbuf;     // 2 x 16 pivot-row entries
+    u64* red;        // P x 16 x (16 + n) partial products
+    u64* redsum;     // 16 x (16 + n) reduced products
     double* ratio;   // min |R_ii| / max |R_ii|
     int* err;
 };
@@ -285,8 +377,13 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
     double* wv = red + kRowGroups * kPb;       // 16
     double* rowj = wv + kPb;                   // 16
     double* tau = rowj + kPb;                  // n
-    unsigned ep = 0;
     double bmin = INFINITY, bmax = 0.0;
+    const int npanel = (n + kPb - 1) / kPb;
+    // exchange tags: column round j, then two per panel for the trailing
+    // updates and two per panel for the formation of Q
+    auto tag_round = [&](int j) { return (unsigned)(1 + j); };
+    auto tag_trail = [&](int pk) { return (unsigned)(n + 1 + 2 * pk); };
+    auto tag_q = [&](int pk) { return (unsigned)(n + 1 + 2 * npanel + 2 * pk); };
 
     // working copy of this workgroup's rows
     for (int e = tid; e < rows.nr * n; e += kQrThreads) {
@@ -295,8 +392,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
     }
     __syncthreads();
 
-    const int cl = tid % kPb, rg = tid / kPb;
-    const int npanel = (n + kPb - 1) / kPb;
+    const int cl = tid % kPb, rg = tid / kPb, lane = tid & 63, wave = tid >> 6;
     for (int pk = 0; pk < npanel; ++pk) {
         const int c0 = pk * kPb, nb = min(kPb, n - c0), c1 = c0 + nb;
         const int ilo = rows.first_at_or_after(c0);
@@ -313,31 +409,48 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
                 const double x = Pn[i * kPb];
                 const double v = Pn[i * kPb + cl];
                 if (gi > c0) acc += x * v;
-                if (gi == c0) a.rowbuf[(size_t)(c0 & 1) * kPb + cl] = v;
+                if (gi == c0) ll_put(a.rowbuf + 2 * ((size_t)(c0 & 1) * kPb + cl), v, tag_round(c0));
             }
-            red[rg * kPb + cl] = acc;
+            acc = quarter_sum(acc);
+            if (lane < kPb) red[wave * kPb + lane] = acc;
             __syncthreads();
-            if (tid < kPb)  {
+            if (tid < kPb) {
                 double s = 0.0;
-                for (int g = 0; g < kRowGroups; ++g) s += red[g * kPb + tid];
-                a.part[((size_t)(c0 & 1) * P + p) * kPb + tid] = s;
+                for (int w = 0; w < kWaves; ++w) s += red[w * kPb + tid];
+                ll_put(a.part + 2 * (((size_t)(c0 & 1) * P + p) * kPb + tid), s, tag_round(c0));
             }
         }
         for (int q = 0; q < nb; ++q) {
             const int j = c0 + q;
             const int buf = j & 1;
-            flag_barrier(a.flags, P, ++ep, a.err);
+            __syncthreads();  // the previous reduction's reads of red are done
             // combine: slot s = column j + s (slot 0: squared norm below j)
             {
-                const int s = tid % kPb, g = tid / kPb;
-                double acc = 0.0;
-                for (int w = g; w < P; w += kRowGroups) acc += a.part[((size_t)buf * P + w) * kPb + s];
-                red[g * kPb + s] = acc;
-                if (tid < kPb) rowj[tid] = a.rowbuf[(size_t)buf * kPb + tid];
+                // row group rg sums workgroups rg, rg + 32, ... (all loads
+                // issued before the first add), then the four groups of a
+                // wave, then the eight waves
+                // (only the slots s < nb - q of this round are sent)
+                double v[kMaxWg / kRowGroups];
+                const int nw = (rg < P && cl < nb - q) ? (P - rg + kRowGroups - 1) / kRowGroups : 0;
+#pragma unroll
+                for (int k = 0; k < kMaxWg / kRowGroups; ++k) v[k] = 0.0;
+                ll_get<kMaxWg / kRowGroups>(
+                    [&](int k) { return a.part + 2 * (((size_t)buf * P + rg + kRowGroups * k) * kPb + cl); },
+                    nw, tag_round(j), v, a.err);
+                double acc = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+                acc = quarter_sum(acc);
+                if (lane < kPb) red[wave * kPb + lane] = acc;
+                // pivot row j, panel columns q .. nb - 1 (the ones sent)
+                if (tid >= 64 + q && tid < 64 + nb) {
+                    double r1[1];
+                    ll_get<1>([&](int) { return a.rowbuf + 2 * ((size_t)buf * kPb + tid - 64); }, 1,
+                              tag_round(j), r1, a.err);
+                    rowj[tid - 64] = r1[0];
+                }
                 __syncthreads();
                 if (tid < kPb) {
                     double t = 0.0;
-                    for (int gg = 0; gg < kRowGroups; ++gg) t += red[gg * kPb + tid];
+                    for (int w = 0; w < kWaves; ++w) t += red[w * kPb + tid];
                     wv[tid] = t;
                 }
                 __syncthreads();
@@ -355,10 +468,12 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
                 gamma = alpha <= 0.0 ? alpha - beta : -sigma2 / (alpha + beta);
                 t = -gamma / beta;
             }
-            // w_k = v^T a_k over rows >= j for the panel columns k > j
+            // v = x / gamma below j (as a product with the reciprocal); w_k =
+            // v^T a_k over rows >= j for the panel columns k > j
+            const double rgam = 1.0 / gamma;
             auto wcol = [&](int qq) {  // panel column qq > q
                 const double rj = rowj[qq];
-                return mode == 2 ? wv[qq - q] / gamma + rj : rj;
+                return mode == 2 ? wv[qq - q] * rgam + rj : rj;
             };
             if (tid == 0) {
                 tau[j] = t;
@@ -385,7 +500,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
                 const int gi = rows.global(i);
                 double* row = Pn + i * kPb;
                 const double xj = row[q];
-                const double v = gi > j ? (mode == 2 ? xj / gamma : 0.0) : 1.0;
+                const double v = gi > j ? (mode == 2 ? xj * rgam : 0.0) : 1.0;
                 const double tv = t * v;
                 const double x1 = next ? row[q + 1] - tv * w1 : 0.0;
                 if (cl == q && gi > j) row[q] = v;
@@ -393,17 +508,20 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
                     const double u = row[cl] - tv * wc;
                     row[cl] = u;
                     if (gi > j + 1) acc += x1 * u;
-                    if (gi == j + 1) a.rowbuf[(size_t)((j + 1) & 1) * kPb + cl] = u;
+                    if (gi == j + 1)
+                        ll_put(a.rowbuf + 2 * ((size_t)((j + 1) & 1) * kPb + cl), u, tag_round(j + 1));
                 }
             }
             if (next) {
-                red[rg * kPb + cl] = acc;
+                acc = quarter_sum(acc);
+                if (lane < kPb) red[wave * kPb + lane] = acc;
                 __syncthreads();
-                if (tid < kPb) {
+                if (tid < kPb && tid > q) {
                     double s = 0.0;
-                    if (tid > q) for (int g = 0; g < kRowGroups; ++g) s += red[g * kPb + tid];
+                    for (int w = 0; w < kWaves; ++w) s += red[w * kPb + tid];
                     // slot tid - (q + 1) for column j + 1 + (tid - q - 1)
-                    if (tid > q) a.part[((size_t)((j + 1) & 1) * P + p) * kPb + (tid - q - 1)] = s;
+                    ll_put(a.part + 2 * (((size_t)((j + 1) & 1) * P + p) * kPb + (tid - q - 1)), s,
+                           tag_round(j + 1));
                 }
             }
         }
@@ -416,29 +534,10 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
         if (c1 < n) {
             const int nt = n - c1, L = kPb + nt;
             PanelV V{Pn, kPb, rows, c0, nb};
-            panel_vt_x(V, rows, ilo, a.A, n, c1, nt, a.red + (size_t)p * kPb * L);
-            flag_barrier(a.flags, P, ++ep, a.err);
-            reduce_chunk(a.red, a.redsum, P, p, kPb * L, red);
-            flag_barrier(a.flags, P, ++ep, a.err);
-            for (int e = tid; e < kPb * kPb; e += kQrThreads)
-                Gs[e] = a.redsum[(size_t)(e / kPb) * L + (e % kPb)];
-            __syncthreads();
-            form_t(Gs, tau + c0, nb, Ts);
-            __syncthreads();
-            // Y = T^T W, W = V^T A_trail (columns kPb.. of the reduced product)
-            for (int c = tid; c < nt; c += kQrThreads) {
-                double w[kPb];
-#pragma unroll
-                for (int r = 0; r < kPb; ++r) w[r] = a.redsum[(size_t)r * L + kPb + c];
-#pragma unroll
-                for (int q = 0; q < kPb; ++q) {
-                    double y = 0.0;
-#pragma unroll
-                    for (int r = 0; r <= q; ++r) y += Ts[r * kPb + q] * w[r];
-                    Ys[(size_t)q * nt + c] = y;
-                }
-            }
-            __syncthreads();
+            panel_vt_x(V, rows, ilo, a.A, n, c1, nt, a.red + 2 * (size_t)p * kPb * L, tag_trail(pk));
+            reduce_chunk(a.red, a.redsum, P, p, kPb * L, tag_trail(pk), tag_trail(pk) + 1, red, a.err);
+            // Y = T^T W, W = V^T A_trail
+            form_y(a.redsum, L, nt, tag_trail(pk) + 1, tau + c0, nb, true, Gs, Ts, Ys, a.err);
             panel_update(V, rows, ilo, a.A, n, c1, nt, Ys);
             __syncthreads();
             // rows c0..c1-1 are final beyond the panel: they are R's rows there
@@ -463,37 +562,20 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
         const int nq = n - c0, L = kPb + nq;
         const int ilo = rows.first_at_or_after(c0);
         GlobalV VG{a.A, n, rows, c0, nb};
-        panel_vt_x(VG, rows, ilo, a.Q, n, c0, nq, a.red + (size_t)p * kPb * L);
-        flag_barrier(a.flags, P, ++ep, a.err);
-        reduce_chunk(a.red, a.redsum, P, p, kPb * L, red);
-        flag_barrier(a.flags, P, ++ep, a.err);
-        for (int e = tid; e < kPb * kPb; e += kQrThreads)
-            Gs[e] = a.redsum[(size_t)(e / kPb) * L + (e % kPb)];
-        __syncthreads();
-        form_t(Gs, tau + c0, nb, Ts);
-        __syncthreads();
-        // Y = T W
-        for (int c = tid; c < nq; c += kQrThreads) {
-            double w[kPb];
-#pragma unroll
-            for (int r = 0; r < kPb; ++r) w[r] = a.redsum[(size_t)r * L + kPb + c];
-#pragma unroll
-            for (int q = 0; q < kPb; ++q) {
-                double y = 0.0;
-#pragma unroll
-                for (int r = q; r < kPb; ++r) y += Ts[q * kPb + r] * w[r];
-                Ys[(size_t)q * nq + c] = y;
-            }
-        }
-        __syncthreads();
+        panel_vt_x(VG, rows, ilo, a.Q, n, c0, nq, a.red + 2 * (size_t)p * kPb * L, tag_q(pk));
+        reduce_chunk(a.red, a.redsum, P, p, kPb * L, tag_q(pk), tag_q(pk) + 1, red, a.err);
+        // Y = T W, W = V^T Q
+        form_y(a.redsum, L, nq, tag_q(pk) + 1, tau + c0, nb, false, Gs, Ts, Ys, a.err);
         panel_update(VG, rows, ilo, a.Q, n, c0, nq, Ys);
         __syncthreads();
     }
 }
 
-__global__ void zero_flags_kernel(unsigned* flags, int count) {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x)
-        flags[e] = 0u;
+// Tag 0 into the exchange buffers (a range of 64-bit words).
+__global__ void clear_words_kernel(u64* w, long long count) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+         e += (long long)gridDim.x * blockDim.x)
+        w[e] = 0ull;
 }
 
 }  // namespace
@@ -509,11 +591,12 @@ QrScratch qr_scratch_layout(int m, int n) {
     };
     const size_t w = kPb + (size_t)n;
     s.off_A = take(sizeof(double) * (size_t)m * n);
-    s.off_part = take(sizeof(double) * 2 * (size_t)L.P * kPb);
-    s.off_rowbuf = take(sizeof(double) * 2 * kPb);
-    s.off_red = take(sizeof(double) * (size_t)L.P * kPb * w);
-    s.off_redsum = take(sizeof(double) * kPb * w);
-    s.off_flags = take(sizeof(unsigned) * (size_t)L.P * kFlagStride);
+    // the exchange buffers are one contiguous range (cleared before each launch)
+    s.off_part = take(2 * sizeof(u64) * 2 * (size_t)L.P * kPb);
+    s.off_rowbuf = take(2 * sizeof(u64) * 2 * kPb);
+    s.off_red = take(2 * sizeof(u64) * (size_t)L.P * kPb * w);
+    s.off_redsum = take(2 * sizeof(u64) * kPb * w);
+    s.off_xend = off;
     s.off_ratio = take(sizeof(double));
     s.off_err = take(sizeof(int));
     s.total = off;
@@ -549,11 +632,10 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     a.A = reinterpret_cast<double*>(base + S.off_A);
     a.Q = Q;
     a.R = R;
-    a.part = reinterpret_cast<double*>(base + S.off_part);
-    a.rowbuf = reinterpret_cast<double*>(base + S.off_rowbuf);
-    a.red = reinterpret_cast<double*>(base + S.off_red);
-    a.redsum = reinterpret_cast<double*>(base + S.off_redsum);
-    a.flags = reinterpret_cast<unsigned*>(base + S.off_flags);
+    a.part = reinterpret_cast<u64*>(base + S.off_part);
+    a.rowbuf = reinterpret_cast<u64*>(base + S.off_rowbuf);
+    a.red = reinterpret_cast<u64*>(base + S.off_red);
+    a.redsum = reinterpret_cast<u64*>(base + S.off_redsum);
     a.ratio = diag_ratio_dev ? diag_ratio_dev : reinterpret_cast<double*>(base + S.off_ratio);
     a.err = err_dev ? err_dev : reinterpret_cast<int*>(base + S.off_err);
 
@@ -571,10 +653,10 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
         s.msg = "qr: cooperative grid does not fit on the device";
         return s;
     }
-    const int nflags = L.P * kFlagStride;
-    hipLaunchKernelGGL(zero_flags_kernel, dim3((nflags + 255) / 256), dim3(256), 0, st, a.flags,
-                       nflags);
-    QRCTM_TRY(launch_check("zero_flags_kernel"));
+    const long long nwords = (long long)((S.off_xend - S.off_part) / sizeof(u64));
+    hipLaunchKernelGGL(clear_words_kernel, dim3((unsigned)std::min<long long>(ceil_div(nwords, 256), 2048)),
+                       dim3(256), 0, st, a.part, nwords);
+    QRCTM_TRY(launch_check("clear_words_kernel"));
     void* args[] = {(void*)&a};
     QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_kernel, dim3(L.P), dim3(kQrThreads), args,
                                          L.lds_bytes, st));
