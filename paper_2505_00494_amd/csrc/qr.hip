@@ -20,9 +20,10 @@
 //  * after a panel, the trailing columns get the panel's reflectors in compact
 //    WY form, I - V T V^T: V^T [V | A_trail] is reduced over all rows (FP64
 //    matrix-core tiles per workgroup, then a reduction of the partial products
-//    spread over the workgroups), T follows from V^T V and the tau's by the
-//    forward recurrence, and A_trail -= V (T^T (V^T A_trail)) is a matrix-core
-//    update of each workgroup's own rows;
+//    spread over the workgroups), T^T (V^T A_trail) follows from V^T V and the
+//    tau's by substitution (T itself is never formed), and
+//    A_trail -= V (T^T (V^T A_trail)) is a matrix-core update of each
+//    workgroup's own rows;
 //  * the explicit thin factor Q = H_0 ... H_{n-1} [I; 0] is formed in the same
 //    kernel by applying the panels in reverse order to [I; 0], with the same
 //    reduction pattern.
@@ -68,9 +69,9 @@ struct QrPlan {
 };
 
 size_t lds_doubles(int rb, int n) {
-    // panel rows + Y (16 x n) + G, T (16 x 16 each) + reduction scratch
-    // (32 x 16) + w, pivot row (16 each) + tau (n) + scalars
-    return (size_t)rb * kPb + (size_t)kPb * n + 2 * kPb * kPb + kRowGroups * kPb + 2 * kPb +
+    // panel rows + Y (16 x n) + G (16 x 16) + reduction scratch (32 x 16)
+    // + w, pivot row (16 each) + tau (n) + scalars
+    return (size_t)rb * kPb + (size_t)kPb * n + kPb * kPb + kRowGroups * kPb + 2 * kPb +
            (size_t)n + 8;
 }
 
@@ -89,7 +90,7 @@ typedef unsigned long long u64;
 
 // A double sent to other workgroups: word 0 holds the low 32 bits, word 1 the
 // high 32 bits, each with the tag in its upper half.
-__device__ void ll_put(u64* w, double v, unsigned tag) {
+__device__ __forceinline__ void ll_put(u64* w, double v, unsigned tag) {
     const u64 b = (u64)__double_as_longlong(v);
     const u64 t = (u64)tag << 32;
     __hip_atomic_store(w, (b & 0xffffffffull) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -100,7 +101,7 @@ __device__ void ll_put(u64* w, double v, unsigned tag) {
 // pending pairs are loaded in one round, those with both tags right are taken,
 // the rest polled again.  On timeout the missing values are 0 and err gets 2.
 template <int N, class Addr>
-__device__ void ll_get(const Addr& addr, int n, unsigned tag, double* out, int* err) {
+__device__ __forceinline__ void ll_get(const Addr& addr, int n, unsigned tag, double* out, int* err) {
     unsigned pending = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
     unsigned spins = 0;
     while (pending) {
@@ -133,7 +134,7 @@ __device__ void ll_get(const Addr& addr, int n, unsigned tag, double* out, int* 
 
 // Sum of v over the four lanes of a wave that share lane % 16 (the four row
 // groups of a wave), in a fixed order; every lane gets the sum.
-__device__ double quarter_sum(double v) {
+__device__ __forceinline__ double quarter_sum(double v) {
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
     return v;
@@ -142,9 +143,9 @@ __device__ double quarter_sum(double v) {
 // Everything a workgroup needs to address its rows.
 struct Rows {
     int p, P, nr;  // workgroup, workgroups, rows held (local i <-> global p + i P)
-    __device__ int global(int i) const { return p + i * P; }
+    __device__ __forceinline__ int global(int i) const { return p + i * P; }
     // first local row with global index >= g
-    __device__ int first_at_or_after(int g) const {
+    __device__ __forceinline__ int first_at_or_after(int g) const {
         if (g <= p) return 0;
         return (g - p + P - 1) / P;
     }
@@ -158,7 +159,7 @@ struct PanelV {
     long long ld;
     Rows rows;
     int c0, nb;
-    __device__ double operator()(int i, int q) const {
+    __device__ __forceinline__ double operator()(int i, int q) const {
         if (i >= rows.nr || q >= nb) return 0.0;
         const int gi = rows.global(i), jq = c0 + q;
         if (gi > jq) return base[(size_t)i * ld + q];
@@ -173,7 +174,7 @@ struct GlobalV {
     int n;
     Rows rows;
     int c0, nb;
-    __device__ double operator()(int i, int q) const {
+    __device__ __forceinline__ double operator()(int i, int q) const {
         if (i >= rows.nr || q >= nb) return 0.0;
         const int gi = rows.global(i), jq = c0 + q;
         if (gi > jq) return A[(size_t)gi * n + jq];
@@ -186,7 +187,7 @@ struct GlobalV {
 // cores: one 16 x 16 output tile per wave at a time, 4 rows per MFMA, the
 // operands of 16 rows loaded before the four MFMAs that use them.
 template <class VF>
-__device__ void panel_vt_x(const VF& V, const Rows& rows, int ilo, const double* Xg, int ldx,
+__device__ __forceinline__ void panel_vt_x(const VF& V, const Rows& rows, int ilo, const double* Xg, int ldx,
                            int xc0, int nx, u64* out, unsigned tag) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int L = kPb + nx;
@@ -219,7 +220,7 @@ __device__ void panel_vt_x(const VF& V, const Rows& rows, int ilo, const double*
 // (Y is 16 x nx in LDS, row stride nx), on the FP64 matrix cores: 16 x 16
 // tiles, K = 16 in four steps.
 template <class VF>
-__device__ void panel_update(const VF& V, const Rows& rows, int ilo, double* Xg, int ldx, int xc0,
+__device__ __forceinline__ void panel_update(const VF& V, const Rows& rows, int ilo, double* Xg, int ldx, int xc0,
                              int nx, const double* Y) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nrt = (rows.nr - ilo + 15) / 16, nct = (nx + 15) / 16;
@@ -252,7 +253,7 @@ __device__ void panel_update(const VF& V, const Rows& rows, int ilo, double* Xg,
 // the entries owned by this workgroup (a contiguous chunk of E / P), sent on
 // to sum.  Entries are spread over ew lanes and the partial products over
 // 512 / ew thread groups (at most 32 per thread, received 16 at a time).
-__device__ void reduce_chunk(const u64* part, u64* sum, int P, int p, int E, unsigned tag_in,
+__device__ __forceinline__ void reduce_chunk(const u64* part, u64* sum, int P, int p, int E, unsigned tag_in,
                              unsigned tag_out, double* red, int* err) {
     const int tid = threadIdx.x;
     const int chunk = (E + P - 1) / P;
@@ -284,41 +285,19 @@ __device__ void reduce_chunk(const u64* part, u64* sum, int P, int p, int E, uns
     }
 }
 
-// Upper-triangular T of H_{c0} ... H_{c0+nb-1} = I - V T V^T from G = V^T V
-// (16 x 16 in LDS) and tau: T[q][q] = tau_q, T[r][q] = -tau_q sum_l T[r][l] G[l][q]
-// (the forward recurrence).  Lane r of the first wave computes row r alone.
-__device__ void form_t(const double* G, const double* tau, int nb, double* T) {
-    const int r = threadIdx.x;
-    if (r < kPb) {
-        double tr[kPb];
-#pragma unroll
-        for (int q = 0; q < kPb; ++q) {
-            double v = 0.0;
-            if (q < nb) {
-                if (r == q) {
-                    v = tau[q];
-                } else if (r < q) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int l = 0; l < q; ++l)
-                        if (l >= r) s += tr[l] * G[l * kPb + q];
-                    v = -tau[q] * s;
-                }
-            }
-            tr[q] = v;
-        }
-#pragma unroll
-        for (int q = 0; q < kPb; ++q) T[r * kPb + q] = tr[q];
-    }
-}
-
-// From the reduced products redsum (16 x L, L = 16 + nx, sent with tag): G (the
-// first 16 columns) into LDS and column tid of W = redsum[:, 16:] into
-// registers in one round of loads, T by the first wave, then column tid of
-// Y = T^T W (trans) or Y = T W into Ys (16 x nx, row stride nx).  nx <= the
-// thread count.
-__device__ void form_y(const u64* redsum, int L, int nx, unsigned tag, const double* tau, int nb,
-                       bool trans, double* Gs, double* Ts, double* Ys, int* err) {
+// Y = T^T W (trans) or Y = T W, where I - V T V^T = H_{c0} ... H_{c0+nb-1} in
+// compact WY form, without forming T: from the recurrences that define T,
+// column by column (T[q][q] = tau_q, T[0:q, q] = -tau_q T[0:q, 0:q] G[0:q, q])
+// or row by row (T[q, q+1:] = -tau_q G[q, q+1:] T[q+1:, q+1:]), with G = V^T V,
+//   (T^T W)[q] = tau_q (W[q] - sum_{l<q} G[l][q] (T^T W)[l])   (forward),
+//   (T W)[q]   = tau_q (W[q] - sum_{l>q} G[q][l] (T W)[l])     (backward).
+// The reduced products redsum (16 x L, L = 16 + nx, sent with tag) hold G in
+// their first 16 columns and W after them: G goes to LDS and column tid of W to
+// registers in one round of loads; thread tid < nx then writes column tid of Y
+// into Ys (16 x nx, row stride nx).  nx <= the thread count.
+__device__ __forceinline__ void form_y(const u64* redsum, int L, int nx, unsigned tag,
+                                       const double* tau, int nb, bool trans, double* Gs,
+                                       double* Ys, int* err) {
     const int tid = threadIdx.x;
     double w[kPb];
     if (tid < kPb * kPb) {
@@ -329,21 +308,27 @@ __device__ void form_y(const u64* redsum, int L, int nx, unsigned tag, const dou
     if (tid < nx)
         ll_get<kPb>([&](int r) { return redsum + 2 * ((size_t)r * L + kPb + tid); }, kPb, tag, w, err);
     __syncthreads();
-    form_t(Gs, tau, nb, Ts);
-    __syncthreads();
     if (tid < nx) {
+        double y[kPb];
+        if (trans) {
 #pragma unroll
-        for (int q = 0; q < kPb; ++q) {
-            double y = 0.0;
-            if (trans) {
+            for (int q = 0; q < kPb; ++q) {
+                double s = w[q];
 #pragma unroll
-                for (int r = 0; r <= q; ++r) y += Ts[r * kPb + q] * w[r];
-            } else {
-#pragma unroll
-                for (int r = q; r < kPb; ++r) y += Ts[q * kPb + r] * w[r];
+                for (int l = 0; l < q; ++l) s -= Gs[l * kPb + q] * y[l];
+                y[q] = q < nb ? tau[q] * s : 0.0;
             }
-            Ys[(size_t)q * nx + tid] = y;
+        } else {
+#pragma unroll
+            for (int q = kPb - 1; q >= 0; --q) {
+                double s = w[q];
+#pragma unroll
+                for (int l = q + 1; l < kPb; ++l) s -= Gs[q * kPb + l] * y[l];
+                y[q] = q < nb ? tau[q] * s : 0.0;
+            }
         }
+#pragma unroll
+        for (int q = 0; q < kPb; ++q) Ys[(size_t)q * nx + tid] = y[q];
     }
     __syncthreads();
 }
@@ -363,7 +348,11 @@ struct QrArgs {
     int* err;
 };
 
-__global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
+__global__ __launch_bounds__(kQrThreads) void qr_kernel(
+    const double* M, int m_, int n_, double* __restrict__ Aw, double* Qo, double* __restrict__ Ro,
+    u64* __restrict__ part, u64* __restrict__ rowbuf, u64* __restrict__ redp,
+    u64* __restrict__ redsum, double* __restrict__ ratio, int* __restrict__ err) {
+    QrArgs a{M, m_, n_, Aw, Qo, Ro, part, rowbuf, redp, redsum, ratio, err};
     extern __shared__ double lds[];
     const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
     const int m = a.m, n = a.n;
@@ -372,8 +361,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
     double* Pn = lds;                          // rbmax x 16 panel rows
     double* Ys = Pn + (size_t)rbmax * kPb;     // 16 x n
     double* Gs = Ys + (size_t)kPb * n;         // 16 x 16
-    double* Ts = Gs + kPb * kPb;               // 16 x 16
-    double* red = Ts + kPb * kPb;              // 32 x 16
+    double* red = Gs + kPb * kPb;              // 32 x 16
     double* wv = red + kRowGroups * kPb;       // 16
     double* rowj = wv + kPb;                   // 16
     double* tau = rowj + kPb;                  // n
@@ -537,7 +525,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
             panel_vt_x(V, rows, ilo, a.A, n, c1, nt, a.red + 2 * (size_t)p * kPb * L, tag_trail(pk));
             reduce_chunk(a.red, a.redsum, P, p, kPb * L, tag_trail(pk), tag_trail(pk) + 1, red, a.err);
             // Y = T^T W, W = V^T A_trail
-            form_y(a.redsum, L, nt, tag_trail(pk) + 1, tau + c0, nb, true, Gs, Ts, Ys, a.err);
+            form_y(a.redsum, L, nt, tag_trail(pk) + 1, tau + c0, nb, true, Gs, Ys, a.err);
             panel_update(V, rows, ilo, a.A, n, c1, nt, Ys);
             __syncthreads();
             // rows c0..c1-1 are final beyond the panel: they are R's rows there
@@ -565,7 +553,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(QrArgs a) {
         panel_vt_x(VG, rows, ilo, a.Q, n, c0, nq, a.red + 2 * (size_t)p * kPb * L, tag_q(pk));
         reduce_chunk(a.red, a.redsum, P, p, kPb * L, tag_q(pk), tag_q(pk) + 1, red, a.err);
         // Y = T W, W = V^T Q
-        form_y(a.redsum, L, nq, tag_q(pk) + 1, tau + c0, nb, false, Gs, Ts, Ys, a.err);
+        form_y(a.redsum, L, nq, tag_q(pk) + 1, tau + c0, nb, false, Gs, Ys, a.err);
         panel_update(VG, rows, ilo, a.Q, n, c0, nq, Ys);
         __syncthreads();
     }
@@ -657,7 +645,9 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     hipLaunchKernelGGL(clear_words_kernel, dim3((unsigned)std::min<long long>(ceil_div(nwords, 256), 2048)),
                        dim3(256), 0, st, a.part, nwords);
     QRCTM_TRY(launch_check("clear_words_kernel"));
-    void* args[] = {(void*)&a};
+    void* args[] = {(void*)&a.M,    (void*)&a.m,     (void*)&a.n,   (void*)&a.A,
+                    (void*)&a.Q,    (void*)&a.R,     (void*)&a.part, (void*)&a.rowbuf,
+                    (void*)&a.red,  (void*)&a.redsum, (void*)&a.ratio, (void*)&a.err};
     QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_kernel, dim3(L.P), dim3(kQrThreads), args,
                                          L.lds_bytes, st));
     return s;
