@@ -14,9 +14,10 @@ launch with HIP events on the library's stream in a second pass, for the
 roofline figure.  The CPU baseline is the FP64 oracle on the host cores on a
 bounded sample of the same workload.
 
-Also reported (same tensor): the mixed form (bulk contractions on the FP32
-matrix cores) with its speed-up and energy error against the FP64 path, and
-the time of one dE/dA (k tracked steps, energy and the reverse pass).
+Also reported (same tensor): the mixed forms (bulk contractions on the FP32
+matrix cores, or as split-BF16 products on the bf16 matrix cores) with their
+speed-ups and energy errors against the FP64 path, and the time of one dE/dA
+(k tracked steps, energy and the reverse pass).
 
 Prints ONE JSON line.
 """
@@ -213,41 +214,51 @@ def main():
                      "kernel": "double-layer contraction Z = Y a (3b)",
                      "flops_per_launch": flops_3b(chi, D), "ms_per_launch": ms_3b},
     }
-    # mixed form: same tensor, bulk contractions on FP32 matrix cores
+    # mixed forms: same tensor, bulk contractions on the FP32 matrix cores or
+    # as split-BF16 products on the bf16 matrix cores; QR, normalisation and
+    # spectrum in FP64
     if not args.no_mixed:
         C0, T0 = ctx.get_env()
-        mctx = P.Context(A, chi, precision=P.PREC_FP32_MFMA, n_warmup=0)
-        mctx.set_env(C0, T0)
-        mctx.step(args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mctx.step(args.steps)
-        torch.cuda.synchronize()
-        el_m = time.perf_counter() - t0
-        mctx.set_timing(True)
-        mctx.step(nt)
-        mst = mctx.stats()
-        mctx.set_timing(False)
-        ms_m = {k: v / mst["timed_steps"] for k, v in mst["ms_phase"].items()}
-        # accuracy: the same number of steps from the same environment, energy
-        # from the FP64 energy contraction
         h = inp.heisenberg_bond_rotated()
         nacc = args.acc_steps
         ctx.set_env(C0, T0)
         ctx.step(nacc)
         e64 = ctx.energy(h)
-        mctx.set_env(C0, T0)
-        mctx.step(nacc)
-        e32 = mctx.energy(h)
-        out["mixed"] = {"precision": "fp32 matrix cores (FP32 products and accumulation); "
-                                     "QR, normalisation, spectrum FP64",
+        for key, prec, desc in (
+                ("mixed", P.PREC_FP32_MFMA,
+                 "fp32 matrix cores (FP32 products and accumulation); QR, normalisation, "
+                 "spectrum FP64"),
+                ("mixed_bf16x6", P.PREC_BF16X6_MFMA,
+                 "split-BF16: operands as three bf16 parts, six products, FP32 accumulation "
+                 "(large products; the rest on the fp32 matrix cores); QR, normalisation, "
+                 "spectrum FP64")):
+            mctx = P.Context(A, chi, precision=prec, n_warmup=0)
+            mctx.set_env(C0, T0)
+            mctx.step(args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mctx.step(args.steps)
+            torch.cuda.synchronize()
+            el_m = time.perf_counter() - t0
+            mctx.set_timing(True)
+            mctx.step(nt)
+            mst = mctx.stats()
+            mctx.set_timing(False)
+            ms_m = {k: v / mst["timed_steps"] for k, v in mst["ms_phase"].items()}
+            # accuracy: the same number of steps from the same environment,
+            # energy from the FP64 energy contraction
+            mctx.set_env(C0, T0)
+            mctx.step(nacc)
+            em = mctx.energy(h)
+            out[key] = {"precision": desc,
                         "steps_per_s": args.steps / el_m, "ms_per_step": 1e3 * el_m / args.steps,
                         "speedup_vs_fp64": (args.steps / el_m) / steps_per_s,
                         "ms_per_phase": ms_m,
-                        "energy_fp64": e64, "energy_mixed": e32,
-                        "energy_rel_err_vs_fp64": abs(e32 - e64) / abs(e64),
+                        "tflops_3b_equiv": flops_3b(chi, D) / (ms_m["edge_3b"] * 1e-3) / 1e12,
+                        "energy_fp64": e64, "energy_mixed": em,
+                        "energy_rel_err_vs_fp64": abs(em - e64) / abs(e64),
                         "accuracy_steps": nacc}
-        mctx.close()
+            mctx.close()
     # dE/dA: k tracked steps + energy + reverse pass from the current environment
     if not args.no_grad:
         gctx = P.Context(A, chi, n_warmup=0, k_tracked=args.k)

@@ -50,6 +50,11 @@ extern "C" {
 /* precision of the bulk contractions */
 #define CTM_PREC_FP64      0
 #define CTM_PREC_FP32_MFMA 1
+/* split-BF16: each FP64 operand rounded to FP32 and split exactly into three
+   bf16 parts; six bf16 products (all terms down to 2^-24 relative) with FP32
+   accumulation on the bf16 matrix cores.  Used for the large products of the
+   step (3a, 3b at the usual sizes); the smaller ones take the FP32 path. */
+#define CTM_PREC_BF16X6_MFMA 2
 
 typedef struct ctm_ctx ctm_ctx;
 

@@ -1,6 +1,6 @@
 """QR-CTMRG on MI355X: HIP kernels behind a C ABI (libqrctm.so) and a thin binding."""
-from .qrctm import (CTMError, Context, PREC_FP32_MFMA, PREC_FP64, energy, gemm,
-                    header_functions, lib, qr)
+from .qrctm import (CTMError, Context, PREC_BF16X6_MFMA, PREC_FP32_MFMA, PREC_FP64, energy,
+                    gemm, header_functions, lib, qr)
 
-__all__ = ["CTMError", "Context", "PREC_FP32_MFMA", "PREC_FP64", "energy", "gemm",
+__all__ = ["CTMError", "Context", "PREC_BF16X6_MFMA", "PREC_FP32_MFMA", "PREC_FP64", "energy", "gemm",
            "header_functions", "lib", "qr"]

@@ -52,6 +52,23 @@ inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 // A plain row-major C with leading dimension ldc is mdiv = M, ms2 = ldc,
 // ndiv = N, ns2 = 1.
 // ---------------------------------------------------------------------------
+// x (FP32) = hi + mid + lo exactly, each a bf16 (round to nearest even; the
+// remainders x - hi and x - hi - mid are exact in FP32).  Bit patterns.
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short h) {
+    return __uint_as_float((unsigned)h << 16);
+}
+__device__ __forceinline__ void bf16_split3(float x, unsigned short& h, unsigned short& m,
+                                            unsigned short& l) {
+    h = bf16_rne(x);
+    const float r1 = x - bf16_value(h);
+    m = bf16_rne(r1);
+    l = bf16_rne(r1 - bf16_value(m));
+}
+
 struct OutMap {
     long long mdiv, ms1, ms2, ndiv, ns1, ns2;
     static OutMap plain(long long M, long long N, long long ldc) {
@@ -69,12 +86,30 @@ struct GemmDesc {
     double* C = nullptr;
     OutMap map{};
     double alpha = 1.0, beta = 0.0;
-    int prec = 0;  // 0: FP64 matrix cores; 1: FP32 products and accumulation
+    int prec = 0;  // 0: FP64 matrix cores; 1: FP32 products and accumulation;
+                   // 2: split-BF16 (six bf16 products, FP32 accumulation) when an
+                   //    operand or the result is given as bf16 planes, else as 1
+    // split-BF16 planes (three bf16 parts; element (row, k) of plane s at
+    // base[s * plane + row * ld + k]): A16 (rows m), B16 (rows n = output
+    // columns), and the split result C16 (plane s at C16[s * pC16 + map(m, n)])
+    const unsigned short* A16 = nullptr;
+    long long lda16 = 0, pA16 = 0;
+    const unsigned short* B16 = nullptr;
+    long long ldb16 = 0, pB16 = 0;
+    unsigned short* C16 = nullptr;
+    long long pC16 = 0;
 };
 
 // Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the
 // shape does not split.
 size_t gemm_splitk_bytes(const GemmDesc& g);
 Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStream_t st);
+// split-BF16 GEMM (gemm_bf16.hip): planes in and FP64 out, or FP64 (transposed
+// A and B) in and planes out; no split-K, no scratch
+Status gemm_bf16x6(const GemmDesc& g, hipStream_t st);
+// out[s][n][k] = part s of X[k][n] (X rows x cols FP64): the split of an
+// operand used as B, transposed so that k is contiguous
+Status split_planes_t(const double* X, long long rows, long long cols, unsigned short* out,
+                      hipStream_t st);
 
 }  // namespace qrctm

@@ -36,6 +36,8 @@ struct Plan {
     // device buffers (byte offsets into the workspace)
     Buf As, a, bvec, C0, C1, T0, T1, Q, R, Y, Z, Tp, W, Cp, S, spec0, spec1, small, normpart, qr,
         splitk, eig, energy, grad;
+    // split-BF16 form: Y and the (transposed) double layer as three bf16 planes
+    Buf Y16, a16;
     size_t total = 0;
     size_t qr_bytes = 0, splitk_bytes = 0, eig_bytes = 0, energy_bytes = 0, grad_bytes = 0;
 };
@@ -216,6 +218,10 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     take(P.energy, P.energy_bytes);
     P.grad_bytes = grad_layout(sh, o.k_tracked).total;
     take(P.grad, P.grad_bytes);
+    // planes need the contraction length Dab^2 to be a multiple of 8 (D even)
+    const bool planes = o.precision == CTM_PREC_BF16X6_MFMA && (Dab * Dab) % 8 == 0;
+    take(P.Y16, planes ? 3 * sizeof(unsigned short) * chi * chi * Dab * Dab : 0);
+    take(P.a16, planes ? 3 * sizeof(unsigned short) * Dab * Dab * Dab * Dab : 0);
     P.total = off;
     return P;
 }
@@ -351,10 +357,24 @@ Status mark(ctm_ctx* c, int i) {
     return hip_status(hipEventRecord(c->ev[i], c->st), "hipEventRecord");
 }
 
+// GEMM precision of the forward step (the reverse pass always runs FP64).
+int step_prec(const ctm_ctx* c) {
+    return c->opts.precision == CTM_PREC_FP32_MFMA    ? 1
+           : c->opts.precision == CTM_PREC_BF16X6_MFMA ? 2
+                                                        : 0;
+}
+
+// The double layer's split-BF16 planes (transposed) after a new tensor.
+Status refresh_planes(ctm_ctx* c) {
+    if (c->plan.a16.bytes == 0) return Status{};
+    const long long D2 = (long long)c->sh.Dab * c->sh.Dab;
+    return split_planes_t(c->ptr(c->plan.a), D2, D2, c->ptr<unsigned short>(c->plan.a16), c->st);
+}
+
 // a5-a9 from (Cin, Tin) into (Cout, Tout); intermediates stay in the step
 // buffers (Q, R, Y, Z, Tp, W, Cp) and the norms in the small-scalar slots.
 Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Cout, double* Tout,
-                    bool timed) {
+                    bool timed, int prec) {
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     StepPtrs p = step_ptrs(c);
     p.C = Cin;
@@ -366,22 +386,43 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     };
     void* sk = c->ptr<void>(c->plan.splitk);
     const size_t skb = c->plan.splitk_bytes;
-    // mixed form: the bulk contractions on FP32 matrix cores; QR, normalisation
-    // and the spectrum stay FP64
-    const int prec = c->opts.precision == CTM_PREC_FP32_MFMA ? 1 : 0;
+    // mixed forms (prec 1, 2): the contractions on the FP32 matrix cores, or
+    // 3a/3b as split-BF16 products through bf16 planes of Y and of the double
+    // layer; QR, normalisation and the spectrum stay FP64
     auto G = [&](GemmDesc g) {
         g.prec = prec;
         return gemm_f64(g, sk, skb, c->st);
     };
+    const bool planes = prec == 2 && c->plan.Y16.bytes > 0;
+    unsigned short* Y16 = planes ? c->ptr<unsigned short>(c->plan.Y16) : nullptr;
     QRCTM_TRY(mark(0));
     QRCTM_TRY(G(g_reduced_corner(p, chi, Dab)));                                       // a5
     QRCTM_TRY(mark(1));
     QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
                      c->st, c->small() + SL_RATIO, c->bad()));                      // a6
     QRCTM_TRY(mark(2));
-    QRCTM_TRY(G(g_edge_a(p, p.Q, chi, chi, Dab)));                                     // a7 3a
+    {
+        GemmDesc ga = g_edge_a(p, p.Q, chi, chi, Dab);                                 // a7 3a
+        if (planes) {
+            ga.C16 = Y16;
+            ga.pC16 = ga.M * ga.N;
+        }
+        QRCTM_TRY(G(ga));
+    }
     QRCTM_TRY(mark(3));
-    QRCTM_TRY(G(g_edge_b(p, chi, chi, Dab)));                                          // a7 3b
+    {
+        GemmDesc gb = g_edge_b(p, chi, chi, Dab);                                      // a7 3b
+        if (planes) {
+            const long long D2 = (long long)Dab * Dab;
+            gb.A16 = Y16;
+            gb.lda16 = D2;
+            gb.pA16 = gb.M * gb.K;
+            gb.B16 = c->ptr<unsigned short>(c->plan.a16);
+            gb.ldb16 = D2;
+            gb.pB16 = D2 * D2;
+        }
+        QRCTM_TRY(G(gb));
+    }
     QRCTM_TRY(mark(4));
     QRCTM_TRY(G(g_edge_c(p, p.Q, chi, chi, Dab)));                                     // a7 3c
     QRCTM_TRY(mark(5));
@@ -399,7 +440,7 @@ Status qr_step_once(ctm_ctx* c) {
     const int chi = c->chi_cur;
     const int target = c->cur ^ 1;  // environment buffer this step writes
     if (c->spec_pending[target]) QRCTM_HIP(hipStreamWaitEvent(c->st, c->ev_specdone[target], 0));
-    QRCTM_TRY(qr_step_core(c, c->C(), c->T(), c->Cn(), c->Tn(), true));
+    QRCTM_TRY(qr_step_core(c, c->C(), c->T(), c->Cn(), c->Tn(), true, step_prec(c)));
     QRCTM_HIP(hipEventRecord(c->ev_normed, c->st));
     QRCTM_HIP(hipStreamWaitEvent(c->aux, c->ev_normed, 0));
     const int slot = (int)(c->steps % kDeltaSlots);
@@ -487,7 +528,7 @@ GradPtrs grad_ptrs(ctm_ctx* c) {
 // intermediates are recomputed first (only (C_i, T_i) are stored).
 Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, const double* Ci, const double* Ti) {
     const int chi = c->chi_cur, Dab = c->sh.Dab;
-    QRCTM_TRY(qr_step_core(c, Ci, Ti, g.Ctmp, g.Ttmp, false));
+    QRCTM_TRY(qr_step_core(c, Ci, Ti, g.Ctmp, g.Ttmp, false, 0));
     StepPtrs sp = step_ptrs(c);
     BwPtrs p;
     p.C = Ci; p.T = Ti; p.a = sp.a; p.Q = sp.Q; p.R = sp.R; p.Y = sp.Y; p.Z = sp.Z; p.Tp = sp.Tp;
@@ -529,7 +570,7 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA) {
     QRCTM_HIP(hipMemcpyAsync(g.ckT, c->T(), nT * 8, hipMemcpyDeviceToDevice, c->st));
     for (int i = 0; i < k; ++i) {
         QRCTM_TRY(qr_step_core(c, g.ckC + i * nC, g.ckT + i * nT, g.ckC + (i + 1) * nC,
-                               g.ckT + (i + 1) * nT, false));
+                               g.ckT + (i + 1) * nT, false, 0));
         QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, i == 0, c->st));
     }
     EnergyArgs ea{};
@@ -615,7 +656,9 @@ Status start_environment(ctm_ctx* c) {
 }
 
 bool valid_opts(const ctm_opts& o) {
-    return (o.precision == CTM_PREC_FP64 || o.precision == CTM_PREC_FP32_MFMA) && o.k_tracked >= 0;
+    return (o.precision == CTM_PREC_FP64 || o.precision == CTM_PREC_FP32_MFMA ||
+            o.precision == CTM_PREC_BF16X6_MFMA) &&
+           o.k_tracked >= 0;
 }
 
 int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_t ws_bytes,
@@ -720,6 +763,7 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
         QRCTM_TRY(c4v_prepare(A, d, D, c->ptr(c->plan.As), c->small() + SL_SCALE, c->bad(),
                               c->imax(), c->st));
         QRCTM_TRY(double_layer(c->ptr(c->plan.As), d, D, c->ptr(c->plan.a), c->st));
+        QRCTM_TRY(refresh_planes(c));
         QRCTM_TRY(eye_vec(c->ptr(c->plan.bvec), D, c->st));
         bool bad = false;
         QRCTM_TRY(read_bad(c, &bad));
@@ -750,6 +794,7 @@ int ctm_init_dl(ctm_ctx** out, const double* a, const double* bvec, int Dab, int
     rc = guarded(c, [&]() -> Status {
         QRCTM_TRY(clear_bad(c));
         QRCTM_TRY(dl_to_internal(a, Dab, c->ptr(c->plan.a), c->st));
+        QRCTM_TRY(refresh_planes(c));
         QRCTM_HIP(hipMemcpyAsync(c->ptr(c->plan.bvec), bvec, sizeof(double) * Dab,
                                  hipMemcpyDeviceToDevice, c->st));
         return start_environment(c);
@@ -772,6 +817,7 @@ int ctm_set_tensor(ctm_ctx* c, const double* A) {
         QRCTM_TRY(c4v_prepare(A, c->sh.d, c->sh.D, c->ptr(c->plan.As), c->small() + SL_SCALE,
                               c->bad(), c->imax(), c->st));
         QRCTM_TRY(double_layer(c->ptr(c->plan.As), c->sh.d, c->sh.D, c->ptr(c->plan.a), c->st));
+        QRCTM_TRY(refresh_planes(c));
         bool bad = false;
         QRCTM_TRY(read_bad(c, &bad));
         if (bad) {

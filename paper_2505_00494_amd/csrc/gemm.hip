@@ -10,8 +10,11 @@
 // Tiling: a workgroup computes a BM x BN tile of C with (BM/WM) x (BN/WN) waves;
 // each wave owns a WM x WN sub-tile held in (WM/16) x (WN/16) MFMA accumulators.
 // K advances in slabs of BK staged through LDS (double buffered, one barrier per
-// slab), stored k-major so that every MFMA operand fetch is 16 consecutive
-// doubles per quarter-wave.
+// slab).  LDS holds each row of A and each column of B k-contiguous (row stride
+// BK plus 16 bytes), and within a slab quarter-wave q of the MFMA's k slots
+// takes the k range [q BK/4, (q+1) BK/4): every lane fetches all of its
+// operand values for the slab with 16-byte reads, and the 16 lanes of a
+// quarter-wave (16 rows, stride BK * size + 16 bytes) hit distinct banks.
 #include "common.h"
 
 #ifndef MMA_F32_ROW
@@ -33,6 +36,8 @@ struct KArgs {
     long long kchunk;  // K range per split (split index = blockIdx.y)
     int tiles_m, tiles_n;
     int partial;       // 1: write raw sums to C + split*M*N (plain M x N)
+    unsigned short* C16;  // non-null: the result split into three bf16 planes,
+    long long pC16;       // plane s at C16[s pC16 + map(m, n)] (alpha only)
 };
 
 // Matrix-core operation per compute type.  FP64: v_mfma_f64_16x16x4_f64; FP32:
@@ -71,9 +76,11 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int LA = (BM * BK + NT - 1) / NT, LB = (BN * BK + NT - 1) / NT;
-    constexpr int PAD = 2;  // doubles; breaks the power-of-two row stride
-    __shared__ CT As[2][BK][BM + PAD];
-    __shared__ CT Bs[2][BK][BN + PAD];
+    constexpr int KP = BK + 16 / (int)sizeof(CT);  // row stride in LDS (elements)
+    constexpr int KQ = BK / 4;                      // k values per quarter-wave
+    static_assert((KQ * sizeof(CT)) % 16 == 0, "k range of a quarter-wave in 16-byte units");
+    __shared__ __attribute__((aligned(16))) CT As[2][BM][KP];
+    __shared__ __attribute__((aligned(16))) CT Bs[2][BN][KP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -94,50 +101,65 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
     const long long kbeg = (long long)blockIdx.y * p.kchunk;
     const long long kend = min(p.K, kbeg + p.kchunk);
 
-    CT ra[LA], rb[LB];
+    // raw operand values of the next slab, held in registers across the MFMAs
+    double ra[LA], rb[LB];
 
-    // Out-of-range elements are loaded from a clamped (valid) address and
-    // replaced by zero, so the loads carry no branches.
+    // Out-of-range elements are loaded from a clamped (valid) address; they
+    // are replaced by zero (and converted to CT) only when stored to LDS, after
+    // the MFMAs of the current slab, so that the loads are not waited for
+    // before the matrix-core work.
+    auto a_in = [&](int i, long long k0, long long& gm, long long& gk) {
+        const int e = tid + i * NT;
+        int mm, kk;
+        if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
+        gm = m0 + mm;
+        gk = k0 + kk;
+        return (BM * BK % NT == 0 || e < BM * BK) && gm < p.M && gk < kend;
+    };
+    auto b_in = [&](int i, long long k0, long long& gn, long long& gk) {
+        const int e = tid + i * NT;
+        int nn, kk;
+        if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+        gn = n0 + nn;
+        gk = k0 + kk;
+        return (BN * BK % NT == 0 || e < BN * BK) && gn < p.N && gk < kend;
+    };
     auto load = [&](long long k0) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
-            const int e = tid + i * NT;
-            int mm, kk;
-            if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
-            const long long gm = m0 + mm, gk = k0 + kk;
-            const bool in = (BM * BK % NT == 0 || e < BM * BK) && gm < p.M && gk < kend;
+            long long gm, gk;
+            const bool in = a_in(i, k0, gm, gk);
             const long long cm = in ? gm : 0, ck = in ? gk : kbeg;
-            const double v = TA ? p.A[ck * p.lda + cm] : p.A[cm * p.lda + ck];
-            ra[i] = in ? (CT)v : (CT)0;
+            ra[i] = TA ? p.A[ck * p.lda + cm] : p.A[cm * p.lda + ck];
         }
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
-            const int e = tid + i * NT;
-            int nn, kk;
-            if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-            const long long gn = n0 + nn, gk = k0 + kk;
-            const bool in = (BN * BK % NT == 0 || e < BN * BK) && gn < p.N && gk < kend;
+            long long gn, gk;
+            const bool in = b_in(i, k0, gn, gk);
             const long long cn = in ? gn : 0, ck = in ? gk : kbeg;
-            const double v = TB ? p.B[cn * p.ldb + ck] : p.B[ck * p.ldb + cn];
-            rb[i] = in ? (CT)v : (CT)0;
+            rb[i] = TB ? p.B[cn * p.ldb + ck] : p.B[ck * p.ldb + cn];
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, long long k0) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int e = tid + i * NT;
             if (BM * BK % NT != 0 && e >= BM * BK) break;
+            long long gm, gk;
+            const bool in = a_in(i, k0, gm, gk);
             int mm, kk;
             if (TA) { mm = e % BM; kk = e / BM; } else { kk = e % BK; mm = e / BK; }
-            As[buf][kk][mm] = ra[i];
+            As[buf][mm][kk] = in ? (CT)ra[i] : (CT)0;
         }
 #pragma unroll
         for (int i = 0; i < LB; ++i) {
             const int e = tid + i * NT;
             if (BN * BK % NT != 0 && e >= BN * BK) break;
+            long long gn, gk;
+            const bool in = b_in(i, k0, gn, gk);
             int nn, kk;
             if (TB) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-            Bs[buf][kk][nn] = rb[i];
+            Bs[buf][nn][kk] = in ? (CT)rb[i] : (CT)0;
         }
     };
 
@@ -148,31 +170,39 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
         for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     const int lrow = lane & 15;  // operand row/col within a 16-block
-    const int lk = lane >> 4;    // k within a 4-slab
+    const int lk = lane >> 4;    // quarter-wave: MFMA k slot, k range [lk KQ, (lk+1) KQ)
 
     int buf = 0;
     if (kbeg < kend) {
         load(kbeg);
-        store(0);
+        store(0, kbeg);
     }
     __syncthreads();
     for (long long k0 = kbeg; k0 < kend; k0 += BK) {
         const bool more = k0 + BK < kend;
         if (more) load(k0 + BK);
+        CT af[FM][KQ], bf[FN][KQ];
 #pragma unroll
-        for (int kk = 0; kk < BK / 4; ++kk) {
-            CT af[FM], bf[FN];
+        for (int i = 0; i < FM; ++i) {
+            const CT* src = &As[buf][wm * WM + i * 16 + lrow][lk * KQ];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) af[i] = As[buf][kk * 4 + lk][wm * WM + i * 16 + lrow];
+            for (int q = 0; q < KQ; ++q) af[i][q] = src[q];
+        }
 #pragma unroll
-            for (int j = 0; j < FN; ++j) bf[j] = Bs[buf][kk * 4 + lk][wn * WN + j * 16 + lrow];
+        for (int j = 0; j < FN; ++j) {
+            const CT* src = &Bs[buf][wn * WN + j * 16 + lrow][lk * KQ];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) bf[j][q] = src[q];
+        }
+        // k step q: slot lk of the MFMA carries k = lk KQ + q for A and B alike
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = Mma<CT>::run(af[i], bf[j], acc[i][j]);
-        }
-        if (more) store(buf ^ 1);
+                    acc[i][j] = Mma<CT>::run(af[i][q], bf[j][q], acc[i][j]);
+        if (more) store(buf ^ 1, k0 + BK);
         __syncthreads();
         buf ^= 1;
     }
@@ -201,6 +231,15 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
             for (int j = 0; j < FN; ++j) {
                 if (!nok[j]) continue;
                 const double v = (double)acc[i][j][r];
+                if (p.C16) {
+                    unsigned short h, mm, l;
+                    bf16_split3((float)(p.alpha * v), h, mm, l);
+                    const long long o16 = moff + noff[j];
+                    p.C16[o16] = h;
+                    p.C16[p.pC16 + o16] = mm;
+                    p.C16[2 * p.pC16 + o16] = l;
+                    continue;
+                }
                 double* o = Cb + moff + noff[j];
                 if (p.partial) *o = v;
                 else *o = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *o;
@@ -239,7 +278,8 @@ void launch_t(const KArgs& a, int ta, int tb, int splits, hipStream_t st) {
 }
 
 struct Plan {
-    int cfg;  // 0: 128x128 (8 waves of 64x32); 1: 64x64 (8 waves of 32x16);
+    int cfg;  // 0: 128x128 (8 waves of 64x32; K slabs of 32 in FP64, 16 in FP32);
+              // 1: 64x64 (8 waves of 32x16);
               // 2: 128x48 (12 waves of 32x16) for skinny N
     int bm, bn;
     int splits;
@@ -296,12 +336,22 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
         s.msg = "gemm_f64: K must be positive";
         return s;
     }
+    // split-BF16 products when the operands come as planes; a result wanted
+    // as planes (with FP64 operands) comes from the FP32 matrix cores
+    if (g.prec == 2 && (g.A16 || g.B16)) return gemm_bf16x6(g, st);
     const Plan pl = make_plan(g);
     KArgs a{};
     a.M = g.M; a.N = g.N; a.K = g.K;
     a.A = g.A; a.lda = g.lda; a.B = g.B; a.ldb = g.ldb;
     a.alpha = g.alpha; a.beta = g.beta; a.map = g.map;
     a.kchunk = pl.kchunk;
+    a.C16 = g.prec == 2 ? g.C16 : nullptr;
+    a.pC16 = g.pC16;
+    if (a.C16 && (pl.splits > 1 || g.beta != 0.0)) {
+        s.code = -1;
+        s.msg = "gemm_f64: a split result needs an unsplit K and beta = 0";
+        return s;
+    }
     a.tiles_m = (int)ceil_div(g.M, pl.bm);
     a.tiles_n = (int)ceil_div(g.N, pl.bn);
     if (pl.splits > 1) {
@@ -317,12 +367,12 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
         a.C = g.C;
         a.partial = 0;
     }
-    if (g.prec == 1) {
+    if (g.prec != 0) {
         if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32, float>(a, g.trans_a, g.trans_b, pl.splits, st);
         else if (pl.cfg == 2) launch_t<128, 48, 16, 32, 16, float>(a, g.trans_a, g.trans_b, pl.splits, st);
         else launch_t<64, 64, 16, 32, 16, float>(a, g.trans_a, g.trans_b, pl.splits, st);
     } else {
-        if (pl.cfg == 0) launch_t<128, 128, 16, 64, 32, double>(a, g.trans_a, g.trans_b, pl.splits, st);
+        if (pl.cfg == 0) launch_t<128, 128, 32, 64, 32, double>(a, g.trans_a, g.trans_b, pl.splits, st);
         else if (pl.cfg == 2) launch_t<128, 48, 16, 32, 16, double>(a, g.trans_a, g.trans_b, pl.splits, st);
         else launch_t<64, 64, 16, 32, 16, double>(a, g.trans_a, g.trans_b, pl.splits, st);
     }

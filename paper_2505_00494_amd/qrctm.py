@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "qrctm.h")
 CTM_OK, CTM_NOTCONV = 0, 1
 CTM_EINVAL, CTM_EWORKSPACE, CTM_EHIP, CTM_ENONFINITE, CTM_ESINGULAR, CTM_ESTATE = (
     -1, -2, -3, -4, -5, -6)
-PREC_FP64, PREC_FP32_MFMA = 0, 1
+PREC_FP64, PREC_FP32_MFMA, PREC_BF16X6_MFMA = 0, 1, 2
 
 
 class CTMError(RuntimeError):

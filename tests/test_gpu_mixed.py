@@ -1,9 +1,13 @@
-"""GPU checks of the mixed form (bulk contractions on the FP32 matrix cores,
-QR / normalisation / spectrum in FP64) against the FP64 path and the oracle.
+"""GPU checks of the mixed forms (bulk contractions on the FP32 matrix cores,
+or as six split-BF16 products on the bf16 matrix cores; QR / normalisation /
+spectrum in FP64) against the FP64 path and the oracle.
 
 FP32 products with FP32 accumulation carry a relative rounding of about
-sqrt(K) 2^-24 per contraction; the bounds below are that budget, not the
-FP64 ones.  The measured errors are reported by the benchmark.
+sqrt(K) 2^-24 per contraction, and the split-BF16 form keeps every term down
+to 2^-24 with the same accumulation; the bounds below are that budget, not
+the FP64 ones.  The measured errors are reported by the benchmark.  The
+split-BF16 kernel serves products of at least 256 tiles of 128 x 128, which
+first occur at D = 6, chi = 144 (3a and 3b).
 """
 import numpy as np
 import pytest
@@ -22,13 +26,17 @@ def _dev(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
 
 
-@pytest.mark.parametrize("d,D,chi", [(2, 2, 16), (2, 4, 64)])
-def test_mixed_step_close_to_fp64(d, D, chi):
+@pytest.mark.parametrize("prec,d,D,chi", [(P.PREC_FP32_MFMA, 2, 2, 16), (P.PREC_FP32_MFMA, 2, 4, 64),
+                                          (P.PREC_FP32_MFMA, 2, 6, 144),
+                                          (P.PREC_BF16X6_MFMA, 2, 4, 64),
+                                          (P.PREC_BF16X6_MFMA, 2, 6, 144)])
+def test_mixed_step_close_to_fp64(prec, d, D, chi):
+    print(f"mixed prec={prec} d={d} D={D} chi={chi}", flush=True)
     A = inp.random_site_tensor(d, D, 1)
     As = ctm.prepare_site_tensor(A)
     a = ctm.double_layer(As)
     C, T = ctm.warmup_env(a, chi, ctm.identity_boundary_vector(D))
-    ctx = P.Context(_dev(A), chi, n_warmup=0, precision=P.PREC_FP32_MFMA)
+    ctx = P.Context(_dev(A), chi, n_warmup=0, precision=prec)
     ctx.set_env(_dev(C), _dev(T))
     C1, T1 = ctm.sym_norm(*ctm.qr_step(C, T, a))
     ctx.step(1)
@@ -48,7 +56,8 @@ def test_mixed_step_close_to_fp64(d, D, chi):
     ctx.close()
 
 
-def test_mixed_ising_free_energy():
+@pytest.mark.parametrize("prec", [P.PREC_FP32_MFMA, P.PREC_BF16X6_MFMA])
+def test_mixed_ising_free_energy(prec):
     from scipy import integrate
     K = 0.40
     kap = 2 * np.sinh(2 * K) / np.cosh(2 * K) ** 2
@@ -57,7 +66,30 @@ def test_mixed_ising_free_energy():
     ref = np.log(2 * np.cosh(2 * K)) + v / np.pi
     a = inp.ising_classical_tensor(K)
     ctx = P.Context(a=_dev(a), bvec=_dev(inp.ising_boundary_vector(K)), chi=32,
-                    precision=P.PREC_FP32_MFMA)
+                    precision=prec)
     ctx.converge(1e-7, 2000)
     assert abs(ctx.lnz_per_site() - ref) < 1e-6
+    ctx.close()
+
+
+def test_split_bf16_matches_fp32_form_at_d6():
+    # the split-BF16 products (3a, 3b here) against the FP32-matrix-core form
+    # and FP64 over ten steps from the same environment: both mixed forms stay
+    # within the FP32 budget of FP64, and of each other
+    d, D, chi = 2, 6, 144
+    A = inp.random_site_tensor(d, D, 1)
+    ctx = P.Context(_dev(A), chi)
+    C0, T0 = ctx.get_env()
+    h = inp.heisenberg_bond_rotated()
+    es = {}
+    for prec in (P.PREC_FP64, P.PREC_FP32_MFMA, P.PREC_BF16X6_MFMA):
+        c = P.Context(_dev(A), chi, n_warmup=0, precision=prec)
+        c.set_env(C0, T0)
+        c.step(10)
+        es[prec] = c.energy(h)
+        c.close()
+    e64 = es[P.PREC_FP64]
+    print({k: abs(v - e64) / abs(e64) for k, v in es.items()}, flush=True)
+    assert abs(es[P.PREC_FP32_MFMA] - e64) < 1e-5 * abs(e64)
+    assert abs(es[P.PREC_BF16X6_MFMA] - e64) < 1e-5 * abs(e64)
     ctx.close()
