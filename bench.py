@@ -143,6 +143,9 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--acc-steps", type=int, default=20)
     ap.add_argument("--k", type=int, default=10, help="tracked steps of the gradient")
+    ap.add_argument("--converge-tol", type=float, default=0.0,
+                    help="time to a converged environment per form (0: skip)")
+    ap.add_argument("--converge-max", type=int, default=600)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -224,6 +227,7 @@ def main():
         ctx.set_env(C0, T0)
         ctx.step(nacc)
         e64 = ctx.energy(h)
+        conv_ref = {}
         for key, prec, desc in (
                 ("mixed", P.PREC_FP32_MFMA,
                  "fp32 matrix cores (FP32 products and accumulation); QR, normalisation, "
@@ -250,6 +254,31 @@ def main():
             mctx.set_env(C0, T0)
             mctx.step(nacc)
             em = mctx.energy(h)
+            conv = None
+            if args.converge_tol > 0:
+                # time to solution from the same environment: mixed steps down to
+                # mixed_tol, then FP64 steps to the tolerance, against FP64 alone
+                if "fp64" not in conv_ref:
+                    ctx.set_env(C0, T0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ok, n, dl = ctx.converge(args.converge_tol, args.converge_max)
+                    torch.cuda.synchronize()
+                    conv_ref["fp64"] = {"converged": ok, "steps": n, "s": time.perf_counter() - t0,
+                                        "energy": ctx.energy(h)}
+                mctx.set_env(C0, T0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ok, n, dl = mctx.converge(args.converge_tol, args.converge_max)
+                torch.cuda.synchronize()
+                tm = time.perf_counter() - t0
+                ec = mctx.energy(h)
+                r = conv_ref["fp64"]
+                conv = {"tol": args.converge_tol, "converged": ok, "steps": n, "s": tm,
+                        "mixed_tol": mctx.opts.mixed_tol,
+                        "fp64_steps": r["steps"], "fp64_s": r["s"], "fp64_converged": r["converged"],
+                        "speedup_time_to_solution": r["s"] / tm,
+                        "energy_rel_err_vs_fp64": abs(ec - r["energy"]) / abs(r["energy"])}
             out[key] = {"precision": desc,
                         "steps_per_s": args.steps / el_m, "ms_per_step": 1e3 * el_m / args.steps,
                         "speedup_vs_fp64": (args.steps / el_m) / steps_per_s,
@@ -257,7 +286,8 @@ def main():
                         "tflops_3b_equiv": flops_3b(chi, D) / (ms_m["edge_3b"] * 1e-3) / 1e12,
                         "energy_fp64": e64, "energy_mixed": em,
                         "energy_rel_err_vs_fp64": abs(em - e64) / abs(e64),
-                        "accuracy_steps": nacc}
+                        "accuracy_steps": nacc,
+                        "converged_with_fp64_refinement": conv}
             mctx.close()
     # dE/dA: k tracked steps + energy + reverse pass from the current environment
     if not args.no_grad:

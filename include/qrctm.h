@@ -65,9 +65,14 @@ typedef struct ctm_opts {
     int k_tracked;      /* tracked QR steps in ctm_energy_grad (AD paragraph)       */
     double qr_sing_tol; /* ctm_energy_grad fails with CTM_ESINGULAR when
                            min|R_ii| / max|R_ii| of a tracked step is below this    */
+    double mixed_tol;   /* mixed precisions only: ctm_converge takes mixed steps until
+                           the spectrum change is below max(tol, mixed_tol), then FP64
+                           steps until it is below tol, so the converged environment is
+                           an FP64 fixed point; 0 = mixed steps throughout             */
 } ctm_opts;
 
-/* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = 10, qr_sing_tol = 1e-14. */
+/* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = 10, qr_sing_tol = 1e-14,
+   mixed_tol = 1e-6. */
 void ctm_default_opts(ctm_opts* o);
 
 /*

@@ -246,6 +246,7 @@ struct ctm_ctx {
     Plan plan;
     int chi_cur = 0;
     int cur = 0;       // which of (C0,T0)/(C1,T1) holds the environment
+    bool fp64_steps = false;  // FP64 refinement phase of ctm_converge
     int spec_cur = 0;  // which spectrum buffer holds the spectrum of C
     int n_spec = 0;    // its length
     long long steps = 0;
@@ -359,6 +360,7 @@ Status mark(ctm_ctx* c, int i) {
 
 // GEMM precision of the forward step (the reverse pass always runs FP64).
 int step_prec(const ctm_ctx* c) {
+    if (c->fp64_steps) return 0;
     return c->opts.precision == CTM_PREC_FP32_MFMA    ? 1
            : c->opts.precision == CTM_PREC_BF16X6_MFMA ? 2
                                                         : 0;
@@ -731,6 +733,7 @@ void ctm_default_opts(ctm_opts* o) {
     o->n_warmup = -1;
     o->k_tracked = 10;
     o->qr_sing_tol = 1e-14;
+    o->mixed_tol = 1e-6;
 }
 
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
@@ -866,17 +869,18 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delt
         // Step i+1 is queued before delta_i is read, so the GPU never waits
         // for the host; if step i has converged, step i+1 is discarded (its
         // outputs live in the other environment / spectrum buffers).
-        if (max_steps > 0) {
+        auto run = [&](double tl, int budget) -> Status {
+            if (budget <= 0) return Status{};
             QRCTM_TRY(qr_step_once(c));
-            taken = 1;
+            int n = 1;
             while (true) {
                 const int slot = c->last_slot;
-                const bool speculate = taken < max_steps;
+                const bool speculate = n < budget;
                 if (speculate) QRCTM_TRY(qr_step_once(c));
                 QRCTM_HIP(hipMemcpyAsync(&dl, c->small() + SL_DELTA + slot, sizeof(double),
                                          hipMemcpyDeviceToHost, c->aux));
                 QRCTM_TRY(hip_status(hipStreamSynchronize(c->aux), "hipStreamSynchronize"));
-                if (!std::isfinite(dl) || dl < tol) {
+                if (!std::isfinite(dl) || dl < tl) {
                     if (speculate) {
                         QRCTM_TRY(join_aux(c));
                         QRCTM_TRY(sync(c->st));
@@ -888,8 +892,24 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delt
                     break;
                 }
                 if (!speculate) break;
-                ++taken;
+                ++n;
             }
+            taken += n;
+            return Status{};
+        };
+        // mixed forms: mixed steps down to mixed_tol, then FP64 refinement
+        const bool refine = c->opts.precision != CTM_PREC_FP64 && c->opts.mixed_tol > 0.0 &&
+                            c->opts.mixed_tol > tol;
+        if (refine) {
+            QRCTM_TRY(run(c->opts.mixed_tol, max_steps));
+            if (std::isfinite(dl) && dl < c->opts.mixed_tol) {
+                c->fp64_steps = true;
+                const Status s = run(tol, max_steps - taken);
+                c->fp64_steps = false;
+                QRCTM_TRY(s);
+            }
+        } else {
+            QRCTM_TRY(run(tol, max_steps));
         }
         bool bad = false;
         QRCTM_TRY(read_bad(c, &bad));

@@ -32,7 +32,7 @@ class CTMError(RuntimeError):
 
 class CtmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("n_warmup", c_int), ("k_tracked", c_int),
-                ("qr_sing_tol", c_double)]
+                ("qr_sing_tol", c_double), ("mixed_tol", c_double)]
 
 
 class CtmStats(ctypes.Structure):
@@ -122,10 +122,13 @@ def _dev_f64(x, dev):
     return t.contiguous()
 
 
-def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-14) -> CtmOpts:
+def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-14,
+                 mixed_tol=None) -> CtmOpts:
     o = CtmOpts()
     lib().ctm_default_opts(byref(o))
     o.precision, o.n_warmup, o.k_tracked, o.qr_sing_tol = precision, n_warmup, k_tracked, qr_sing_tol
+    if mixed_tol is not None:
+        o.mixed_tol = mixed_tol
     return o
 
 
@@ -134,10 +137,10 @@ class Context:
 
     def __init__(self, A=None, chi: int = 16, *, a=None, bvec=None, device="cuda:0",
                  n_warmup: int = -1, precision: int = PREC_FP64, k_tracked: int = 10,
-                 qr_sing_tol: float = 1e-14):
+                 qr_sing_tol: float = 1e-14, mixed_tol=None):
         torch = _torch()
         self.device = torch.device(device)
-        self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol)
+        self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol)
         self.chi = chi
         L = lib()
         ctx = c_void_p()

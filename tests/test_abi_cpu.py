@@ -20,6 +20,7 @@ def test_library_exports_every_declared_function():
 def test_default_opts():
     o = B.default_opts()
     assert o.precision == B.PREC_FP64 and o.n_warmup == -1 and o.k_tracked == 10
+    assert o.qr_sing_tol == 1e-14 and o.mixed_tol == 1e-6
 
 
 def test_workspace_sizes_grow_with_problem():

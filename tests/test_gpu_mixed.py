@@ -93,3 +93,30 @@ def test_split_bf16_matches_fp32_form_at_d6():
     assert abs(es[P.PREC_FP32_MFMA] - e64) < 1e-5 * abs(e64)
     assert abs(es[P.PREC_BF16X6_MFMA] - e64) < 1e-5 * abs(e64)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [P.PREC_FP32_MFMA, P.PREC_BF16X6_MFMA])
+def test_mixed_converge_refines_to_fp64_fixed_point(prec):
+    # mixed steps down to mixed_tol, then FP64 steps: the environment that
+    # ctm_converge returns is a fixed point of the FP64 iteration (further FP64
+    # steps leave its energy unchanged), while the purely mixed iteration
+    # stalls at the FP32 level.  (A random tensor can have several fixed points
+    # at finite chi, so its energy is not compared with an FP64 run from the
+    # warm-up; the benchmark reports that difference.)
+    d, D, chi = 2, 4, 64
+    A = inp.random_site_tensor(d, D, 3)
+    h = inp.heisenberg_bond_rotated()
+    ctx = P.Context(_dev(A), chi, precision=prec)
+    ok, n, dl = ctx.converge(1e-11, 3000)
+    assert ok and dl < 1e-11
+    em = ctx.energy(h)
+    C, T = ctx.get_env()
+    ref = P.Context(_dev(A), chi, n_warmup=0)
+    ref.set_env(C, T)
+    ref.step(20)
+    e64 = ref.energy(h)
+    print(f"prec {prec}: {n} steps; energy change over 20 more FP64 steps "
+          f"{abs(em - e64) / abs(e64):.2e}", flush=True)
+    assert abs(em - e64) < 1e-10 * abs(e64)
+    ref.close()
+    ctx.close()
