@@ -54,7 +54,7 @@ constexpr int kQrThreads = 512;
 constexpr int kWaves = kQrThreads / 64;
 constexpr int kPb = 16;                        // panel width (one MFMA tile)
 constexpr int kRowGroups = kQrThreads / kPb;   // 32 row groups x 16 column lanes
-constexpr int kRowsPerWg = 64;                 // target rows per workgroup
+constexpr int kRowsPerWg = 32;                 // target rows per workgroup (measured best)
 constexpr int kMaxWg = 256;
 constexpr int kMaxN = 512;
 constexpr unsigned kSpinLimit = 1u << 17;      // polls of about a microsecond: ~0.1 s
