@@ -4,7 +4,8 @@
 //   sym_norm_backward   reverse of "symmetrise, divide by the Frobenius norm",
 //   copyltu             tril(M) + tril(M,-1)^T for the thin-QR adjoint
 //                       Abar = (Qbar + Q copyltu(R Rbar^T - Qbar^T Q)) R^{-T},
-//   tri_inv_upper       R^{-1} of the upper-triangular R (one column per thread),
+//   tri_inv_upper       R^{-1} of the upper-triangular R (one workgroup per column,
+//                       the triangle of R in LDS; one column per thread for large n),
 //   double_layer_backward, c4v_backward (reverse of a2 and a1),
 //   ratio_min           running minimum of min|R_ii|/max|R_ii| over tracked steps.
 #include "adjoint.h"
@@ -108,6 +109,32 @@ __global__ void tri_inv_upper_kernel(const double* __restrict__ R, int n, double
         for (int k = i + 1; k <= j; ++k) acc -= R[(size_t)i * n + k] * Ri[(size_t)k * n + j];
         Ri[(size_t)i * n + j] = acc / R[(size_t)i * n + i];
     }
+}
+
+// Column j of R^{-1} by one workgroup: the upper triangle of R is copied to
+// LDS (packed by rows: row k starts at k n - k (k - 1) / 2), thread k keeps
+// b_k; for i = j down to 0, x_i = b_i / R_ii (thread i, through LDS) and every
+// thread k < i updates b_k -= R_ki x_i.  One workgroup barrier per step.
+constexpr int kTriThreads = 256;
+constexpr int kTriMaxLds = 150 * 1024;
+
+__global__ __launch_bounds__(kTriThreads) void tri_inv_col_kernel(const double* __restrict__ R,
+                                                                  int n, double* Ri) {
+    extern __shared__ double tri[];
+    double* x = tri + (size_t)n * (n + 1) / 2;
+    const int j = blockIdx.x, k = threadIdx.x;
+    for (int r = 0; r <= j; ++r) {
+        const size_t off = (size_t)r * n - (size_t)r * (r - 1) / 2;
+        for (int c = r + k; c <= j; c += kTriThreads) tri[off + (c - r)] = R[(size_t)r * n + c];
+    }
+    double b = (k == j) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int i = j; i >= 0; --i) {
+        if (k == i) x[i] = b / tri[(size_t)i * n - (size_t)i * (i - 1) / 2];
+        __syncthreads();
+        if (k < i) b -= tri[(size_t)k * n - (size_t)k * (k - 1) / 2 + (i - k)] * x[i];
+    }
+    for (int i = k; i < n; i += kTriThreads) Ri[(size_t)i * n + j] = i <= j ? x[i] : 0.0;
 }
 
 // Asb[s,u,l,d,r] += sum_{u',l',d',r'} (abar[(u u'),(l l'),(r r'),(d d')] +
@@ -218,6 +245,13 @@ Status copyltu(const double* M, int n, double* Ms, hipStream_t st) {
 }
 
 Status tri_inv_upper(const double* R, int n, double* Ri, hipStream_t st) {
+    const size_t lds = sizeof(double) * ((size_t)n * (n + 1) / 2 + (size_t)n);
+    if (n <= kTriThreads && lds <= (size_t)kTriMaxLds) {
+        QRCTM_HIP(hipFuncSetAttribute((const void*)tri_inv_col_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(tri_inv_col_kernel, dim3(n), dim3(kTriThreads), lds, st, R, n, Ri);
+        return launch_check("tri_inv_col_kernel");
+    }
     hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, R, n, Ri);
     return launch_check("tri_inv_upper_kernel");
 }

@@ -293,7 +293,9 @@ constexpr int kTargetBlocks = 512;
 // everything else 64x64.  Split-K brings small grids to about 2 blocks per CU.
 Plan make_plan(const GemmDesc& g) {
     Plan pl{};
-    if (ceil_div(g.M, 128) * ceil_div(g.N, 128) >= 256) {
+    if (ceil_div(g.M, 128) * ceil_div(g.N, 128) >= 256 ||
+        (g.M >= 512 && g.N >= 512 && g.K >= 4096)) {
+        // large tiles; a long K with fewer tiles is split below
         pl.cfg = 0; pl.bm = 128; pl.bn = 128;
     } else if (g.N <= 256 && g.M >= 1024) {
         pl.cfg = 2; pl.bm = 128; pl.bn = 48;
