@@ -15,6 +15,7 @@
 #include "../../include/qrctm.h"
 #include "adjoint.h"
 #include "common.h"
+#include "edge_split.h"
 #include "eigh.h"
 #include "energy.h"
 #include "qr.h"
@@ -38,6 +39,8 @@ struct Plan {
         splitk, eig, energy, grad;
     // split-BF16 form: Y and the (transposed) double layer as three bf16 planes
     Buf Y16, a16;
+    // ket/bra-split 3b: the site tensor as its GEMM operand (empty: not used)
+    Buf Bk;
     size_t total = 0;
     size_t qr_bytes = 0, splitk_bytes = 0, eig_bytes = 0, energy_bytes = 0, grad_bytes = 0;
 };
@@ -222,6 +225,8 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     const bool planes = o.precision == CTM_PREC_BF16X6_MFMA && (Dab * Dab) % 8 == 0;
     take(P.Y16, planes ? 3 * sizeof(unsigned short) * chi * chi * Dab * Dab : 0);
     take(P.a16, planes ? 3 * sizeof(unsigned short) * Dab * Dab * Dab * Dab : 0);
+    const bool split = sh.quantum && o.edge_split == 1 && edge_split_supported(sh.d, sh.D);
+    take(P.Bk, split ? d8 * edge_split_operand_size(sh.d, sh.D) : 0);
     P.total = off;
     return P;
 }
@@ -339,7 +344,10 @@ Status renormalise_edge(ctm_ctx* c, const StepPtrs& p, const double* Q, int chi,
     void* sk = c->ptr<void>(c->plan.splitk);
     const size_t skb = c->plan.splitk_bytes;
     QRCTM_TRY(gemm_f64(g_edge_a(p, Q, chi, chio, Dab), sk, skb, c->st));
-    QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chio, Dab), sk, skb, c->st));
+    if (c->plan.Bk.bytes > 0)
+        QRCTM_TRY(edge_split_3b(p.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chio, p.Z, c->st));
+    else
+        QRCTM_TRY(gemm_f64(g_edge_b(p, chi, chio, Dab), sk, skb, c->st));
     QRCTM_TRY(gemm_f64(g_edge_c(p, Q, chi, chio, Dab), sk, skb, c->st));
     return Status{};
 }
@@ -366,8 +374,11 @@ int step_prec(const ctm_ctx* c) {
                                                         : 0;
 }
 
-// The double layer's split-BF16 planes (transposed) after a new tensor.
+// Operands derived from the site tensor (the double layer's split-BF16 planes,
+// the ket/bra-split operand) after a new tensor.
 Status refresh_planes(ctm_ctx* c) {
+    if (c->plan.Bk.bytes > 0)
+        QRCTM_TRY(edge_split_prepare(c->ptr(c->plan.As), c->sh.d, c->sh.D, c->ptr(c->plan.Bk), c->st));
     if (c->plan.a16.bytes == 0) return Status{};
     const long long D2 = (long long)c->sh.Dab * c->sh.Dab;
     return split_planes_t(c->ptr(c->plan.a), D2, D2, c->ptr<unsigned short>(c->plan.a16), c->st);
@@ -395,7 +406,9 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
         g.prec = prec;
         return gemm_f64(g, sk, skb, c->st);
     };
-    const bool planes = prec == 2 && c->plan.Y16.bytes > 0;
+    // 3b as the fused ket/bra-split kernel (FP64) when the plan holds its operand
+    const bool split = c->plan.Bk.bytes > 0;
+    const bool planes = prec == 2 && c->plan.Y16.bytes > 0 && !split;
     unsigned short* Y16 = planes ? c->ptr<unsigned short>(c->plan.Y16) : nullptr;
     QRCTM_TRY(mark(0));
     QRCTM_TRY(G(g_reduced_corner(p, chi, Dab)));                                       // a5
@@ -412,7 +425,10 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
         QRCTM_TRY(G(ga));
     }
     QRCTM_TRY(mark(3));
-    {
+    if (split) {
+        QRCTM_TRY(edge_split_3b(p.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi, p.Z,
+                                c->st));                                               // a7 3b
+    } else {
         GemmDesc gb = g_edge_b(p, chi, chi, Dab);                                      // a7 3b
         if (planes) {
             const long long D2 = (long long)Dab * Dab;
@@ -660,7 +676,7 @@ Status start_environment(ctm_ctx* c) {
 bool valid_opts(const ctm_opts& o) {
     return (o.precision == CTM_PREC_FP64 || o.precision == CTM_PREC_FP32_MFMA ||
             o.precision == CTM_PREC_BF16X6_MFMA) &&
-           o.k_tracked >= 0;
+           o.k_tracked >= 0 && (o.edge_split == 0 || o.edge_split == 1);
 }
 
 int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_t ws_bytes,
@@ -717,10 +733,13 @@ int guarded(ctm_ctx* c, F&& f) {
 // Householder QR 4 m n^2 - 4 n^3 / 3 with m = chi Dab, n = chi, edge
 // renormalisation 2 chi^3 Dab^2 + 2 chi^2 Dab^4 + 2 chi^3 Dab^2, accelerated
 // corner 4 chi^3 Dab.
-double step_flops(int chi, int Dab) {
+// Algorithmic flops of one QR step; 3b is 2 chi^2 Dab^4 with the double layer,
+// 4 d chi^2 Dab^3 with the ket/bra split (d > 0).
+double step_flops(int chi, int Dab, int d_split) {
     const double c = chi, Db = Dab, Db2 = Db * Db;
+    const double f3b = d_split > 0 ? 4.0 * d_split * c * c * Db2 * Db : 2 * c * c * Db2 * Db2;
     return 2 * c * c * c * Db + (4 * c * c * c * Db - 4.0 / 3.0 * c * c * c) +
-           2 * c * c * c * Db2 + 2 * c * c * Db2 * Db2 + 2 * c * c * c * Db2 + 4 * c * c * c * Db;
+           2 * c * c * c * Db2 + f3b + 2 * c * c * c * Db2 + 4 * c * c * c * Db;
 }
 
 }  // namespace
@@ -734,6 +753,7 @@ void ctm_default_opts(ctm_opts* o) {
     o->k_tracked = 10;
     o->qr_sing_tol = 1e-14;
     o->mixed_tol = 1e-6;
+    o->edge_split = 1;
 }
 
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
@@ -1026,7 +1046,8 @@ int ctm_stats(ctm_ctx* c, ctm_stats_t* st) {
         st->Dab = c->sh.Dab;
         st->steps = c->steps;
         st->last_delta = c->last_delta;
-        st->flops_per_step = step_flops(c->chi_cur, c->sh.Dab);
+        st->flops_per_step =
+            step_flops(c->chi_cur, c->sh.Dab, c->plan.Bk.bytes > 0 ? c->sh.d : 0);
         st->r_diag_ratio = c->steps > 0 ? r : NAN;
         st->timed_steps = c->timed_steps;
         for (int i = 0; i < kPhases; ++i) st->ms_phase[i] = c->ms_phase[i];

@@ -32,7 +32,7 @@ class CTMError(RuntimeError):
 
 class CtmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("n_warmup", c_int), ("k_tracked", c_int),
-                ("qr_sing_tol", c_double), ("mixed_tol", c_double)]
+                ("qr_sing_tol", c_double), ("mixed_tol", c_double), ("edge_split", c_int)]
 
 
 class CtmStats(ctypes.Structure):
@@ -123,12 +123,14 @@ def _dev_f64(x, dev):
 
 
 def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-14,
-                 mixed_tol=None) -> CtmOpts:
+                 mixed_tol=None, edge_split=None) -> CtmOpts:
     o = CtmOpts()
     lib().ctm_default_opts(byref(o))
     o.precision, o.n_warmup, o.k_tracked, o.qr_sing_tol = precision, n_warmup, k_tracked, qr_sing_tol
     if mixed_tol is not None:
         o.mixed_tol = mixed_tol
+    if edge_split is not None:
+        o.edge_split = int(edge_split)
     return o
 
 
@@ -137,10 +139,11 @@ class Context:
 
     def __init__(self, A=None, chi: int = 16, *, a=None, bvec=None, device="cuda:0",
                  n_warmup: int = -1, precision: int = PREC_FP64, k_tracked: int = 10,
-                 qr_sing_tol: float = 1e-14, mixed_tol=None):
+                 qr_sing_tol: float = 1e-14, mixed_tol=None, edge_split=None):
         torch = _torch()
         self.device = torch.device(device)
-        self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol)
+        self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol,
+                                 edge_split)
         self.chi = chi
         L = lib()
         ctx = c_void_p()

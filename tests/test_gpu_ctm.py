@@ -1,7 +1,9 @@
 """GPU parity of the CTMRG path against the CPU oracle, through the C ABI.
 
 * One QR step at a time from the same environment: C and T elementwise (the
-  QR with diag(R) >= 0 makes the step a deterministic function of (C, T, a)).
+  QR with diag(R) >= 0 makes the step a deterministic function of (C, T, a)),
+  with the edge contraction as one double-layer product and as the fused
+  ket/bra-split kernel (edge_split 0 / 1), at bond dimensions 2 to 8.
 * Initialisation + warm-up (a1-a4): spectrum and environment.
 * The classical Ising network against Onsager / Yang and against the oracle.
 * The nearest-neighbour energy against the oracle.
@@ -37,12 +39,14 @@ def _rel(x, y):
     return np.abs(x - y).max() / np.abs(y).max()
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("d,D,chi,nsteps", [(2, 2, 16, 6), (2, 3, 36, 4), (2, 4, 64, 3),
-                                            (2, 6, 144, 2)])
-def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps):
-    print(f"steps d={d} D={D} chi={chi}", flush=True)
+                                            (2, 5, 75, 2), (2, 6, 144, 2), (2, 7, 98, 1),
+                                            (2, 8, 128, 1)])
+def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps, split):
+    print(f"steps d={d} D={D} chi={chi} edge_split={split}", flush=True)
     A, As, a, C, T = _oracle_setup(d, D, chi, seed=1)
-    ctx = P.Context(_dev(A), chi, n_warmup=0)
+    ctx = P.Context(_dev(A), chi, n_warmup=0, edge_split=split)
     ctx.set_env(_dev(C), _dev(T))
     s_prev = ctm.spectrum(C)
     for i in range(nsteps):

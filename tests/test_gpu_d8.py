@@ -26,14 +26,16 @@ from synth import inputs as inp  # noqa: E402
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "qrctm_d2_D8_chi256.json")
 
 
-def test_d8_chi256_forward_and_gradient_match_oracle():
+@pytest.mark.parametrize("split", [1, 0])
+def test_d8_chi256_forward_and_gradient_match_oracle(split):
     with open(GOLDEN) as f:
         g = json.load(f)
     d, D, chi = g["d"], g["D"], g["chi"]
-    print(f"d={d} D={D} chi={chi}: warm-up", flush=True)
+    print(f"d={d} D={D} chi={chi} edge_split={split}: warm-up", flush=True)
     A = inp.random_site_tensor(d, D, g["seed"])
     h = inp.heisenberg_bond_rotated()
-    ctx = P.Context(torch.as_tensor(A, device="cuda:0"), chi, k_tracked=g["k_tracked"])
+    ctx = P.Context(torch.as_tensor(A, device="cuda:0"), chi, k_tracked=g["k_tracked"],
+                    edge_split=split)
     for i in range(g["qr_steps"]):
         dl = ctx.step(1)
         e = ctx.energy(h)

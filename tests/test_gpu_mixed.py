@@ -7,7 +7,9 @@ sqrt(K) 2^-24 per contraction, and the split-BF16 form keeps every term down
 to 2^-24 with the same accumulation; the bounds below are that budget, not
 the FP64 ones.  The measured errors are reported by the benchmark.  The
 split-BF16 kernel serves products of at least 256 tiles of 128 x 128, which
-first occur at D = 6, chi = 144 (3a and 3b).
+first occur at D = 6, chi = 144 (3a and 3b).  With the ket/bra-split edge
+contraction (edge_split 1) 3b runs in FP64 in every form, so the mixed forms
+are checked with both settings.
 """
 import numpy as np
 import pytest
@@ -26,17 +28,18 @@ def _dev(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("prec,d,D,chi", [(P.PREC_FP32_MFMA, 2, 2, 16), (P.PREC_FP32_MFMA, 2, 4, 64),
                                           (P.PREC_FP32_MFMA, 2, 6, 144),
                                           (P.PREC_BF16X6_MFMA, 2, 4, 64),
                                           (P.PREC_BF16X6_MFMA, 2, 6, 144)])
-def test_mixed_step_close_to_fp64(prec, d, D, chi):
-    print(f"mixed prec={prec} d={d} D={D} chi={chi}", flush=True)
+def test_mixed_step_close_to_fp64(prec, d, D, chi, split):
+    print(f"mixed prec={prec} d={d} D={D} chi={chi} edge_split={split}", flush=True)
     A = inp.random_site_tensor(d, D, 1)
     As = ctm.prepare_site_tensor(A)
     a = ctm.double_layer(As)
     C, T = ctm.warmup_env(a, chi, ctm.identity_boundary_vector(D))
-    ctx = P.Context(_dev(A), chi, n_warmup=0, precision=prec)
+    ctx = P.Context(_dev(A), chi, n_warmup=0, precision=prec, edge_split=split)
     ctx.set_env(_dev(C), _dev(T))
     C1, T1 = ctm.sym_norm(*ctm.qr_step(C, T, a))
     ctx.step(1)
@@ -83,7 +86,7 @@ def test_split_bf16_matches_fp32_form_at_d6():
     h = inp.heisenberg_bond_rotated()
     es = {}
     for prec in (P.PREC_FP64, P.PREC_FP32_MFMA, P.PREC_BF16X6_MFMA):
-        c = P.Context(_dev(A), chi, n_warmup=0, precision=prec)
+        c = P.Context(_dev(A), chi, n_warmup=0, precision=prec, edge_split=0)
         c.set_env(C0, T0)
         c.step(10)
         es[prec] = c.energy(h)
