@@ -4,20 +4,23 @@
 Workload: C4v QR-CTMRG on a random C4v-symmetrised site tensor, d = 2, D = 6,
 chi = 144 (reduced corner 5184 x 144), FP64.  One "step" is one full QR-CTMRG
 step: reduced corner, Householder QR, T' = Q^T (T a) Q, accelerated corner,
-symmetrise/normalise and the corner-spectrum convergence measure.
+symmetrise/normalise and the corner-spectrum convergence measure.  The value is
+the library's default form: FP64, with the edge contraction's middle product
+(3b) done by the fused ket/bra-split kernel.
 
 The environment is initialised (C4v average, double layer, boundary, standard
 warm-up step) before the timed region; W untimed steps follow; then exactly K
-steps are timed between two stream synchronisations.  The dominant kernel (the
-double-layer contraction Z = Y a, a GEMM of 2 chi^2 D^8 flops) is timed per
-launch with HIP events on the library's stream in a second pass, for the
-roofline figure.  The CPU baseline is the FP64 oracle on the host cores on a
-bounded sample of the same workload.
+steps are timed between two stream synchronisations.  Every phase is then timed
+per launch with HIP events on the library's stream in a second pass; the
+roofline figure is for the phase with the largest share of the step, and the
+per-kernel figures for the others follow.  The CPU baseline is the FP64 oracle
+on the host cores on a bounded sample of the same workload.
 
-Also reported (same tensor): the mixed forms (bulk contractions on the FP32
-matrix cores, or as split-BF16 products on the bf16 matrix cores) with their
-speed-ups and energy errors against the FP64 path, and the time of one dE/dA
-(k tracked steps, energy and the reverse pass).
+Also reported (same tensor): the plain form (3b as one GEMM with the
+double-layer tensor, 2 chi^2 D^8 flops), the mixed forms (bulk contractions on
+the FP32 matrix cores, or as split-BF16 products on the bf16 matrix cores) with
+their speed-ups and energy errors against FP64, and the time of one dE/dA (k
+tracked steps, energy and the reverse pass).
 
 Prints ONE JSON line.
 """
@@ -38,35 +41,61 @@ if ROOT not in sys.path:
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
-# Sources whose change makes a stored traffic measurement of the 3b GEMM stale:
-# the GEMM kernel and its tile plans, and the operand maps of the step.
-TRAFFIC_SOURCES = ("paper_2505_00494_amd/csrc/gemm.hip", "paper_2505_00494_amd/csrc/common.h",
-                   "paper_2505_00494_amd/csrc/step_gemms.h")
+# Sources whose change makes a stored traffic measurement stale, per kernel.
+TRAFFIC_SOURCES = {
+    "qr": ("paper_2505_00494_amd/csrc/qr.hip", "paper_2505_00494_amd/csrc/qr.h",
+           "paper_2505_00494_amd/csrc/common.h"),
+    "edge_3b": ("paper_2505_00494_amd/csrc/edge_split.hip", "paper_2505_00494_amd/csrc/edge_split.h",
+                "paper_2505_00494_amd/csrc/common.h"),
+}
 
 
 def flops_3b(chi: int, D: int) -> float:
+    """3b as one GEMM with the double-layer tensor."""
     return 2.0 * chi * chi * float(D) ** 8
 
 
-def traffic_source_hash() -> str:
+def kernel_figures(d, D, chi):
+    """Algorithmic flops and HBM bytes per launch of each phase's kernel (FP64).
+
+    qr: Householder R (2mn^2 - 2n^3/3) and the explicit thin Q (same again) of
+    the m x n reduced corner, reading it once and writing Q (m n) and R (n^2).
+    edge_3b: the fused split kernel, 4 d chi^2 D^6 flops; reads Y, writes Z.
+    edge_3a / edge_3c: 2 chi^3 D^4 each; the operands once and the result once.
+    """
+    m, n = chi * D * D, chi
+    R = D * D
+    b = 8.0
+    y = float(chi) * chi * R * R
+    return {
+        "qr": (4.0 * m * n * n - 4.0 * n ** 3 / 3.0, b * (2.0 * m * n + n * n)),
+        "edge_3b": (4.0 * d * chi * chi * float(D) ** 6, b * 2.0 * y),
+        "edge_3a": (2.0 * float(chi) ** 3 * R * R, b * (m * n + chi * chi * R + y)),
+        "edge_3c": (2.0 * float(chi) ** 3 * R * R, b * (y + m * n + chi * chi * R)),
+    }
+
+
+def traffic_source_hash(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in TRAFFIC_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(d, D, chi):
-    """HBM bytes per launch of the 3b GEMM from the committed counter summary.
+def measured_traffic(kernel, d, D, chi):
+    """HBM bytes per launch of a phase's kernel from the committed counter summary.
 
-    The summary (profiles/gemm_3b_traffic_d{d}_D{D}_chi{chi}.md) holds the
+    The summary (profiles/{kernel}_traffic_d{d}_D{D}_chi{chi}.md) holds the
     FETCH_SIZE and WRITE_SIZE readings per dispatch, each already scaled by
     what the same counter reads for a plain copy of known size, and the hash
     of the kernel sources they were taken with.  Returns None when there is no
     summary or the kernel has changed since.
     """
-    path = os.path.join(ROOT, "profiles", f"gemm_3b_traffic_d{d}_D{D}_chi{chi}.md")
+    if kernel not in TRAFFIC_SOURCES:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_d{d}_D{D}_chi{chi}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -76,7 +105,7 @@ def measured_traffic(d, D, chi):
             if len(m) == 2:
                 vals[m[0].strip()] = m[1].strip().strip("`")
     try:
-        if vals["kernel_source_sha256"] != traffic_source_hash():
+        if vals["kernel_source_sha256"] != traffic_source_hash(kernel):
             return None
         return {"bytes": float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"]),
                 "fetch_bytes": float(vals["fetch_bytes_per_launch"]),
@@ -186,9 +215,28 @@ def main():
     st2 = ctx.stats()
     ctx.set_timing(False)
     ms = {k: v / st2["timed_steps"] for k, v in st2["ms_phase"].items()}
-    ms_3b = ms["edge_3b"]
-    achieved = flops_3b(chi, D) / (ms_3b * 1e-3) / 1e12
-    traffic = measured_traffic(d, D, chi)
+    figs = kernel_figures(d, D, chi)
+    names = {"qr": "cooperative blocked Householder QR of the reduced corner (a6)",
+             "edge_3b": "fused ket/bra-split edge contraction Z = Y (A x A) (a7 3b)",
+             "edge_3a": "FP64 GEMM Y = Q^T T (a7 3a)",
+             "edge_3c": "FP64 GEMM T' = Z Q (a7 3c)"}
+
+    def roof(k):
+        fl, by = figs[k]
+        t = ms[k] * 1e-3
+        ach = fl / t / 1e12
+        tr = measured_traffic(k, d, D, chi)
+        r = {"bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": ach / FP64_MFMA_PEAK_TFLOPS, "traffic": tr["bytes"] if tr else None,
+             "kernel": names[k], "phase": k, "flops_per_launch": fl, "ms_per_launch": ms[k],
+             "algorithmic_bytes_per_launch": by, "algorithmic_hbm_gbs": by / t / 1e9}
+        if tr:
+            r["traffic_detail"] = tr
+        return r
+
+    # the phase with the largest share of the step on the library stream (the
+    # spectrum runs on the auxiliary stream, overlapped with the next step)
+    dom = max((k for k in figs), key=lambda k: ms[k])
 
     out = {
         "metric": f"QR-CTMRG steps/s (d={d}, D={D}, chi={chi}, FP64)",
@@ -211,17 +259,36 @@ def main():
         "last_delta": delta,
         "init_s": t_init,
         "ms_per_phase": ms,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": traffic["bytes"] if traffic else None,
-                     "kernel": "double-layer contraction Z = Y a (3b)",
-                     "flops_per_launch": flops_3b(chi, D), "ms_per_launch": ms_3b},
+        "roofline": roof(dom),
+        "roofline_kernels": {k: roof(k) for k in figs},
     }
+    C0, T0 = ctx.get_env()
+    # plain form: 3b as one FP64 GEMM with the double-layer tensor
+    pctx = P.Context(A, chi, n_warmup=0, edge_split=0)
+    pctx.set_env(C0, T0)
+    pctx.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pctx.step(args.steps)
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    pctx.set_timing(True)
+    pctx.step(nt)
+    pst = pctx.stats()
+    pctx.close()
+    ms_p = {k: v / pst["timed_steps"] for k, v in pst["ms_phase"].items()}
+    plain_sps = args.steps / el_p
+    t3b = flops_3b(chi, D) / (ms_p["edge_3b"] * 1e-3) / 1e12
+    out["plain_double_layer"] = {
+        "form": "FP64, 3b as one GEMM with the double-layer tensor (2 chi^2 D^8 flops)",
+        "steps_per_s": plain_sps, "ms_per_step": 1e3 * el_p / args.steps,
+        "tflops": pst["flops_per_step"] * plain_sps / 1e12, "ms_per_phase": ms_p,
+        "gemm_3b_tflops": t3b, "gemm_3b_frac_fp64_peak": t3b / FP64_MFMA_PEAK_TFLOPS,
+        "default_form_speedup": steps_per_s / plain_sps}
     # mixed forms: same tensor, bulk contractions on the FP32 matrix cores or
     # as split-BF16 products on the bf16 matrix cores; QR, normalisation and
     # spectrum in FP64
     if not args.no_mixed:
-        C0, T0 = ctx.get_env()
         h = inp.heisenberg_bond_rotated()
         nacc = args.acc_steps
         ctx.set_env(C0, T0)
@@ -230,12 +297,12 @@ def main():
         conv_ref = {}
         for key, prec, desc in (
                 ("mixed", P.PREC_FP32_MFMA,
-                 "fp32 matrix cores (FP32 products and accumulation); QR, normalisation, "
-                 "spectrum FP64"),
+                 "GEMMs on the fp32 matrix cores (FP32 products and accumulation); 3b the "
+                 "fused FP64 split kernel; QR, normalisation, spectrum FP64"),
                 ("mixed_bf16x6", P.PREC_BF16X6_MFMA,
-                 "split-BF16: operands as three bf16 parts, six products, FP32 accumulation "
-                 "(large products; the rest on the fp32 matrix cores); QR, normalisation, "
-                 "spectrum FP64")):
+                 "split-BF16 form: large GEMMs as six bf16 products of three-part operands "
+                 "with FP32 accumulation, the rest on the fp32 matrix cores; 3b the fused "
+                 "FP64 split kernel; QR, normalisation, spectrum FP64")):
             mctx = P.Context(A, chi, precision=prec, n_warmup=0)
             mctx.set_env(C0, T0)
             mctx.step(args.warmup)
@@ -282,8 +349,8 @@ def main():
             out[key] = {"precision": desc,
                         "steps_per_s": args.steps / el_m, "ms_per_step": 1e3 * el_m / args.steps,
                         "speedup_vs_fp64": (args.steps / el_m) / steps_per_s,
+                        "speedup_vs_plain_fp64": (args.steps / el_m) / plain_sps,
                         "ms_per_phase": ms_m,
-                        "tflops_3b_equiv": flops_3b(chi, D) / (ms_m["edge_3b"] * 1e-3) / 1e12,
                         "energy_fp64": e64, "energy_mixed": em,
                         "energy_rel_err_vs_fp64": abs(em - e64) / abs(e64),
                         "accuracy_steps": nacc,
@@ -304,8 +371,6 @@ def main():
                        "energy": e, "grad_norm": float(g.norm())}
         gctx.close()
     ctx.close()
-    if traffic:
-        out["roofline"]["traffic_detail"] = traffic
     if args.calibrate_copy:
         copy_calibration(args.calibrate_copy)
     if not args.no_cpu_baseline:

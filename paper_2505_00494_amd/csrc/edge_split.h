@@ -16,15 +16,19 @@ namespace qrctm {
 
 // (d, D) for which the fused kernel is built: d = 2, 1 <= D <= 8.
 bool edge_split_supported(int d, int D);
-// Doubles in the prepared operand (0 when unsupported).
+// Doubles in the prepared operand, including the launch counters that follow
+// it (0 when unsupported).
 size_t edge_split_operand_size(int d, int D);
 // Bk[s][k][n] = As[s][u][l][dd][r] for k = u D + l, n = r D + dd (zero outside
-// k, n < D^2; rows padded to a multiple of 4, columns to a multiple of 16).
-// As is the prepared site tensor, layout [s][u][l][dd][r].
+// k, n < D^2; rows padded to a multiple of 4, columns to a multiple of 16),
+// and the launch counters cleared.  As is the prepared site tensor, layout
+// [s][u][l][dd][r].
 Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_t st);
 // Z (chio x D^2 x chi x D^2, layout [al][r][f][dd]) from Y (chio x chi x D^2 x
-// D^2, layout [al][f][u][l]) and the prepared operand.  Y and Z must not overlap.
-Status edge_split_3b(const double* Y, const double* Bk, int d, int D, int chi, int chio, double* Z,
+// D^2, layout [al][f][u][l]) and the prepared operand, whose counters the launch
+// uses (launches on one Bk must be ordered, e.g. on one stream).  Y and Z must
+// not overlap.
+Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chio, double* Z,
                      hipStream_t st);
 
 }  // namespace qrctm
