@@ -56,6 +56,10 @@ extern "C" {
    step (3a, 3b at the usual sizes); the smaller ones take the FP32 path. */
 #define CTM_PREC_BF16X6_MFMA 2
 
+/* Gradient schemes of ctm_energy_grad (ctm_opts.grad_mode). */
+#define CTM_GRAD_CHECKPOINT  0   /* k tracked steps from the current environment  */
+#define CTM_GRAD_FIXED_POINT 1   /* implicit differentiation at a converged one   */
+
 typedef struct ctm_ctx ctm_ctx;
 
 typedef struct ctm_opts {
@@ -75,10 +79,16 @@ typedef struct ctm_opts {
                            flops, FP64 in every precision, same result up to rounding.
                            Used where available (quantum contexts with d = 2, D <= 8),
                            otherwise ignored.  0: always the double-layer product.  */
+    int grad_mode;      /* CTM_GRAD_CHECKPOINT or CTM_GRAD_FIXED_POINT (ctm_energy_grad) */
+    double fp_tol;      /* fixed point: the series stops when a term's norm is below
+                           fp_tol times the norm of dE/d(C, T)                        */
+    int fp_max_iter;    /* fixed point: at most this many reversed steps (rounded up
+                           to even); ctm_energy_grad returns CTM_NOTCONV beyond it     */
 } ctm_opts;
 
 /* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = 10, qr_sing_tol = 1e-14,
-   mixed_tol = 1e-6, edge_split = 1. */
+   mixed_tol = 1e-6, edge_split = 1, grad_mode = CTM_GRAD_CHECKPOINT, fp_tol = 1e-10,
+   fp_max_iter = 1000. */
 void ctm_default_opts(ctm_opts* o);
 
 /*
@@ -158,15 +168,31 @@ int ctm_energy(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
                double* E);
 
 /*
- * ctm_energy_grad: E and dE/dA (AD paragraph).  Starting from the current
- * environment, held fixed, the library runs opts.k_tracked QR steps, evaluates
- * E, and reverses the whole computation by hand-written adjoints (contraction
- * adjoints, the thin-QR adjoint, the double layer and the C4v average).  Only
- * (C_i, T_i) of every tracked step are kept; each step's intermediates are
- * recomputed in the reverse sweep.  dA is a device array of d*D^4 entries, the
- * gradient with respect to the raw A given to ctm_init / ctm_set_tensor.
- * The environment is left unchanged.  h_nnn must be NULL (nearest-neighbour
- * models).
+ * ctm_energy_grad: E and dE/dA (AD paragraph).  dA is a device array of d*D^4
+ * entries, the gradient with respect to the raw A given to ctm_init /
+ * ctm_set_tensor; E is a host output.  The environment is left unchanged.
+ * h_nnn must be NULL (nearest-neighbour models).  Two schemes (opts.grad_mode):
+ *   CTM_GRAD_CHECKPOINT: starting from the current environment, held fixed,
+ *     run opts.k_tracked QR steps, evaluate E, and reverse the whole
+ *     computation by hand-written adjoints (contraction adjoints, the thin-QR
+ *     adjoint, the double layer and the C4v average).  Only (C_i, T_i) of
+ *     every tracked step are kept; each step's intermediates are recomputed in
+ *     the reverse sweep.
+ *   CTM_GRAD_FIXED_POINT: the fixed-point scheme (Discussion paragraph): the
+ *     current environment must be converged.  With F one QR step and G = F o F
+ *     (T may alternate between two gauges from step to step; the pair of
+ *     steps is a fixed point in either case), dE/dA follows from the implicit
+ *     function theorem, lam = ebar (I - dG/denv)^{-1} being summed as a
+ *     Neumann series of reversed step pairs until a term's norm is below
+ *     opts.fp_tol times |ebar|.  Memory: two environments, no checkpoints.
+ *     The environment must be a fixed point of G elementwise: CTM_ESTATE when
+ *     |G(env) - env| / |env| > 1e-8 (the corner spectrum can converge while
+ *     C and T still drift; the series then need not converge).  Returns
+ *     CTM_NOTCONV (dA still written) after opts.fp_max_iter reversed steps, or
+ *     when the terms grow (the linearised step pair does not contract);
+ *     ctm_stats reports the steps taken and the residual.
+ * Returns CTM_ESINGULAR when a reversed step's R has min|R_ii|/max|R_ii| below
+ * opts.qr_sing_tol.
  */
 int ctm_energy_grad(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
                     double* E, double* dA);
@@ -188,6 +214,9 @@ typedef struct ctm_stats_t {
                                  3 double-layer contraction (3b), 4 .Q (3c),
                                  5 accelerated corner, 6 symmetrise/normalise,
                                  7 corner spectrum                             */
+    long long grad_steps;     /* steps reversed by the last ctm_energy_grad    */
+    double fp_residual;       /* |G(env) - env| / |env| seen by the last
+                                 fixed-point ctm_energy_grad (G: two steps)    */
 } ctm_stats_t;
 int ctm_stats(ctm_ctx* ctx, ctm_stats_t* st);
 

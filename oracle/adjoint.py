@@ -199,3 +199,45 @@ def energy_grad_k(A_raw, C0, T0, k, h):
         ab += abi
     Asb = Asb + double_layer_backward(As, ab)
     return e, prepare_backward(A_raw, Asb)
+
+
+# ----------------------------------------------------------------------------
+# Fixed-point (implicit) gradient at a converged environment.
+# ----------------------------------------------------------------------------
+
+
+def energy_grad_fixed_point(A_raw, C, T, h, tol=1e-12, max_iter=2000):
+    """(E, dE/dA_raw, n_iter) by differentiating the fixed-point condition.
+
+    Discussion paragraph: the fixed-point AD scheme of Liao et al. (2019).
+    Let F be one QR step followed by sym_norm.  A converged environment is a
+    fixed point of F in C, but T can alternate between two gauges (a cycle of
+    period 2), so the condition used is env* = G(env*, a) with G = F o F,
+    which holds in either case.  The converged energy E(A) = e(env*(A), As(A))
+    then has
+
+        dE/dAs = de/dAs + lam . dG/da . da/dAs,
+        lam    = ebar (I - dG/denv)^{-1} = sum_{n >= 0} ebar (dG/denv)^n,
+
+    ebar = de/denv.  The series is summed term by term: each term reverses the
+    two steps env* -> env1 = F(env*) -> env*, with the a-cotangent of every
+    reversed step accumulated, until a term's norm falls below tol times that
+    of ebar; it converges at the rate the CTMRG iteration itself does.
+    n_iter counts the reversed steps (even); None means max_iter was reached.
+    """
+    As = ctm.prepare_site_tensor(A_raw)
+    a = ctm.double_layer(As)
+    C1, T1 = ctm.sym_norm(*ctm.qr_step(C, T, a))
+    e, Cb, Tb, Asb = energy_nn_backward(C, T, As, h)
+    n0 = np.sqrt(np.sum(Cb * Cb) + np.sum(Tb * Tb))
+    ab = np.zeros_like(a)
+    n_iter = None
+    for it in range(0, max_iter, 2):
+        for Ci, Ti in ((C1, T1), (C, T)):
+            Cb, Tb, abi = qr_step_backward(Ci, Ti, a, Cb, Tb)
+            ab += abi
+        if np.sqrt(np.sum(Cb * Cb) + np.sum(Tb * Tb)) <= tol * n0:
+            n_iter = it + 2
+            break
+    Asb = Asb + double_layer_backward(As, ab)
+    return e, prepare_backward(A_raw, Asb), n_iter

@@ -11,6 +11,13 @@ Status sym_norm_backward(const double* Cn, const double* Tn, const double* Cb, c
                          const double* norms, int chi, int Dab, double* Cpb, double* Tpb,
                          double* part, hipStream_t st);
 Status copyltu(const double* M, int n, double* Ms, hipStream_t st);
+// *out (host) = |Cb|^2 + |Tb|^2 (nC, nT entries); part: sym_norm_backward scratch.
+// Synchronises the stream.
+Status sq_norm(const double* Cb, const double* Tb, long long nC, long long nT, double* part,
+               double* out, hipStream_t st);
+// *out (host) = |C1 - C0|^2 + |T1 - T0|^2; synchronises the stream.
+Status sq_diff(const double* C1, const double* C0, const double* T1, const double* T0,
+               long long nC, long long nT, double* part, double* out, hipStream_t st);
 Status tri_inv_upper(const double* R, int n, double* Ri, hipStream_t st);
 // Asb += reverse of a_int = sum_s As (x) As (a_int layout [U][L][R][Dn])
 Status double_layer_backward(const double* abar, const double* As, int d, int D, double* Asb,

@@ -9,6 +9,9 @@
 //   double_layer_backward, c4v_backward (reverse of a2 and a1),
 //   ratio_min           running minimum of min|R_ii|/max|R_ii| over tracked steps.
 #include "adjoint.h"
+
+#include <vector>
+
 #include "common.h"
 
 namespace qrctm {
@@ -237,6 +240,58 @@ Status sym_norm_backward(const double* Cn, const double* Tn, const double* Cb, c
     hipLaunchKernelGGL(sym_norm_bwd_kernel, dim3(b), dim3(kThreads), 0, st, part, b, norms, Cn, Cb, Tn,
                        Tb, chi, Dab, Cpb, Tpb);
     return launch_check("sym_norm_bwd_kernel");
+}
+
+__global__ __launch_bounds__(kThreads) void diff_sq_kernel(const double* __restrict__ C1,
+                                                           const double* __restrict__ C0,
+                                                           const double* __restrict__ T1,
+                                                           const double* __restrict__ T0,
+                                                           long long nC, long long nT, double* part) {
+    __shared__ double r[kThreads];
+    double acc = 0.0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nC + nT;
+         e += (long long)gridDim.x * blockDim.x) {
+        const double v = e < nC ? C1[e] - C0[e] : T1[e - nC] - T0[e - nC];
+        acc += v * v;
+    }
+    r[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = r[0];
+        part[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+Status sq_diff(const double* C1, const double* C0, const double* T1, const double* T0,
+               long long nC, long long nT, double* part, double* out, hipStream_t st) {
+    const int b = grid(nC + nT);
+    hipLaunchKernelGGL(diff_sq_kernel, dim3(b), dim3(kThreads), 0, st, C1, C0, T1, T0, nC, nT, part);
+    QRCTM_TRY(launch_check("diff_sq_kernel"));
+    std::vector<double> h(2 * (size_t)b);
+    QRCTM_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    QRCTM_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : h) s += v;
+    *out = s;
+    return Status{};
+}
+
+Status sq_norm(const double* Cb, const double* Tb, long long nC, long long nT, double* part,
+               double* out, hipStream_t st) {
+    const int b = grid(nC + nT);
+    hipLaunchKernelGGL(dots_kernel, dim3(b), dim3(kThreads), 0, st, Cb, Cb, Tb, Tb, nC, nT, part);
+    QRCTM_TRY(launch_check("dots_kernel"));
+    std::vector<double> h(2 * (size_t)b);
+    QRCTM_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    QRCTM_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : h) s += v;
+    *out = s;
+    return Status{};
 }
 
 Status copyltu(const double* M, int n, double* Ms, hipStream_t st) {

@@ -144,8 +144,10 @@ GradLayout grad_layout(const Shape& sh, int k) {
         return o;
     };
     const size_t c = sh.chi, Db = sh.Dab, c2 = c * c;
-    L.ckC = take((size_t)(k + 1) * c2);
-    L.ckT = take((size_t)(k + 1) * c2 * Db);
+    // checkpoints C_0..C_k; at least three (the fixed-point scheme's env, F(env), F(F(env)))
+    const size_t nck = (size_t)std::max(k + 1, 3);
+    L.ckC = take(nck * c2);
+    L.ckT = take(nck * c2 * Db);
     L.Cb = take(c2); L.Tb = take(c2 * Db);
     L.Cb2 = take(c2); L.Tb2 = take(c2 * Db);
     L.Ctmp = take(c2); L.Ttmp = take(c2 * Db);
@@ -232,6 +234,9 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
 }
 
 constexpr int kPhases = 8;  // reduced corner, QR, 3a, 3b, 3c, corner, sym/norm, spectrum
+// largest relative change of (C, T) under two QR steps that the fixed-point
+// gradient accepts as a fixed point
+constexpr double kFpMaxResidual = 1e-8;
 
 // small-scalar slots (doubles) inside Plan::small
 // SL_DELTA: ring of kDeltaSlots deltas (one per QR step, written on the
@@ -260,6 +265,8 @@ struct ctm_ctx {
     std::string err;
     // optional per-phase timing of QR steps (hipEvents on the context stream)
     bool timing = false;
+    long long grad_steps = 0;  // steps reversed by the last gradient
+    double fp_residual = 0.0;  // |G(env) - env| / |env| of the last fixed-point gradient
     hipEvent_t ev[kPhases + 1] = {};
     hipEvent_t ev_sp[2] = {};
     double ms_phase[kPhases] = {};
@@ -577,23 +584,42 @@ __global__ void zero_kernel(double* x, long long n) {
         x[e] = 0.0;
 }
 
-Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA) {
+Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, bool* series_done) {
     QRCTM_TRY(join_aux(c));
+    const bool fixed_point = c->opts.grad_mode == CTM_GRAD_FIXED_POINT;
     const int k = c->opts.k_tracked;
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     const size_t nC = (size_t)chi * chi, nT = nC * Dab;
     const GradPtrs g = grad_ptrs(c);
-    // checkpoints C_0..C_k (compact, chi_cur-sized)
+    // checkpoints: C_0..C_k (checkpointed), or env, F(env), F(F(env)) (fixed point)
+    const int nfwd = fixed_point ? 2 : k;
     QRCTM_HIP(hipMemcpyAsync(g.ckC, c->C(), nC * 8, hipMemcpyDeviceToDevice, c->st));
     QRCTM_HIP(hipMemcpyAsync(g.ckT, c->T(), nT * 8, hipMemcpyDeviceToDevice, c->st));
-    for (int i = 0; i < k; ++i) {
+    for (int i = 0; i < nfwd; ++i) {
         QRCTM_TRY(qr_step_core(c, g.ckC + i * nC, g.ckT + i * nT, g.ckC + (i + 1) * nC,
                                g.ckT + (i + 1) * nT, false, 0));
         QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, i == 0, c->st));
     }
+    if (fixed_point) {
+        // the scheme needs env = G(env) elementwise (C and T each have unit norm)
+        double r2 = 0.0;
+        QRCTM_TRY(sq_diff(g.ckC + 2 * nC, g.ckC, g.ckT + 2 * nT, g.ckT, (long long)nC,
+                          (long long)nT, g.part, &r2, c->st));
+        c->fp_residual = std::sqrt(r2 / 2.0);
+        if (!(c->fp_residual <= kFpMaxResidual)) {
+            Status s;
+            s.code = CTM_ESTATE;
+            s.msg = "fixed-point gradient: the environment is not a fixed point of two QR steps "
+                    "(relative change " + std::to_string(c->fp_residual) +
+                    "); converge it further or use the checkpointed scheme";
+            return s;
+        }
+    }
+    // the energy of the tracked steps' end (checkpointed) or of env itself
+    const size_t ke = fixed_point ? 0 : (size_t)k;
     EnergyArgs ea{};
     ea.d = c->sh.d; ea.D = c->sh.D; ea.chi = chi;
-    ea.C = g.ckC + (size_t)k * nC; ea.T = g.ckT + (size_t)k * nT; ea.As = c->ptr(c->plan.As);
+    ea.C = g.ckC + ke * nC; ea.T = g.ckT + ke * nT; ea.As = c->ptr(c->plan.As);
     ea.ws = c->ptr<char>(c->plan.energy); ea.ws_bytes = c->plan.energy_bytes;
     ea.splitk = nullptr; ea.splitk_bytes = 0;
     QRCTM_TRY(energy_grad_eval(ea, h_nn, E, g.Cb, g.Tb, g.Asb, c->st));
@@ -605,20 +631,59 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA) {
     double* Tb = g.Tb;
     double* Cb2 = g.Cb2;
     double* Tb2 = g.Tb2;
-    for (int i = k - 1; i >= 0; --i) {
+    auto reverse_step = [&](int i) -> Status {
         GradPtrs gi = g;
         gi.Cb = Cb; gi.Tb = Tb; gi.Cb2 = Cb2; gi.Tb2 = Tb2;
         QRCTM_TRY(qr_step_backward(c, gi, g.ckC + i * nC, g.ckT + i * nT));
         std::swap(Cb, Cb2);
         std::swap(Tb, Tb2);
+        return Status{};
+    };
+    *series_done = true;
+    if (!fixed_point) {
+        for (int i = k - 1; i >= 0; --i) QRCTM_TRY(reverse_step(i));
+        c->grad_steps = k;
+    } else {
+        // lam = sum_n ebar (dG/denv)^n, G = F o F: reverse env1 -> env, then env -> env1,
+        // accumulating the a-cotangent of every reversed step, until a term is small
+        double n0 = 0.0, nn = 0.0;
+        QRCTM_TRY(sq_norm(Cb, Tb, (long long)nC, (long long)nT, g.part, &n0, c->st));
+        const double stop = c->opts.fp_tol * c->opts.fp_tol * n0;
+        double least = n0;
+        long long steps = 0;
+        *series_done = false;
+        while (steps < c->opts.fp_max_iter) {
+            QRCTM_TRY(reverse_step(1));
+            // the reversed step recomputed the QR at env1: its R enters the check too
+            if (steps == 0) QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, false, c->st));
+            QRCTM_TRY(reverse_step(0));
+            steps += 2;
+            QRCTM_TRY(sq_norm(Cb, Tb, (long long)nC, (long long)nT, g.part, &nn, c->st));
+            if (!std::isfinite(nn)) {
+                Status s;
+                s.code = CTM_ENONFINITE;
+                s.msg = "non-finite cotangent in the fixed-point series";
+                return s;
+            }
+            if (nn <= stop) {
+                *series_done = true;
+                break;
+            }
+            // a term whose norm is a hundred times the smallest so far (squared
+            // norms compared): the linearised step pair does not contract here
+            least = std::min(least, nn);
+            if (nn > 1e4 * least) break;
+        }
+        c->grad_steps = steps;
     }
     QRCTM_TRY(double_layer_backward(g.abar, c->ptr(c->plan.As), c->sh.d, c->sh.D, g.Asb, c->st));
     QRCTM_TRY(c4v_backward(g.Asb, c->ptr(c->plan.As), c->small() + SL_SCALE, c->imax(), c->sh.d,
                            c->sh.D, dA, c->st));
     double ratio = 1.0;
-    if (k > 0) QRCTM_HIP(hipMemcpyAsync(&ratio, g.ratio, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    if (nfwd > 0)
+        QRCTM_HIP(hipMemcpyAsync(&ratio, g.ratio, sizeof(double), hipMemcpyDeviceToHost, c->st));
     QRCTM_TRY(sync(c->st));
-    if (k > 0 && !(ratio >= c->opts.qr_sing_tol)) {
+    if (nfwd > 0 && !(ratio >= c->opts.qr_sing_tol)) {
         Status s;
         s.code = CTM_ESINGULAR;
         s.msg = "reduced corner numerically rank deficient in a tracked step (min|R_ii|/max|R_ii| = " +
@@ -676,7 +741,9 @@ Status start_environment(ctm_ctx* c) {
 bool valid_opts(const ctm_opts& o) {
     return (o.precision == CTM_PREC_FP64 || o.precision == CTM_PREC_FP32_MFMA ||
             o.precision == CTM_PREC_BF16X6_MFMA) &&
-           o.k_tracked >= 0 && (o.edge_split == 0 || o.edge_split == 1);
+           o.k_tracked >= 0 && (o.edge_split == 0 || o.edge_split == 1) &&
+           (o.grad_mode == CTM_GRAD_CHECKPOINT || o.grad_mode == CTM_GRAD_FIXED_POINT) &&
+           o.fp_tol > 0.0 && o.fp_max_iter >= 2;
 }
 
 int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_t ws_bytes,
@@ -754,6 +821,9 @@ void ctm_default_opts(ctm_opts* o) {
     o->qr_sing_tol = 1e-14;
     o->mixed_tol = 1e-6;
     o->edge_split = 1;
+    o->grad_mode = CTM_GRAD_CHECKPOINT;
+    o->fp_tol = 1e-10;
+    o->fp_max_iter = 1000;
 }
 
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
@@ -1006,7 +1076,9 @@ int ctm_energy_grad(ctm_ctx* c, const double* h_nn, const double* h_nnn, double 
     if (!c->sh.quantum) return fail(c, CTM_ESTATE, "gradient needs a site tensor (ctm_init)");
     if (h_nnn != nullptr && J2 != 0.0)
         return fail(c, CTM_EINVAL, "ctm_energy_grad supports nearest-neighbour models (h_nnn = NULL)");
-    return guarded(c, [&]() -> Status { return energy_grad_impl(c, h_nn, E, dA); });
+    bool series_done = true;
+    const int rc = guarded(c, [&]() -> Status { return energy_grad_impl(c, h_nn, E, dA, &series_done); });
+    return (rc == CTM_OK && !series_done) ? CTM_NOTCONV : rc;
 }
 
 int ctm_lnz_per_site(ctm_ctx* c, double* lnk) {
@@ -1051,6 +1123,8 @@ int ctm_stats(ctm_ctx* c, ctm_stats_t* st) {
         st->r_diag_ratio = c->steps > 0 ? r : NAN;
         st->timed_steps = c->timed_steps;
         for (int i = 0; i < kPhases; ++i) st->ms_phase[i] = c->ms_phase[i];
+        st->grad_steps = c->grad_steps;
+        st->fp_residual = c->fp_residual;
         return Status{};
     });
 }

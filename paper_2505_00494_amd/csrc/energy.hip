@@ -164,24 +164,40 @@ ELayout e_layout(int d, int D, int chi) {
     L.rhob = take(dd * dd * dd * dd);
     L.rho2 = take(dd * dd * dd * dd);
     L.red = take(kRedBlocks);
-    // split-K partials: the largest of the reductions over chi^2 D^2 or chi^2 d D^2
+    // split-K partials: the largest over every product of the forward and reverse
+    // energy contractions (M, N, K as in nn_rho_forward, energy_grad_eval, nnn_rho)
     size_t sk = 0;
     {
-        GemmDesc g;
-        g.M = (long long)dd * dd; g.N = g.M; g.K = (long long)c * c * D2;
-        sk = std::max(sk, gemm_splitk_bytes(g));
-        g.M = (long long)D2; g.N = (long long)dd * D2; g.K = (long long)c * c * dd * D2;
-        sk = std::max(sk, gemm_splitk_bytes(g));
-        g.K = (long long)c * c * D2;
-        sk = std::max(sk, gemm_splitk_bytes(g));
-        g.M = (long long)c * D2; g.N = (long long)c; g.K = (long long)c * dd * dd * D2;
-        sk = std::max(sk, gemm_splitk_bytes(g));
-        g.M = (long long)c; g.N = (long long)c; g.K = (long long)c * D2;
-        sk = std::max(sk, gemm_splitk_bytes(g));
-        g.M = (long long)c; g.N = (long long)c * D2; g.K = (long long)c * D2;
-        sk = std::max(sk, gemm_splitk_bytes(g));
-        g.M = (long long)dd * dd; g.N = (long long)c * D2 * c; g.K = (long long)dd * dd;
-        sk = std::max(sk, gemm_splitk_bytes(g));
+        auto add = [&](long long M, long long N, long long K) {
+            GemmDesc g;
+            g.M = M; g.N = N; g.K = K;
+            sk = std::max(sk, gemm_splitk_bytes(g));
+        };
+        const long long cc = (long long)c, q = (long long)D2, e = (long long)dd;
+        const long long K = cc * q * cc, Mleft = cc * e * e * q, n = cc * q;
+        // forward
+        add(q * cc, q * cc, cc);
+        add(cc * cc * q, e * q, q);
+        add(cc * cc * e * q, e * q, q);
+        add(cc * e * e * q, cc, cc * q);
+        add(e * e, e * e, K);
+        // reverse
+        add(e * e, K, e * e);
+        add(Mleft, cc * q, cc);
+        add(cc * q, cc, Mleft);
+        add(cc * cc * e * q, q, e * q);
+        add(q, e * q, cc * cc * e * q);
+        add(cc * cc * q, q, e * q);
+        add(q, e * q, cc * cc * q);
+        add(cc, q * cc, q * cc);
+        add(cc * q, cc, cc);
+        add(cc, cc, cc * q);
+        add(cc, q * cc, cc);
+        // next-nearest-neighbour term (Dab = D^2)
+        add(cc, q * cc, cc);
+        add(q * cc, q * cc, cc);
+        add(cc * cc, q * q, q * q);
+        add(n, n, n);
     }
     L.splitk_bytes = sk + 256;
     L.splitk = take(L.splitk_bytes / sizeof(double) + 1);

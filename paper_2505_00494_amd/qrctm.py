@@ -22,6 +22,7 @@ CTM_OK, CTM_NOTCONV = 0, 1
 CTM_EINVAL, CTM_EWORKSPACE, CTM_EHIP, CTM_ENONFINITE, CTM_ESINGULAR, CTM_ESTATE = (
     -1, -2, -3, -4, -5, -6)
 PREC_FP64, PREC_FP32_MFMA, PREC_BF16X6_MFMA = 0, 1, 2
+GRAD_CHECKPOINT, GRAD_FIXED_POINT = 0, 1
 
 
 class CTMError(RuntimeError):
@@ -32,14 +33,16 @@ class CTMError(RuntimeError):
 
 class CtmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("n_warmup", c_int), ("k_tracked", c_int),
-                ("qr_sing_tol", c_double), ("mixed_tol", c_double), ("edge_split", c_int)]
+                ("qr_sing_tol", c_double), ("mixed_tol", c_double), ("edge_split", c_int),
+                ("grad_mode", c_int), ("fp_tol", c_double), ("fp_max_iter", c_int)]
 
 
 class CtmStats(ctypes.Structure):
     _fields_ = [("chi", c_int), ("chi_cur", c_int), ("Dab", c_int), ("steps", c_longlong),
                 ("last_delta", c_double), ("flops_per_step", c_double),
                 ("r_diag_ratio", c_double), ("timed_steps", c_longlong),
-                ("ms_phase", c_double * 8)]
+                ("ms_phase", c_double * 8), ("grad_steps", c_longlong),
+                ("fp_residual", c_double)]
 
 PHASES = ("reduced_corner", "qr", "edge_3a", "edge_3b", "edge_3c", "corner", "sym_norm",
           "spectrum")
@@ -123,7 +126,8 @@ def _dev_f64(x, dev):
 
 
 def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-14,
-                 mixed_tol=None, edge_split=None) -> CtmOpts:
+                 mixed_tol=None, edge_split=None, grad_mode=None, fp_tol=None,
+                 fp_max_iter=None) -> CtmOpts:
     o = CtmOpts()
     lib().ctm_default_opts(byref(o))
     o.precision, o.n_warmup, o.k_tracked, o.qr_sing_tol = precision, n_warmup, k_tracked, qr_sing_tol
@@ -131,6 +135,12 @@ def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-
         o.mixed_tol = mixed_tol
     if edge_split is not None:
         o.edge_split = int(edge_split)
+    if grad_mode is not None:
+        o.grad_mode = int(grad_mode)
+    if fp_tol is not None:
+        o.fp_tol = float(fp_tol)
+    if fp_max_iter is not None:
+        o.fp_max_iter = int(fp_max_iter)
     return o
 
 
@@ -139,11 +149,12 @@ class Context:
 
     def __init__(self, A=None, chi: int = 16, *, a=None, bvec=None, device="cuda:0",
                  n_warmup: int = -1, precision: int = PREC_FP64, k_tracked: int = 10,
-                 qr_sing_tol: float = 1e-14, mixed_tol=None, edge_split=None):
+                 qr_sing_tol: float = 1e-14, mixed_tol=None, edge_split=None,
+                 grad_mode=None, fp_tol=None, fp_max_iter=None):
         torch = _torch()
         self.device = torch.device(device)
         self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol,
-                                 edge_split)
+                                 edge_split, grad_mode, fp_tol, fp_max_iter)
         self.chi = chi
         L = lib()
         ctx = c_void_p()
@@ -243,9 +254,11 @@ class Context:
         dA = torch.empty((self.d, self.D, self.D, self.D, self.D), dtype=torch.float64,
                          device=self.device)
         E = c_double()
-        self._c(lib().ctm_energy_grad(self._ctx, h1.ctypes.data_as(POINTER(c_double)),
-                                      None if h2 is None else h2.ctypes.data_as(POINTER(c_double)),
-                                      J2, byref(E), c_void_p(dA.data_ptr())))
+        rc = self._c(lib().ctm_energy_grad(self._ctx, h1.ctypes.data_as(POINTER(c_double)),
+                                           None if h2 is None else h2.ctypes.data_as(POINTER(c_double)),
+                                           J2, byref(E), c_void_p(dA.data_ptr())))
+        # fixed-point scheme: False when the series stopped at opts.fp_max_iter
+        self.grad_converged = rc == CTM_OK
         return E.value, dA
 
     def lnz_per_site(self) -> float:

@@ -31,7 +31,8 @@ def _env(d, D, chi, seed, steps):
     return A, C, T
 
 
-@pytest.mark.parametrize("d,D,chi,k", [(2, 2, 16, 0), (2, 2, 16, 4), (2, 3, 27, 3), (2, 4, 64, 2)])
+@pytest.mark.parametrize("d,D,chi,k", [(2, 2, 16, 0), (2, 2, 16, 4), (2, 3, 27, 3), (2, 4, 64, 2),
+                                       (2, 5, 100, 1)])
 def test_gradient_matches_oracle(d, D, chi, k):
     print(f"grad d={d} D={D} chi={chi} k={k}", flush=True)
     A, C, T = _env(d, D, chi, seed=1, steps=10)

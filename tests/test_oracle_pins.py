@@ -363,3 +363,60 @@ def test_energy_gradient_matches_finite_differences():
     # invariants: scale invariance and C4v symmetry of the gradient
     assert abs(np.sum(g * A)) < 1e-10 * np.linalg.norm(g) * np.linalg.norm(A)
     assert np.abs(ctm.c4v_average(g) - g).max() < 1e-14
+
+
+def _converged_pair_env(a, chi, D, tol):
+    """Environment converged under G = F o F (F one QR step + sym_norm) to max |change| < tol."""
+    r = ctm.ctmrg(a, chi, ctm.identity_boundary_vector(D), tol=1e-14, max_steps=3000)
+    C, T = r.C, r.T
+    for _ in range(3000):
+        Cn, Tn = ctm.sym_norm(*ctm.qr_step(*ctm.sym_norm(*ctm.qr_step(C, T, a)), a))
+        dd = max(np.abs(Cn - C).max(), np.abs(Tn - T).max())
+        C, T = Cn, Tn
+        if dd < tol:
+            break
+    return C, T
+
+
+def test_fixed_point_gradient_matches_finite_differences_of_converged_energy():
+    # Discussion paragraph (fixed-point AD): dE/dA of the energy at the
+    # converged environment, against central differences of that energy, each
+    # side re-converged from the unperturbed fixed point
+    d, D, chi, seed = 2, 2, 8, 3
+    A = inp.random_site_tensor(d, D, seed)
+    h = inp.heisenberg_bond_rotated()
+    a = ctm.double_layer(ctm.prepare_site_tensor(A))
+    C, T = _converged_pair_env(a, chi, D, 1e-15)
+    e, g, n = adj.energy_grad_fixed_point(A, C, T, h, tol=1e-13)
+    assert n is not None and n % 2 == 0
+
+    def e_conv(Ap):
+        Asp = ctm.prepare_site_tensor(Ap)
+        ap = ctm.double_layer(Asp)
+        Cc, Tc = C, T
+        for _ in range(2000):
+            Cn, Tn = ctm.sym_norm(*ctm.qr_step(*ctm.sym_norm(*ctm.qr_step(Cc, Tc, ap)), ap))
+            dd = max(np.abs(Cn - Cc).max(), np.abs(Tn - Tc).max())
+            Cc, Tc = Cn, Tn
+            if dd < 1e-15:
+                break
+        return obs.energy_nn(Cc, Tc, Asp, h)
+
+    idx = inp.fd_entries(d, D, seed, n=8)
+    hh = 1e-5
+    fd = []
+    for i in idx:
+        Ap = A.ravel().copy()
+        Am = A.ravel().copy()
+        Ap[i] += hh
+        Am[i] -= hh
+        fd.append((e_conv(Ap.reshape(A.shape)) - e_conv(Am.reshape(A.shape))) / (2 * hh))
+    fd = np.array(fd)
+    ga = g.ravel()[idx]
+    assert np.linalg.norm(fd - ga) / np.linalg.norm(ga) < 1e-6
+    assert abs(e - obs.energy_nn(C, T, ctm.prepare_site_tensor(A), h)) < 1e-15
+    assert abs(np.sum(g * A)) < 1e-10 * np.linalg.norm(g) * np.linalg.norm(A)
+    assert np.abs(ctm.c4v_average(g) - g).max() < 1e-14
+    # the k-step gradient from the fixed point tends to it as k grows
+    errs = [np.abs(adj.energy_grad_k(A, C, T, k, h)[1] - g).max() for k in (4, 16, 64)]
+    assert errs[2] < errs[1] < errs[0] and errs[2] < 1e-8 * np.abs(g).max()
