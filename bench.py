@@ -266,7 +266,8 @@ def main():
     # plain form: 3b as one FP64 GEMM with the double-layer tensor
     pctx = P.Context(A, chi, n_warmup=0, edge_split=0)
     pctx.set_env(C0, T0)
-    pctx.step(args.warmup)
+    if args.warmup:
+        pctx.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pctx.step(args.steps)
@@ -305,7 +306,8 @@ def main():
                  "FP64 split kernel; QR, normalisation, spectrum FP64")):
             mctx = P.Context(A, chi, precision=prec, n_warmup=0)
             mctx.set_env(C0, T0)
-            mctx.step(args.warmup)
+            if args.warmup:
+                mctx.step(args.warmup)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             mctx.step(args.steps)

@@ -130,11 +130,19 @@ GemmDesc bw_gemm(int id, const BwPtrs& p, int chi, int Dab) {
 
 struct GradLayout {
     size_t ckC, ckT, Cb, Tb, Cb2, Tb2, Ctmp, Ttmp, Cpb, Tpb, Wb, Rb, Qb, Zg, Mm, Ms, Rinv, ctb, abar,
-        Asb, part, ratio, splitk;
-    size_t splitk_bytes = 0, total = 0;
+        Asb, part, ratio, splitk, bwpart;
+    size_t splitk_bytes = 0, bwpart_doubles = 0, total = 0;
 };
 
-GradLayout grad_layout(const Shape& sh, int k) {
+// 3b as the fused split kernel (forward), and its fused reverse where built
+bool use_split(const Shape& sh, const ctm_opts& o) {
+    return sh.quantum && o.edge_split == 1 && edge_split_supported(sh.d, sh.D);
+}
+bool use_split_bw(const Shape& sh, const ctm_opts& o) {
+    return use_split(sh, o) && edge_split_bw_supported(sh.d, sh.D);
+}
+
+GradLayout grad_layout(const Shape& sh, int k, bool split_bw) {
     GradLayout L;
     if (!sh.quantum) return L;
     size_t off = 0;
@@ -164,6 +172,8 @@ GradLayout grad_layout(const Shape& sh, int k) {
         for (int id = 0; id < kBwGemms; ++id) sk = std::max(sk, gemm_splitk_bytes(bw_gemm(id, p, cc, sh.Dab)));
     L.splitk_bytes = sk;
     L.splitk = take(sk / sizeof(double) + 1);
+    L.bwpart_doubles = split_bw ? edge_split_bw_part_size(sh.d, sh.D) : 0;
+    L.bwpart = take(L.bwpart_doubles + 1);
     L.total = off;
     return L;
 }
@@ -221,14 +231,13 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     P.energy_bytes = sh.quantum ? energy_scratch_bytes(sh.d, sh.D, sh.chi)
                                 : classical_scratch_bytes(sh.Dab, sh.chi);
     take(P.energy, P.energy_bytes);
-    P.grad_bytes = grad_layout(sh, o.k_tracked).total;
+    P.grad_bytes = grad_layout(sh, o.k_tracked, use_split_bw(sh, o)).total;
     take(P.grad, P.grad_bytes);
     // planes need the contraction length Dab^2 to be a multiple of 8 (D even)
     const bool planes = o.precision == CTM_PREC_BF16X6_MFMA && (Dab * Dab) % 8 == 0;
     take(P.Y16, planes ? 3 * sizeof(unsigned short) * chi * chi * Dab * Dab : 0);
     take(P.a16, planes ? 3 * sizeof(unsigned short) * Dab * Dab * Dab * Dab : 0);
-    const bool split = sh.quantum && o.edge_split == 1 && edge_split_supported(sh.d, sh.D);
-    take(P.Bk, split ? d8 * edge_split_operand_size(sh.d, sh.D) : 0);
+    take(P.Bk, use_split(sh, o) ? d8 * edge_split_operand_size(sh.d, sh.D) : 0);
     P.total = off;
     return P;
 }
@@ -527,13 +536,13 @@ Status eigh_step_once(ctm_ctx* c) {
 
 struct GradPtrs {
     double *ckC, *ckT, *Cb, *Tb, *Cb2, *Tb2, *Ctmp, *Ttmp, *Cpb, *Tpb, *Wb, *Rb, *Qb, *Zg, *Mm, *Ms,
-        *Rinv, *ctb, *abar, *Asb, *part, *ratio;
+        *Rinv, *ctb, *abar, *Asb, *part, *ratio, *bwpart;
     void* splitk;
-    size_t splitk_bytes;
+    size_t splitk_bytes, bwpart_doubles;
 };
 
 GradPtrs grad_ptrs(ctm_ctx* c) {
-    const GradLayout L = grad_layout(c->sh, c->opts.k_tracked);
+    const GradLayout L = grad_layout(c->sh, c->opts.k_tracked, use_split_bw(c->sh, c->opts));
     char* b = c->ptr<char>(c->plan.grad);
     auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
     GradPtrs g;
@@ -544,6 +553,8 @@ GradPtrs grad_ptrs(ctm_ctx* c) {
     g.ratio = P(L.ratio);
     g.splitk = b + L.splitk;
     g.splitk_bytes = L.splitk_bytes;
+    g.bwpart = P(L.bwpart);
+    g.bwpart_doubles = L.bwpart_doubles;
     return g;
 }
 
@@ -566,7 +577,16 @@ Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, const double* Ci, const d
     // a9: symmetrise / normalise
     QRCTM_TRY(sym_norm_backward(g.Ctmp, g.Ttmp, g.Cb, g.Tb, c->small() + SL_NORMS, chi, Dab, g.Cpb,
                                 g.Tpb, g.part, c->st));
-    for (int id = 0; id <= 9; ++id) QRCTM_TRY(run(id));   // a8, a7 (3c, 3b, 3a)
+    if (g.bwpart_doubles > 0) {
+        // a8, a7 (3c), the split reverse of 3b (Ybar into Y2, the site tensor's
+        // cotangent straight into Asb), a7 (3a)
+        for (int id = 0; id <= 5; ++id) QRCTM_TRY(run(id));
+        QRCTM_TRY(edge_split_3b_backward(sp.Y, g.Zg, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi,
+                                         p.Y2, g.bwpart, g.bwpart_doubles, g.Asb, c->st));
+        for (int id = 8; id <= 9; ++id) QRCTM_TRY(run(id));
+    } else {
+        for (int id = 0; id <= 9; ++id) QRCTM_TRY(run(id));   // a8, a7 (3c, 3b, 3a)
+    }
     QRCTM_TRY(run(10));                                    // a6: M = R Rbar^T - Qbar^T Q
     QRCTM_TRY(run(11));
     QRCTM_TRY(copyltu(g.Mm, chi, g.Ms, c->st));
@@ -676,7 +696,9 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
         }
         c->grad_steps = steps;
     }
-    QRCTM_TRY(double_layer_backward(g.abar, c->ptr(c->plan.As), c->sh.d, c->sh.D, g.Asb, c->st));
+    // the double layer's cotangent is zero when every reversed 3b was the split form
+    if (g.bwpart_doubles == 0)
+        QRCTM_TRY(double_layer_backward(g.abar, c->ptr(c->plan.As), c->sh.d, c->sh.D, g.Asb, c->st));
     QRCTM_TRY(c4v_backward(g.Asb, c->ptr(c->plan.As), c->small() + SL_SCALE, c->imax(), c->sh.d,
                            c->sh.D, dA, c->st));
     double ratio = 1.0;
@@ -940,7 +962,8 @@ int ctm_step(ctm_ctx* c, int nsteps, double* delta) {
         QRCTM_TRY(read_bad(c, &bad));
         c->last_delta = h[0];
         if (delta) *delta = h[0];
-        if (bad || !std::isfinite(h[0])) {
+        // nsteps = 0 reports the last step's change (NaN before the first step)
+        if (bad || (nsteps > 0 && !std::isfinite(h[0]))) {
             Status s;
             s.code = CTM_ENONFINITE;
             s.msg = "non-finite environment in ctm_step";

@@ -21,7 +21,7 @@ bool edge_split_supported(int d, int D);
 size_t edge_split_operand_size(int d, int D);
 // Bk[s][k][n] = As[s][u][l][dd][r] for k = u D + l, n = r D + dd (zero outside
 // k, n < D^2; rows padded to a multiple of 4, columns to a multiple of 16),
-// and the launch counters cleared.  As is the prepared site tensor, layout
+// its transpose in the same shape after it, and the launch counters cleared.  As is the prepared site tensor, layout
 // [s][u][l][dd][r].
 Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_t st);
 // Z (chio x D^2 x chi x D^2, layout [al][r][f][dd]) from Y (chio x chi x D^2 x
@@ -30,5 +30,16 @@ Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_
 // not overlap.
 Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chio, double* Z,
                      hipStream_t st);
+// (d, D) for which the fused reverse is built: d = 2, 1 <= D <= 6.
+bool edge_split_bw_supported(int d, int D);
+// Doubles of the partial-sum scratch edge_split_3b_backward needs.
+size_t edge_split_bw_part_size(int d, int D);
+// Reverse of edge_split_3b: from Zb (the cotangent of Z, layout [al][f][r][dd])
+// and the forward input Y, write Yb (layout [u][al][f][l]) and add the site
+// tensor's cotangent from both layers into Asb (layout [s][u][l][dd][r]).
+// Y, Zb and Yb must not overlap; part is scratch of edge_split_bw_part_size.
+Status edge_split_3b_backward(const double* Y, const double* Zb, double* Bk, int d, int D, int chi,
+                              int chio, double* Yb, double* part, size_t part_doubles, double* Asb,
+                              hipStream_t st);
 
 }  // namespace qrctm

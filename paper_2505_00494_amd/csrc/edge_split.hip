@@ -204,15 +204,299 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
     }
 }
 
+// Bk[s][k][n] = As[s][u][l][dd][r] (k = u D + l, n = r D + dd) and, after it,
+// BkT[s][k][n] = Bk[s][n][k], both [d][KP][NP] and zero outside k, n < D^2;
+// then the ticket counters.
 __global__ void edge_split_prepare_kernel(const double* __restrict__ As, int d, int D, int KP,
                                           int NP, double* Bk) {
     const int R = D * D, n = d * KP * NP;
-    // ticket counters after the operand
-    if (blockIdx.x == 0 && threadIdx.x < kTickets) reinterpret_cast<unsigned*>(Bk + n)[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < kTickets)
+        reinterpret_cast<unsigned*>(Bk + 2 * n)[threadIdx.x] = 0u;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int s = e / (KP * NP), k = (e / NP) % KP, c = e % NP;
-        Bk[e] = (k < R && c < R) ? As[(long long)s * R * R + k * R + (c % D) * D + c / D] : 0.0;
+        const double* A = As + (long long)s * R * R;
+        Bk[e] = (k < R && c < R) ? A[k * R + (c % D) * D + c / D] : 0.0;
+        Bk[n + e] = (k < R && c < R) ? A[c * R + (k % D) * D + k / D] : 0.0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of 3b in the split form.  With Zb the cotangent of Z, per (al, f)
+// block and per s (X_s as in the forward pass):
+//   Xb_s[(r_k d_k)][(u_b l_b)] = sum_{(r_b d_b)} Zb[(r_k r_b)][(d_k d_b)] Bk[s][(u_b l_b)][(r_b d_b)]
+//   Yb[(u_k u_b)][(l_k l_b)]  += sum_{(r_k d_k)} Xb_s[(r_k d_k)][(u_b l_b)] Bk[s][(u_k l_k)][(r_k d_k)]
+//   Bkb[s] (bra) += sum_{blocks, (r_k d_k)} X_s[(u_b l_b)][(r_k d_k)] Zb[(r_k r_b)][(d_k d_b)]
+//   Bkb[s] (ket) += sum_{blocks, (u_b l_b)} Y[(u_k u_b)][(l_k l_b)] Xb_s[(r_k d_k)][(u_b l_b)]
+// in one kernel: Y and Zb staged in LDS (transposed), X_s and Xb_s computed
+// into LDS, Yb accumulated over s in registers and written once, the Bkb
+// sums accumulated over the workgroup's batches in registers and written
+// per workgroup; a second kernel adds the workgroups' sums into the site
+// tensor's cotangent.  Per batch and s: five M x N x K products on
+// v_mfma_f64_16x16x4f64, the last two with K over the batch's blocks.  The
+// LDS row length is odd so that those two read columns conflict-free.
+// ---------------------------------------------------------------------------
+constexpr int kBwPairs[9] = {0, 80, 20, 8, 5, 3, 2, 1, 1};  // D = 7, 8: not built
+
+// x returned through an empty asm statement: index arithmetic on it is redone
+// where it is used instead of being hoisted out of the batch loop into
+// registers (which the accumulators need)
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+constexpr int kBwGroups[9] = {0, 5, 5, 5, 5, 5, 5, 2, 2};
+constexpr int kBwWavesPerSimd[9] = {0, 2, 2, 2, 2, 2, 4, 2, 2};
+constexpr int kBwMaxGrid = 512;
+
+template <int D>
+struct ShapeBw {
+    static constexpr int R = D * D;
+    static constexpr int KP = (R + 3) / 4 * 4;
+    static constexpr int NP = (R + 15) / 16 * 16;
+    static constexpr int NB = NP / 16;
+    static constexpr int P = kBwPairs[D];
+    static constexpr int MP = (P * R + 15) / 16 * 16;
+    static constexpr int MT = MP / 16;
+    static constexpr int G = kBwGroups[D];
+    static constexpr int MTW = MT / G;
+    static constexpr int W = NB * G;                  // waves
+    static constexpr int NT = W * 64;
+    static constexpr int LDM = MP + 1;                // odd row length
+    static constexpr int NY = P * R * R;
+    static constexpr int NL = (NY + NT - 1) / NT;
+    static constexpr int TS = 2 * NB * NB;            // Bkb tiles per s (bra, ket)
+    static constexpr int TPW = (TS + W - 1) / W;      // ... per wave
+    static constexpr int WPE = kBwWavesPerSimd[D];
+    static_assert(MT % G == 0, "row tiles split evenly over the groups");
+};
+
+template <int D>
+__global__ __launch_bounds__(ShapeBw<D>::NT)
+__attribute__((amdgpu_waves_per_eu(ShapeBw<D>::WPE))) void edge_split_bw_kernel(
+    const double* __restrict__ Y, const double* __restrict__ Zb, const double* __restrict__ Bk,
+    const double* __restrict__ BkT, int npairs, double* __restrict__ Yb,
+    double* __restrict__ part, unsigned* ticket) {
+    using S = ShapeBw<D>;
+    constexpr int R = S::R, KP = S::KP, NP = S::NP, NB = S::NB, P = S::P, MP = S::MP;
+    constexpr int MTW = S::MTW, W = S::W, NT = S::NT, LDM = S::LDM, NY = S::NY, NL = S::NL;
+    constexpr int KS = KP / 4, TS = S::TS, TPW = S::TPW;
+    constexpr int DP = 2;
+    __shared__ double ys[NP * LDM];   // ys[(u_k l_k)][(p u_b l_b)]
+    __shared__ double zs[NP * LDM];   // zs[(r_b d_b)][(p r_k d_k)]
+    __shared__ double xs[NP * LDM];   // xs[(u_b l_b)][(p r_k d_k)]   X_s
+    __shared__ double xbs[NP * LDM];  // xbs[(r_k d_k)][(p u_b l_b)]  Xb_s
+    __shared__ int next_batch;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, q = lane >> 4, l16 = lane & 15;
+    const int w = tid >> 6;
+    const int nt = w % NB, mt0 = (w / NB) * MTW;
+    const int nbatch = (npairs + P - 1) / P;
+    auto draw = [&]() {
+        if (tid == 0) {
+            const unsigned t = atomicAdd(ticket, 1u);
+            if (t == (unsigned)(nbatch + gridDim.x - 1)) atomicExch(ticket, 0u);
+            next_batch = (int)min(t, (unsigned)nbatch);
+        }
+    };
+
+    for (int i = tid; i < NP * LDM; i += NT) {
+        ys[i] = 0.0;
+        zs[i] = 0.0;
+        xs[i] = 0.0;
+        xbs[i] = 0.0;
+    }
+    dbl4 ab[DP][TPW];
+#pragma unroll
+    for (int s = 0; s < DP; ++s)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) ab[s][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    // 32-bit offsets: the host guarantees npairs D^4 + 2^16 < 2^31
+    const int ylim = npairs * R * R;
+    double py[NL], pz[NL];
+    auto load = [&](int b) {
+        const int base = b * NY;
+        const int tv = opaque(tid);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tv + i * NT;
+            const bool in = e < NY && base + e < ylim;
+            py[i] = in ? Y[base + e] : 0.0;
+            pz[i] = in ? Zb[base + e] : 0.0;
+        }
+    };
+    // block digits v = ((a0 D + a1) D + a2) D + a3: Y [u_k][u_b][l_k][l_b],
+    // Zb [r_k][r_b][d_k][d_b]
+    auto store = [&]() {
+        const int tv = opaque(tid);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tv + i * NT;
+            if (e < NY) {
+                const int p = e / (R * R), v = e % (R * R);
+                const int a0 = v / (D * R), a1 = (v / R) % D, a2 = (v / D) % D, a3 = v % D;
+                ys[(a0 * D + a2) * LDM + p * R + a1 * D + a3] = py[i];
+                zs[(a1 * D + a3) * LDM + p * R + a0 * D + a2] = pz[i];
+            }
+        }
+    };
+
+    draw();
+    __syncthreads();
+    int b = next_batch;
+    if (b < nbatch) {
+        load(b);
+        store();
+        while (true) {
+            draw();
+            __syncthreads();  // ys, zs hold batch b
+            const int bn = next_batch;
+            dbl4 yb[MTW];
+#pragma unroll
+            for (int i = 0; i < MTW; ++i) yb[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < DP; ++s) {
+                // B fragments (rows 4 kk + q, this wave's 16 columns) of Bk[s] and BkT[s]
+                const double* B1 = Bk + (s * KP + q) * NP + 16 * nt + l16;
+                const double* B2 = BkT + (s * KP + q) * NP + 16 * nt + l16;
+                dbl4 x[MTW], xb[MTW];
+#pragma unroll
+                for (int i = 0; i < MTW; ++i) {
+                    x[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+                    xb[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+                }
+#pragma unroll 3
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int o = (4 * kk + q) * LDM + 16 * mt0 + l16;
+                    const double b1 = B1[4 * kk * NP], b2 = B2[4 * kk * NP];
+#pragma unroll
+                    for (int i = 0; i < MTW; ++i) {
+                        x[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ys[o + 16 * i], b1, x[i], 0, 0, 0);
+                        xb[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(zs[o + 16 * i], b2, xb[i], 0, 0, 0);
+                    }
+                }
+                if (s > 0) __syncthreads();  // reads of xs, xbs for the previous s are done
+#pragma unroll
+                for (int i = 0; i < MTW; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = 16 * (mt0 + i) + 4 * r + q, c = 16 * nt + l16;
+                        if (m < P * R && c < R) {
+                            const int o = (m % R) * LDM + (m / R) * R + c;
+                            xs[o] = x[i][r];
+                            xbs[o] = xb[i][r];
+                        }
+                    }
+                __syncthreads();  // xs, xbs complete
+                if (s == DP - 1 && bn < nbatch) load(bn);
+                // Yb += Xb_s^T-contract Bk[s] (B fragments of BkT[s], as for Xb_s)
+#pragma unroll 3
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int o = (4 * kk + q) * LDM + 16 * mt0 + l16;
+                    const double b2 = B2[4 * kk * NP];
+#pragma unroll
+                    for (int i = 0; i < MTW; ++i)
+                        yb[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(xbs[o + 16 * i], b2, yb[i], 0, 0, 0);
+                }
+                // Bkb[s] tiles: bra (xs, zs) and ket (ys, xbs), K over the batch
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    const int u = w + W * t;
+                    if (u < TS) {
+                        const int kind = u / (NB * NB), it = (u % (NB * NB)) / NB, jt = u % NB;
+                        const double* As_ = kind ? ys : xs;
+                        const double* Bs_ = kind ? xbs : zs;
+                        const int oa = (16 * it + l16) * LDM + q, ob = (16 * jt + l16) * LDM + q;
+#pragma unroll 2
+                        for (int kk = 0; kk < MP / 4; ++kk)
+                            ab[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(As_[oa + 4 * kk],
+                                                                           Bs_[ob + 4 * kk],
+                                                                           ab[s][t], 0, 0, 0);
+                    }
+                }
+            }
+            // Yb[(u_k u_b)][block][(l_k l_b)], rows (p u_b l_b), columns (u_k l_k)
+            const int lv = opaque(lane);
+            const int n = 16 * nt + (lv & 15);
+            if (n < R) {
+                const int uk = n / D, lk = n % D;
+#pragma unroll
+                for (int i = 0; i < MTW; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = 16 * (mt0 + i) + 4 * r + (lv >> 4);
+                        if (m >= P * R) continue;
+                        const int pg = b * P + m / R;
+                        if (pg >= npairs) continue;
+                        const int c = m % R, ub = c / D, lb = c % D;
+                        Yb[((uk * D + ub) * npairs + pg) * R + lk * D + lb] = yb[i][r];
+                    }
+            }
+            if (bn >= nbatch) break;
+            __syncthreads();  // every read of ys, zs for batch b is done
+            store();
+            b = bn;
+        }
+    }
+    // this workgroup's sums: part[wg][kind][s][NP][NP]
+#pragma unroll
+    for (int s = 0; s < DP; ++s)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int u = w + W * t;
+            if (u < TS) {
+                const int kind = u / (NB * NB), it = (u % (NB * NB)) / NB, jt = u % NB;
+                double* o = part + ((size_t)(blockIdx.x * 2 + kind) * DP + s) * NP * NP;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[(16 * it + 4 * r + q) * NP + 16 * jt + l16] = ab[s][t][r];
+            }
+        }
+}
+
+// Asb[s][u][l][dd][r] += sum over workgroups and both kinds of part[..][s][u D + l][r D + dd]
+__global__ void edge_split_bw_reduce_kernel(const double* __restrict__ part, int nwg, int d, int D,
+                                            int NP, double* Asb) {
+    const int R = D * D, n = d * R * R;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int s = e / (R * R), v = e % (R * R);
+        const int k = v / R, r = v % D, dd = (v / D) % D;
+        const int o = k * NP + r * D + dd;
+        double acc = 0.0;
+        for (int g = 0; g < 2 * nwg; ++g) acc += part[((size_t)g * d + s) * NP * NP + o];
+        Asb[e] += acc;
+    }
+}
+
+template <int D>
+Status launch_3b_bw(const double* Y, const double* Zb, const double* Bk, const double* BkT,
+                    unsigned* ticket, int npairs, double* Yb, double* part, size_t part_doubles,
+                    double* Asb, hipStream_t st) {
+    using S = ShapeBw<D>;
+    static int per_cu = -1, cus = 0;
+    if (per_cu < 0) {
+        int dev = 0;
+        QRCTM_HIP(hipGetDevice(&dev));
+        QRCTM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_split_bw_kernel<D>,
+                                                               S::NT, 0));
+        if (per_cu < 1) per_cu = 1;
+    }
+    const long long nbatch = ceil_div(npairs, S::P);
+    long long grid = std::min<long long>(nbatch, (long long)per_cu * cus);
+    grid = std::min<long long>(grid, kBwMaxGrid);
+    Status s;
+    if ((size_t)grid * 4 * S::NP * S::NP > part_doubles) {
+        s.code = -2;
+        s.msg = "edge_split_3b_backward: partial-sum scratch too small";
+        return s;
+    }
+    hipLaunchKernelGGL(edge_split_bw_kernel<D>, dim3((int)grid), dim3(S::NT), 0, st, Y, Zb, Bk, BkT,
+                       npairs, Yb, part, ticket);
+    QRCTM_TRY(launch_check("edge_split_bw_kernel"));
+    hipLaunchKernelGGL(edge_split_bw_reduce_kernel, dim3(16), dim3(256), 0, st, part, (int)grid, 2, D,
+                       S::NP, Asb);
+    return launch_check("edge_split_bw_reduce_kernel");
 }
 
 template <int D>
@@ -243,7 +527,13 @@ int np_of(int D) { return (D * D + 15) / 16 * 16; }
 bool edge_split_supported(int d, int D) { return d == 2 && D >= 1 && D <= 8; }
 
 size_t edge_split_operand_size(int d, int D) {
-    return edge_split_supported(d, D) ? (size_t)d * kp_of(D) * np_of(D) + kTickets / 2 : 0;
+    return edge_split_supported(d, D) ? 2 * (size_t)d * kp_of(D) * np_of(D) + kTickets / 2 : 0;
+}
+
+bool edge_split_bw_supported(int d, int D) { return edge_split_supported(d, D) && D <= 6; }
+
+size_t edge_split_bw_part_size(int d, int D) {
+    return edge_split_bw_supported(d, D) ? (size_t)kBwMaxGrid * 2 * d * np_of(D) * np_of(D) : 0;
 }
 
 Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_t st) {
@@ -269,7 +559,7 @@ Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chi
     }
     const int npairs = chi * chio;
     if (npairs == 0) return s;
-    unsigned* tk = reinterpret_cast<unsigned*>(Bk + (size_t)d * kp_of(D) * np_of(D));
+    unsigned* tk = reinterpret_cast<unsigned*>(Bk + 2 * (size_t)d * kp_of(D) * np_of(D));
     switch (D) {
         case 1: return launch_3b<1>(Y, Bk, tk, chi, npairs, Z, st);
         case 2: return launch_3b<2>(Y, Bk, tk, chi, npairs, Z, st);
@@ -279,6 +569,32 @@ Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chi
         case 6: return launch_3b<6>(Y, Bk, tk, chi, npairs, Z, st);
         case 7: return launch_3b<7>(Y, Bk, tk, chi, npairs, Z, st);
         default: return launch_3b<8>(Y, Bk, tk, chi, npairs, Z, st);
+    }
+}
+
+
+Status edge_split_3b_backward(const double* Y, const double* Zb, double* Bk, int d, int D, int chi,
+                              int chio, double* Yb, double* part, size_t part_doubles, double* Asb,
+                              hipStream_t st) {
+    Status s;
+    if (!edge_split_bw_supported(d, D) || chi < 0 || chio < 0 ||
+        (long long)chi * chio * D * D * D * D + (1LL << 16) >= (1LL << 31)) {
+        s.code = -1;
+        s.msg = "edge_split_3b_backward: unsupported shape";
+        return s;
+    }
+    const int npairs = chi * chio;
+    if (npairs == 0) return s;
+    const size_t n = (size_t)d * kp_of(D) * np_of(D);
+    const double* BkT = Bk + n;
+    unsigned* tk = reinterpret_cast<unsigned*>(Bk + 2 * n) + 1;
+    switch (D) {
+        case 1: return launch_3b_bw<1>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        case 2: return launch_3b_bw<2>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        case 3: return launch_3b_bw<3>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        case 4: return launch_3b_bw<4>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        case 5: return launch_3b_bw<5>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        default: return launch_3b_bw<6>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
     }
 }
 

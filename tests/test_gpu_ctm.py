@@ -174,3 +174,12 @@ def test_j1j2_energy_matches_oracle(d, D, chi):
     e_nn = ctx.energy(h1)
     assert abs((e - e_nn) - 2 * J2 * obs.bond_expectation(obs.rdm_nnn(C, T, As), h2)) < 1e-12
     ctx.close()
+
+
+def test_zero_steps_report_the_last_change():
+    A = inp.random_site_tensor(2, 2, 1)
+    ctx = P.Context(_dev(A), 16, n_warmup=0)
+    assert np.isnan(ctx.step(0))
+    dl = ctx.step(2)
+    assert np.isfinite(dl) and ctx.step(0) == dl
+    ctx.close()
