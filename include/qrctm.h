@@ -77,8 +77,9 @@ typedef struct ctm_opts {
                            layer A and then the bra layer A (Fig. 1b) instead of the
                            double-layer tensor a: 4 d chi^2 D^6 in place of 2 chi^2 D^8
                            flops, FP64 in every precision, same result up to rounding.
-                           Used where available (quantum contexts with d = 2, D <= 8),
-                           otherwise ignored.  0: always the double-layer product.  */
+                           Used where available (quantum contexts with d = 2, D <= 8
+                           and chi^2 D^4 < 2^31 - 2^16), otherwise ignored.  0: always
+                           the double-layer product.                                     */
     int grad_mode;      /* CTM_GRAD_CHECKPOINT or CTM_GRAD_FIXED_POINT (ctm_energy_grad) */
     double fp_tol;      /* fixed point: the series stops when a term's norm is below
                            fp_tol times the norm of dE/d(C, T)                        */

@@ -136,7 +136,10 @@ struct GradLayout {
 
 // 3b as the fused split kernel (forward), and its fused reverse where built
 bool use_split(const Shape& sh, const ctm_opts& o) {
-    return sh.quantum && o.edge_split == 1 && edge_split_supported(sh.d, sh.D);
+    // the kernels index Y and Z with 32-bit offsets
+    const long long D4 = (long long)sh.D * sh.D * sh.D * sh.D;
+    return sh.quantum && o.edge_split == 1 && edge_split_supported(sh.d, sh.D) &&
+           (long long)sh.chi * sh.chi * D4 + (1LL << 16) < (1LL << 31);
 }
 bool use_split_bw(const Shape& sh, const ctm_opts& o) {
     return use_split(sh, o) && edge_split_bw_supported(sh.d, sh.D);

@@ -21,6 +21,23 @@ def test_default_opts():
     o = B.default_opts()
     assert o.precision == B.PREC_FP64 and o.n_warmup == -1 and o.k_tracked == 10
     assert o.qr_sing_tol == 1e-14 and o.mixed_tol == 1e-6
+    assert o.edge_split == 1 and o.grad_mode == B.GRAD_CHECKPOINT
+    assert o.fp_tol == 1e-10 and o.fp_max_iter == 1000
+
+
+def test_split_operand_planned_only_where_the_kernels_apply():
+    L = P.lib()
+    on, off = B.default_opts(edge_split=1), B.default_opts(edge_split=0)
+    ws = lambda d, D, chi, o: L.ctm_workspace_bytes(d, D, chi, ctypes.byref(o))
+    # d = 2, D <= 8: the prepared operand (and, for D <= 6, the reverse pass's
+    # partial sums) are planned
+    assert ws(2, 6, 144, on) > ws(2, 6, 144, off)
+    assert ws(2, 8, 256, on) > ws(2, 8, 256, off)
+    # other d, and chi^2 D^4 beyond 32-bit offsets: the double-layer product
+    assert ws(3, 4, 64, on) == ws(3, 4, 64, off)
+    assert ws(2, 8, 1024, on) == ws(2, 8, 1024, off)
+    bad = B.default_opts(edge_split=2)
+    assert L.ctm_workspace_bytes(2, 4, 64, ctypes.byref(bad)) > 0  # planner only; init rejects
 
 
 def test_workspace_sizes_grow_with_problem():
