@@ -131,6 +131,9 @@ GemmDesc bw_gemm(int id, const BwPtrs& p, int chi, int Dab) {
 struct GradLayout {
     size_t ckC, ckT, Cb, Tb, Cb2, Tb2, Ctmp, Ttmp, Cpb, Tpb, Wb, Rb, Qb, Zg, Mm, Ms, Rinv, ctb, abar,
         Asb, part, ratio, splitk, bwpart;
+    // per reversed step: the forward step's Q, R, T', W and its two norms, kept
+    // so that the reverse sweep recomputes only Y and Z (3a, 3b)
+    size_t sQ, sR, sTp, sW, sN;
     size_t splitk_bytes = 0, bwpart_doubles = 0, total = 0;
 };
 
@@ -165,6 +168,9 @@ GradLayout grad_layout(const Shape& sh, int k, bool split_bw) {
     L.Cpb = take(c2); L.Tpb = take(c2 * Db); L.Wb = take(c2 * Db); L.Rb = take(c2);
     L.Qb = take(c2 * Db); L.Zg = take(c2 * Db * Db);
     L.Mm = take(c2); L.Ms = take(c2); L.Rinv = take(c2); L.ctb = take(c2 * Db);
+    const size_t nslot = (size_t)std::max(k, 2);
+    L.sQ = take(nslot * c2 * Db); L.sR = take(nslot * c2); L.sTp = take(nslot * c2 * Db);
+    L.sW = take(nslot * c2 * Db); L.sN = take(nslot * 8);
     L.abar = take(Db * Db * Db * Db);
     L.Asb = take((size_t)sh.d * sh.D * sh.D * sh.D * sh.D);
     L.part = take(sym_norm_backward_scratch_bytes() / sizeof(double) + 1);
@@ -539,7 +545,7 @@ Status eigh_step_once(ctm_ctx* c) {
 
 struct GradPtrs {
     double *ckC, *ckT, *Cb, *Tb, *Cb2, *Tb2, *Ctmp, *Ttmp, *Cpb, *Tpb, *Wb, *Rb, *Qb, *Zg, *Mm, *Ms,
-        *Rinv, *ctb, *abar, *Asb, *part, *ratio, *bwpart;
+        *Rinv, *ctb, *abar, *Asb, *part, *ratio, *bwpart, *sQ, *sR, *sTp, *sW, *sN;
     void* splitk;
     size_t splitk_bytes, bwpart_doubles;
 };
@@ -558,6 +564,7 @@ GradPtrs grad_ptrs(ctm_ctx* c) {
     g.splitk_bytes = L.splitk_bytes;
     g.bwpart = P(L.bwpart);
     g.bwpart_doubles = L.bwpart_doubles;
+    g.sQ = P(L.sQ); g.sR = P(L.sR); g.sTp = P(L.sTp); g.sW = P(L.sW); g.sN = P(L.sN);
     return g;
 }
 
@@ -565,20 +572,51 @@ GradPtrs grad_ptrs(ctm_ctx* c) {
 // of its normalised outputs; writes the cotangents of (Ci, Ti) into (Cb2, Tb2)
 // and accumulates that of the double layer into abar.  The step's forward
 // intermediates are recomputed first (only (C_i, T_i) are stored).
-Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, const double* Ci, const double* Ti) {
-    const int chi = c->chi_cur, Dab = c->sh.Dab;
-    QRCTM_TRY(qr_step_core(c, Ci, Ti, g.Ctmp, g.Ttmp, false, 0));
+// Keep the forward step's Q, R, T', W and norms (just computed by qr_step_core)
+// in reverse-pass slot i.
+Status save_step(ctm_ctx* c, const GradPtrs& g, int i) {
+    const size_t c2 = (size_t)c->chi_cur * c->chi_cur, nQ = c2 * c->sh.Dab;
     StepPtrs sp = step_ptrs(c);
+    auto cp = [&](double* dst, const double* src, size_t n) {
+        return hip_status(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToDevice, c->st),
+                          "hipMemcpyAsync");
+    };
+    QRCTM_TRY(cp(g.sQ + i * nQ, sp.Q, nQ));
+    QRCTM_TRY(cp(g.sR + i * c2, sp.R, c2));
+    QRCTM_TRY(cp(g.sTp + i * nQ, sp.Tp, nQ));
+    QRCTM_TRY(cp(g.sW + i * nQ, sp.W, nQ));
+    return cp(g.sN + i * 8, c->small() + SL_NORMS, 2);
+}
+
+// Reverse of the QR step kept in slot i, which mapped (Ci, Ti) to (Co, To).
+// Only Y and Z are recomputed (3a from the kept Q, then 3b); the cotangents
+// (g.Cb, g.Tb) of (Co, To) become (g.Cb2, g.Tb2) of (Ci, Ti).
+Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, int i, const double* Ci, const double* Ti,
+                        const double* Co, const double* To) {
+    const int chi = c->chi_cur, Dab = c->sh.Dab;
+    const size_t c2 = (size_t)chi * chi, nQ = c2 * Dab;
+    StepPtrs sp = step_ptrs(c);
+    sp.C = Ci;
+    sp.T = Ti;
+    const double* Qi = g.sQ + i * nQ;
+    QRCTM_TRY(gemm_f64(g_edge_a(sp, Qi, chi, chi, Dab), c->ptr<void>(c->plan.splitk),
+                       c->plan.splitk_bytes, c->st));
+    if (c->plan.Bk.bytes > 0)
+        QRCTM_TRY(edge_split_3b(sp.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi, sp.Z, c->st));
+    else
+        QRCTM_TRY(gemm_f64(g_edge_b(sp, chi, chi, Dab), c->ptr<void>(c->plan.splitk),
+                           c->plan.splitk_bytes, c->st));
     BwPtrs p;
-    p.C = Ci; p.T = Ti; p.a = sp.a; p.Q = sp.Q; p.R = sp.R; p.Y = sp.Y; p.Z = sp.Z; p.Tp = sp.Tp;
-    p.W = sp.W;
+    p.C = Ci; p.T = Ti; p.a = sp.a; p.Q = Qi; p.R = g.sR + i * c2; p.Y = sp.Y; p.Z = sp.Z;
+    p.Tp = g.sTp + i * nQ;
+    p.W = g.sW + i * nQ;
     p.Cpb = g.Cpb; p.Tpb = g.Tpb; p.Wb = g.Wb; p.Rb = g.Rb; p.Qb = g.Qb; p.Zg = g.Zg;
     p.Y2 = sp.Z;  // Z is dead once Zbar and Qbar += Z^T Tpbar are formed
     p.abar = g.abar; p.Mm = g.Mm; p.Ms = g.Ms; p.Rinv = g.Rinv; p.ctb = g.ctb;
     p.Cb2 = g.Cb2; p.Tb2 = g.Tb2;
     auto run = [&](int id) { return gemm_f64(bw_gemm(id, p, chi, Dab), g.splitk, g.splitk_bytes, c->st); };
     // a9: symmetrise / normalise
-    QRCTM_TRY(sym_norm_backward(g.Ctmp, g.Ttmp, g.Cb, g.Tb, c->small() + SL_NORMS, chi, Dab, g.Cpb,
+    QRCTM_TRY(sym_norm_backward(Co, To, g.Cb, g.Tb, g.sN + i * 8, chi, Dab, g.Cpb,
                                 g.Tpb, g.part, c->st));
     if (g.bwpart_doubles > 0) {
         // a8, a7 (3c), the split reverse of 3b (Ybar into Y2, the site tensor's
@@ -594,7 +632,7 @@ Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, const double* Ci, const d
     QRCTM_TRY(run(11));
     QRCTM_TRY(copyltu(g.Mm, chi, g.Ms, c->st));
     QRCTM_TRY(run(12));                                    // Qbar + Q copyltu(M)
-    QRCTM_TRY(tri_inv_upper(sp.R, chi, g.Rinv, c->st));
+    QRCTM_TRY(tri_inv_upper(p.R, chi, g.Rinv, c->st));
     QRCTM_TRY(run(13));                                    // ... R^{-T}
     QRCTM_TRY(run(14));                                    // a5
     QRCTM_TRY(run(15));
@@ -622,6 +660,7 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
         QRCTM_TRY(qr_step_core(c, g.ckC + i * nC, g.ckT + i * nT, g.ckC + (i + 1) * nC,
                                g.ckT + (i + 1) * nT, false, 0));
         QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, i == 0, c->st));
+        QRCTM_TRY(save_step(c, g, i));
     }
     if (fixed_point) {
         // the scheme needs env = G(env) elementwise (C and T each have unit norm)
@@ -657,7 +696,8 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
     auto reverse_step = [&](int i) -> Status {
         GradPtrs gi = g;
         gi.Cb = Cb; gi.Tb = Tb; gi.Cb2 = Cb2; gi.Tb2 = Tb2;
-        QRCTM_TRY(qr_step_backward(c, gi, g.ckC + i * nC, g.ckT + i * nT));
+        QRCTM_TRY(qr_step_backward(c, gi, i, g.ckC + i * nC, g.ckT + i * nT, g.ckC + (i + 1) * nC,
+                                   g.ckT + (i + 1) * nT));
         std::swap(Cb, Cb2);
         std::swap(Tb, Tb2);
         return Status{};
@@ -677,8 +717,6 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
         *series_done = false;
         while (steps < c->opts.fp_max_iter) {
             QRCTM_TRY(reverse_step(1));
-            // the reversed step recomputed the QR at env1: its R enters the check too
-            if (steps == 0) QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, false, c->st));
             QRCTM_TRY(reverse_step(0));
             steps += 2;
             QRCTM_TRY(sq_norm(Cb, Tb, (long long)nC, (long long)nT, g.part, &nn, c->st));
