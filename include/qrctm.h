@@ -176,9 +176,10 @@ int ctm_energy(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
  *   CTM_GRAD_CHECKPOINT: starting from the current environment, held fixed,
  *     run opts.k_tracked QR steps, evaluate E, and reverse the whole
  *     computation by hand-written adjoints (contraction adjoints, the thin-QR
- *     adjoint, the double layer and the C4v average).  Only (C_i, T_i) of
- *     every tracked step are kept; each step's intermediates are recomputed in
- *     the reverse sweep.
+ *     adjoint, the double layer and the C4v average).  (C_i, T_i) and each
+ *     tracked step's Q, R, T', W are kept (k (4 chi^2 D^2 + 2 chi^2) doubles);
+ *     the large intermediates Y and Z (chi^2 D^4 each) are recomputed in the
+ *     reverse sweep.
  *   CTM_GRAD_FIXED_POINT: the fixed-point scheme (Discussion paragraph): the
  *     current environment must be converged.  With F one QR step and G = F o F
  *     (T may alternate between two gauges from step to step; the pair of
