@@ -454,17 +454,28 @@ __attribute__((amdgpu_waves_per_eu(ShapeBw<D>::WPE))) void edge_split_bw_kernel(
         }
 }
 
-// Asb[s][u][l][dd][r] += sum over workgroups and both kinds of part[..][s][u D + l][r D + dd]
-__global__ void edge_split_bw_reduce_kernel(const double* __restrict__ part, int nwg, int d, int D,
-                                            int NP, double* Asb) {
+// Asb[s][u][l][dd][r] += sum over workgroups and both kinds of part[..][s][u D + l][r D + dd]:
+// a block per 32 outputs, its 8 thread rows each summing a share of the partials
+constexpr int kRedOut = 32, kRedRows = 8;
+__global__ __launch_bounds__(kRedOut * kRedRows) void edge_split_bw_reduce_kernel(
+    const double* __restrict__ part, int nwg, int d, int D, int NP, double* Asb) {
+    __shared__ double acc_s[kRedRows][kRedOut];
     const int R = D * D, n = d * R * R;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int lo = threadIdx.x % kRedOut, row = threadIdx.x / kRedOut;
+    const int e = blockIdx.x * kRedOut + lo;
+    double acc = 0.0;
+    if (e < n) {
         const int s = e / (R * R), v = e % (R * R);
         const int k = v / R, r = v % D, dd = (v / D) % D;
-        const int o = k * NP + r * D + dd;
-        double acc = 0.0;
-        for (int g = 0; g < 2 * nwg; ++g) acc += part[((size_t)g * d + s) * NP * NP + o];
-        Asb[e] += acc;
+        const size_t o = (size_t)k * NP + r * D + dd;
+        for (int g = row; g < 2 * nwg; g += kRedRows) acc += part[((size_t)g * d + s) * NP * NP + o];
+    }
+    acc_s[row][lo] = acc;
+    __syncthreads();
+    if (row == 0 && e < n) {
+        double t = 0.0;
+        for (int q = 0; q < kRedRows; ++q) t += acc_s[q][lo];
+        Asb[e] += t;
     }
 }
 
@@ -494,8 +505,9 @@ Status launch_3b_bw(const double* Y, const double* Zb, const double* Bk, const d
     hipLaunchKernelGGL(edge_split_bw_kernel<D>, dim3((int)grid), dim3(S::NT), 0, st, Y, Zb, Bk, BkT,
                        npairs, Yb, part, ticket);
     QRCTM_TRY(launch_check("edge_split_bw_kernel"));
-    hipLaunchKernelGGL(edge_split_bw_reduce_kernel, dim3(16), dim3(256), 0, st, part, (int)grid, 2, D,
-                       S::NP, Asb);
+    const int nout = 2 * S::R * S::R;
+    hipLaunchKernelGGL(edge_split_bw_reduce_kernel, dim3((nout + kRedOut - 1) / kRedOut),
+                       dim3(kRedOut * kRedRows), 0, st, part, (int)grid, 2, D, S::NP, Asb);
     return launch_check("edge_split_bw_reduce_kernel");
 }
 
