@@ -30,7 +30,7 @@ Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_
 // not overlap.
 Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chio, double* Z,
                      hipStream_t st);
-// (d, D) for which the fused reverse is built: d = 2, 1 <= D <= 6.
+// (d, D) for which the fused reverse is built: d = 2, 1 <= D <= 8.
 bool edge_split_bw_supported(int d, int D);
 // Doubles of the partial-sum scratch edge_split_3b_backward needs.
 size_t edge_split_bw_part_size(int d, int D);

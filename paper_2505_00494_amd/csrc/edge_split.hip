@@ -235,7 +235,7 @@ __global__ void edge_split_prepare_kernel(const double* __restrict__ As, int d, 
 // v_mfma_f64_16x16x4f64, the last two with K over the batch's blocks.  The
 // LDS row length is odd so that those two read columns conflict-free.
 // ---------------------------------------------------------------------------
-constexpr int kBwPairs[9] = {0, 80, 20, 8, 5, 3, 2, 1, 1};  // D = 7, 8: not built
+constexpr int kBwPairs[9] = {0, 80, 20, 8, 5, 3, 2, 1, 1};
 
 // x returned through an empty asm statement: index arithmetic on it is redone
 // where it is used instead of being hoisted out of the batch loop into
@@ -244,8 +244,8 @@ __device__ __forceinline__ int opaque(int x) {
     asm volatile("" : "+v"(x));
     return x;
 }
-constexpr int kBwGroups[9] = {0, 5, 5, 5, 5, 5, 5, 2, 2};
-constexpr int kBwWavesPerSimd[9] = {0, 2, 2, 2, 2, 2, 4, 2, 2};
+constexpr int kBwGroups[9] = {0, 5, 5, 5, 5, 5, 5, 4, 4};
+constexpr int kBwWavesPerSimd[9] = {0, 2, 2, 2, 2, 2, 4, 4, 4};
 constexpr int kBwMaxGrid = 512;
 
 template <int D>
@@ -267,6 +267,10 @@ struct ShapeBw {
     static constexpr int TS = 2 * NB * NB;            // Bkb tiles per s (bra, ket)
     static constexpr int TPW = (TS + W - 1) / W;      // ... per wave
     static constexpr int WPE = kBwWavesPerSimd[D];
+    // k steps unrolled per iteration; at D >= 7 none, so that the B fragment
+    // loads are not hoisted into registers the accumulators need
+    static constexpr int KU = D >= 7 ? 1 : 3;
+    static constexpr int KU2 = D >= 7 ? 1 : 2;
     static_assert(MT % G == 0, "row tiles split evenly over the groups");
 };
 
@@ -366,7 +370,7 @@ __attribute__((amdgpu_waves_per_eu(ShapeBw<D>::WPE))) void edge_split_bw_kernel(
                     x[i] = dbl4{0.0, 0.0, 0.0, 0.0};
                     xb[i] = dbl4{0.0, 0.0, 0.0, 0.0};
                 }
-#pragma unroll 3
+#pragma unroll S::KU
                 for (int kk = 0; kk < KS; ++kk) {
                     const int o = (4 * kk + q) * LDM + 16 * mt0 + l16;
                     const double b1 = B1[4 * kk * NP], b2 = B2[4 * kk * NP];
@@ -391,7 +395,7 @@ __attribute__((amdgpu_waves_per_eu(ShapeBw<D>::WPE))) void edge_split_bw_kernel(
                 __syncthreads();  // xs, xbs complete
                 if (s == DP - 1 && bn < nbatch) load(bn);
                 // Yb += Xb_s^T-contract Bk[s] (B fragments of BkT[s], as for Xb_s)
-#pragma unroll 3
+#pragma unroll S::KU
                 for (int kk = 0; kk < KS; ++kk) {
                     const int o = (4 * kk + q) * LDM + 16 * mt0 + l16;
                     const double b2 = B2[4 * kk * NP];
@@ -408,7 +412,7 @@ __attribute__((amdgpu_waves_per_eu(ShapeBw<D>::WPE))) void edge_split_bw_kernel(
                         const double* As_ = kind ? ys : xs;
                         const double* Bs_ = kind ? xbs : zs;
                         const int oa = (16 * it + l16) * LDM + q, ob = (16 * jt + l16) * LDM + q;
-#pragma unroll 2
+#pragma unroll S::KU2
                         for (int kk = 0; kk < MP / 4; ++kk)
                             ab[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(As_[oa + 4 * kk],
                                                                            Bs_[ob + 4 * kk],
@@ -542,7 +546,7 @@ size_t edge_split_operand_size(int d, int D) {
     return edge_split_supported(d, D) ? 2 * (size_t)d * kp_of(D) * np_of(D) + kTickets / 2 : 0;
 }
 
-bool edge_split_bw_supported(int d, int D) { return edge_split_supported(d, D) && D <= 6; }
+bool edge_split_bw_supported(int d, int D) { return edge_split_supported(d, D); }
 
 size_t edge_split_bw_part_size(int d, int D) {
     return edge_split_bw_supported(d, D) ? (size_t)kBwMaxGrid * 2 * d * np_of(D) * np_of(D) : 0;
@@ -606,7 +610,9 @@ Status edge_split_3b_backward(const double* Y, const double* Zb, double* Bk, int
         case 3: return launch_3b_bw<3>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
         case 4: return launch_3b_bw<4>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
         case 5: return launch_3b_bw<5>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
-        default: return launch_3b_bw<6>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        case 6: return launch_3b_bw<6>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        case 7: return launch_3b_bw<7>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
+        default: return launch_3b_bw<8>(Y, Zb, Bk, BkT, tk, npairs, Yb, part, part_doubles, Asb, st);
     }
 }
 

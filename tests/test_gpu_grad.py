@@ -116,7 +116,7 @@ def test_autograd_energy_function():
     ctx2.close()
 
 
-@pytest.mark.parametrize("D,chi", [(4, 64), (6, 144)])
+@pytest.mark.parametrize("D,chi", [(4, 64), (6, 144), (7, 98), (8, 128)])
 def test_split_reverse_matches_double_layer_reverse(D, chi):
     # the fused ket/bra-split reverse of 3b against the double-layer GEMM
     # adjoints, from the same environment (both FP64)
