@@ -179,9 +179,9 @@ def main():
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the path would shard the 3a/3b/3c chain over the new chi index with one "
-              "all-gather of T' per step (see the design notes)", file=sys.stderr)
+              "all-gather of T' per step", file=sys.stderr)
         sys.exit(2)
 
     import torch
