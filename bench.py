@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--converge-tol", type=float, default=0.0,
                     help="time to a converged environment per form (0: skip)")
     ap.add_argument("--converge-max", type=int, default=600)
+    ap.add_argument("--chi-sweep", type=str, default="",
+                    help="comma-separated chi values: also time the default form at each")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -373,6 +375,28 @@ def main():
                        "energy": e, "grad_norm": float(g.norm())}
         gctx.close()
     ctx.close()
+    if args.chi_sweep:
+        # time per step against chi (same tensor, default form), cf. the paper's Fig. 2b
+        sweep = []
+        for c in [int(x) for x in args.chi_sweep.split(",") if x]:
+            print(f"# chi sweep: chi={c}", file=sys.stderr, flush=True)
+            sctx = P.Context(A, c)
+            sctx.step(args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sctx.step(args.steps)
+            torch.cuda.synchronize()
+            el_s = time.perf_counter() - t0
+            sctx.set_timing(True)
+            sctx.step(nt)
+            sst = sctx.stats()
+            sctx.close()
+            sps = args.steps / el_s
+            sweep.append({"chi": c, "steps_per_s": sps, "ms_per_step": 1e3 * el_s / args.steps,
+                          "tflops": sst["flops_per_step"] * sps / 1e12,
+                          "ms_per_phase": {k: v / sst["timed_steps"]
+                                           for k, v in sst["ms_phase"].items()}})
+        out["chi_sweep"] = sweep
     if args.calibrate_copy:
         copy_calibration(args.calibrate_copy)
     if not args.no_cpu_baseline:

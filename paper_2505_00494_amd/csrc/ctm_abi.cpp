@@ -255,6 +255,9 @@ constexpr int kPhases = 8;  // reduced corner, QR, 3a, 3b, 3c, corner, sym/norm,
 // largest relative change of (C, T) under two QR steps that the fixed-point
 // gradient accepts as a fixed point
 constexpr double kFpMaxResidual = 1e-8;
+// largest QR grid (workgroups) that runs beside the corner spectrum without
+// waiting for it (measured: grids of 162 and 225 never did, 240 and 256 did)
+constexpr int kQrGridBeside = 224;
 
 // small-scalar slots (doubles) inside Plan::small
 // SL_DELTA: ring of kDeltaSlots deltas (one per QR step, written on the
@@ -294,8 +297,23 @@ struct ctm_ctx {
     // spectrum that reads environment buffer b; the main stream waits on it
     // before overwriting b two steps later.
     hipStream_t aux = nullptr;
-    hipEvent_t ev_normed = nullptr, ev_join = nullptr, ev_specdone[2] = {};
+    hipEvent_t ev_normed = nullptr, ev_join = nullptr, ev_specdone[2] = {}, ev_qrdone = nullptr;
     bool spec_pending[2] = {false, false};
+    // When the QR's cooperative grid covers nearly every CU, the spectrum of a
+    // step is queued only once the next step's QR is done (or when its result
+    // is needed): a QR workgroup that finds no room beside the running
+    // spectrum would stall the whole QR until the spectrum ends.  Smaller
+    // grids leave room, and the spectrum runs beside the whole next step.
+    struct OwedSpectrum {
+        bool live = false;
+        const double* C = nullptr;
+        int n = 0;
+        const double* s_prev = nullptr;
+        int n_prev = 0;
+        double* s_out = nullptr;
+        double* delta = nullptr;
+        int target = 0;  // environment buffer it reads
+    } owed;
     int last_slot = 0;
     ~ctm_ctx() {
         for (auto& e : ev)
@@ -305,6 +323,7 @@ struct ctm_ctx {
         for (auto& e : ev_specdone)
             if (e) (void)hipEventDestroy(e);
         if (ev_normed) (void)hipEventDestroy(ev_normed);
+        if (ev_qrdone) (void)hipEventDestroy(ev_qrdone);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (aux) {
             (void)hipStreamSynchronize(aux);
@@ -343,8 +362,23 @@ int fail(ctm_ctx* c, int code, const std::string& msg) {
 
 Status sync(hipStream_t st) { return hip_status(hipStreamSynchronize(st), "hipStreamSynchronize"); }
 
-// Make the main stream wait for all work queued on the auxiliary stream.
+// Queue the owed spectrum on the auxiliary stream once `after` has completed.
+Status launch_owed_spectrum(ctm_ctx* c, hipEvent_t after) {
+    if (!c->owed.live) return Status{};
+    const auto o = c->owed;
+    c->owed.live = false;
+    QRCTM_HIP(hipStreamWaitEvent(c->aux, after, 0));
+    QRCTM_TRY(corner_spectrum(o.C, o.n, c->ptr(c->plan.S), o.s_prev, o.n_prev, o.s_out, o.delta,
+                              c->aux));  // a10
+    QRCTM_HIP(hipEventRecord(c->ev_specdone[o.target], c->aux));
+    c->spec_pending[o.target] = true;
+    return Status{};
+}
+
+// Make the main stream wait for all work queued on the auxiliary stream
+// (queueing an owed spectrum first).
 Status join_aux(ctm_ctx* c) {
+    QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
     QRCTM_HIP(hipEventRecord(c->ev_join, c->aux));
     QRCTM_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
     c->spec_pending[0] = c->spec_pending[1] = false;
@@ -412,7 +446,7 @@ Status refresh_planes(ctm_ctx* c) {
 // a5-a9 from (Cin, Tin) into (Cout, Tout); intermediates stay in the step
 // buffers (Q, R, Y, Z, Tp, W, Cp) and the norms in the small-scalar slots.
 Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Cout, double* Tout,
-                    bool timed, int prec) {
+                    bool timed, int prec, hipEvent_t after_qr = nullptr) {
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     StepPtrs p = step_ptrs(c);
     p.C = Cin;
@@ -440,6 +474,7 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     QRCTM_TRY(mark(1));
     QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
                      c->st, c->small() + SL_RATIO, c->bad()));                      // a6
+    if (after_qr) QRCTM_HIP(hipEventRecord(after_qr, c->st));
     QRCTM_TRY(mark(2));
     {
         GemmDesc ga = g_edge_a(p, p.Q, chi, chi, Dab);                                 // a7 3a
@@ -483,16 +518,22 @@ Status qr_step_once(ctm_ctx* c) {
     const int chi = c->chi_cur;
     const int target = c->cur ^ 1;  // environment buffer this step writes
     if (c->spec_pending[target]) QRCTM_HIP(hipStreamWaitEvent(c->st, c->ev_specdone[target], 0));
-    QRCTM_TRY(qr_step_core(c, c->C(), c->T(), c->Cn(), c->Tn(), true, step_prec(c)));
+    const bool owed = c->owed.live;
+    QRCTM_TRY(qr_step_core(c, c->C(), c->T(), c->Cn(), c->Tn(), true, step_prec(c),
+                           owed ? c->ev_qrdone : nullptr));
+    if (owed) QRCTM_TRY(launch_owed_spectrum(c, c->ev_qrdone));  // the previous step's
     QRCTM_HIP(hipEventRecord(c->ev_normed, c->st));
-    QRCTM_HIP(hipStreamWaitEvent(c->aux, c->ev_normed, 0));
     const int slot = (int)(c->steps % kDeltaSlots);
-    if (c->timing) QRCTM_HIP(hipEventRecord(c->ev_sp[0], c->aux));
-    QRCTM_TRY(corner_spectrum(c->Cn(), chi, c->ptr(c->plan.S), c->spec(), c->n_spec,
-                              c->spec_next(), c->small() + SL_DELTA + slot, c->aux));  // a10
-    if (c->timing) QRCTM_HIP(hipEventRecord(c->ev_sp[1], c->aux));
-    QRCTM_HIP(hipEventRecord(c->ev_specdone[target], c->aux));
-    c->spec_pending[target] = true;
+    c->owed = ctm_ctx::OwedSpectrum{true,          c->Cn(),          chi, c->spec(), c->n_spec,
+                                    c->spec_next(), c->small() + SL_DELTA + slot, target};
+    if (c->timing) {  // timed steps run one at a time: the spectrum right after its step
+        QRCTM_HIP(hipStreamWaitEvent(c->aux, c->ev_normed, 0));
+        QRCTM_HIP(hipEventRecord(c->ev_sp[0], c->aux));
+        QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
+        QRCTM_HIP(hipEventRecord(c->ev_sp[1], c->aux));
+    } else if (qr_grid(chi * c->sh.Dab, chi) <= kQrGridBeside) {
+        QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
+    }
     c->last_slot = slot;
     if (c->timing) {
         QRCTM_HIP(hipEventSynchronize(c->ev[kPhases - 1]));
@@ -836,6 +877,7 @@ int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_
     bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_normed, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&c->ev_qrdone, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_specdone[0], hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_specdone[1], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
@@ -993,6 +1035,7 @@ int ctm_step(ctm_ctx* c, int nsteps, double* delta) {
         for (int i = 0; i < nsteps; ++i) QRCTM_TRY(qr_step_once(c));
         double h[2] = {NAN, NAN};
         if (nsteps > 0) {
+            QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
             QRCTM_HIP(hipMemcpyAsync(h, c->small() + SL_DELTA + c->last_slot, sizeof(double),
                                      hipMemcpyDeviceToHost, c->aux));
             QRCTM_HIP(hipStreamSynchronize(c->aux));
@@ -1030,12 +1073,15 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delt
             while (true) {
                 const int slot = c->last_slot;
                 const bool speculate = n < budget;
+                // step i's spectrum is queued by step i+1 (after its QR), or here
                 if (speculate) QRCTM_TRY(qr_step_once(c));
+                else QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
                 QRCTM_HIP(hipMemcpyAsync(&dl, c->small() + SL_DELTA + slot, sizeof(double),
                                          hipMemcpyDeviceToHost, c->aux));
                 QRCTM_TRY(hip_status(hipStreamSynchronize(c->aux), "hipStreamSynchronize"));
                 if (!std::isfinite(dl) || dl < tl) {
                     if (speculate) {
+                        c->owed.live = false;  // step i+1 is discarded with its spectrum
                         QRCTM_TRY(join_aux(c));
                         QRCTM_TRY(sync(c->st));
                         c->cur ^= 1;

@@ -11,6 +11,9 @@ struct QrScratch {
 
 QrScratch qr_scratch_layout(int m, int n);
 bool qr_fits(int m, int n);
+// Workgroups of the cooperative launch for an m x n factorisation (all of them
+// must be resident at once).
+int qr_grid(int m, int n);
 // Q (m x n) and R (n x n) from M (m x n), all device, row-major.  diag_ratio_dev
 // (device, may be null) receives min|R_ii| / max|R_ii|; err_dev (device int, may
 // be null) is or-ed with 2 if a grid barrier timed out.  Q may alias M.  One cooperative

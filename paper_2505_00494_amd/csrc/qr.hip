@@ -591,6 +591,8 @@ QrScratch qr_scratch_layout(int m, int n) {
     return s;
 }
 
+int qr_grid(int m, int n) { return plan_qr(m, n).P; }
+
 bool qr_fits(int m, int n) {
     if (m < n || n < 1 || n > kMaxN) return false;
     const QrPlan L = plan_qr(m, n);

@@ -2,152 +2,381 @@
 // (standard-CTMRG paragraph: iterate "until convergence"; the change in the
 // normalised corner spectrum is the measure used here).
 //
-// One workgroup of 1024 threads: Householder tridiagonalisation of the
-// symmetric chi x chi corner (packed lower triangle in LDS up to chi = 176;
-// beyond that in global scratch, L2 resident, both triangles kept so every
-// access is a coalesced row access), eigenvalues of the
+// One workgroup of 512 threads.  Householder tridiagonalisation of the
+// symmetric chi x chi corner, keeping only its lower triangle (packed in LDS
+// up to chi = 176, beyond that row-major in global scratch, L2 resident).  The
+// rank-2 update of each reflection is applied lazily, in the same sweep of the
+// trailing triangle that forms the next reflection's product A v, so each
+// reflection reads and writes the triangle once.  Eigenvalues of the
 // tridiagonal matrix by Sturm-sequence bisection (one eigenvalue per thread),
 // |lambda| ranked in descending order (ties by index), normalised by their sum,
 // and delta = || s - s_prev ||_2 with the shorter spectrum padded by zeros.
+// Every reduction has a fixed order, so the result does not vary between runs.
 #include "common.h"
 #include "spectrum.h"
 
 namespace qrctm {
 namespace {
 
-constexpr int kSpecThreads = 1024;
+constexpr int kSpecThreads = 512;
+constexpr int kSpecWaves = kSpecThreads / 64;
 constexpr int kMaxN = 1024;
+constexpr int kLdsMaxN = 176;
 
-__device__ double block_sum(double v, double* red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int w = kSpecThreads / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+// lane permutation of a double within rows of 16 lanes (DPP control word CTRL)
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int c = q < 0.0;
-    for (int j = 1; j < n; ++j) {
-        q = d[j] - x - e2[j - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        c += q < 0.0;
-    }
-    return c;
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Symmetric matrix storage: full rows in global scratch (any n), or the packed
-// lower triangle in LDS (n <= kLdsMaxN), index i(i+1)/2 + j for i >= j.
+// Sum over the 64 lanes of a wave (all lanes active); every lane gets the same
+// value.  Butterfly within rows of 16 (xor 1, xor 2, mirror of 8, mirror of
+// 16), then the four row sums.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_perm<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_perm<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_perm<0x141>(v);  // row_half_mirror
+    v += dpp_perm<0x140>(v);  // row_mirror
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// Sums over the 64 lanes of eight values at once.  Each fold adds lanes a
+// distance apart and keeps, per lane, the half belonging to one value, so one
+// register ends up holding all eight: lane l (of any 16) holds the sum of
+// value row8(l & 15).  Folds: distance 8 (row_ror:8), mirror within 8, xor 2,
+// xor 1 (within rows of 16), then across the four rows of 16.
+__device__ __forceinline__ int row8(int p) { return ((p & 2) ? 4 : 0) + ((p & 4) ? 2 : 0) + ((p & 8) ? 1 : 0); }
+__device__ __forceinline__ double sum8(const double* v) {
+    const int p = threadIdx.x & 15;
+    double s4[4], s2[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double a = v[2 * q] + dpp_perm<0x128>(v[2 * q]);
+        const double b = v[2 * q + 1] + dpp_perm<0x128>(v[2 * q + 1]);
+        s4[q] = (p & 8) ? b : a;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double a = s4[2 * q] + dpp_perm<0x141>(s4[2 * q]);
+        const double b = s4[2 * q + 1] + dpp_perm<0x141>(s4[2 * q + 1]);
+        s2[q] = (p & 4) ? b : a;
+    }
+    const double a = s2[0] + dpp_perm<0x4E>(s2[0]);
+    const double b = s2[1] + dpp_perm<0x4E>(s2[1]);
+    double x = (p & 2) ? b : a;
+    x += dpp_perm<0xB1>(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
+// Sum over the workgroup, the same value in every thread.  part holds one
+// slot per wave; two calls in a row must use different part buffers (the
+// barrier of the second call orders the first call's reads before the third
+// call's writes).
+__device__ double block_sum(double v, double* part) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSpecWaves; ++w) s += part[w];
+    return s;
+}
+
+// Sturm counts (eigenvalues below x) of the tridiagonal matrix (d, e^2) at NP
+// points, their recurrences interleaved.  1/q is the hardware reciprocal with
+// two Newton steps; |q| >= pivmin = 1e-300 max(1, max e^2) keeps every value
+// finite.
+template <int NP>
+__device__ void sturm_counts(const double* d, const double* e2, int n, const double* x,
+                             double pivmin, int* cnt) {
+    double q[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        q[p] = d[0] - x[p];
+        if (fabs(q[p]) < pivmin) q[p] = -pivmin;
+        cnt[p] = q[p] < 0.0;
+    }
+    auto step = [&](double dj, double ej) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            double r = __builtin_amdgcn_rcp(q[p]);
+            double h = fma(-q[p], r, 1.0);
+            r = fma(r, h, r);
+            h = fma(-q[p], r, 1.0);
+            r = fma(r, h, r);
+            double qq = fma(-ej, r, dj - x[p]);
+            if (fabs(qq) < pivmin) qq = -pivmin;
+            q[p] = qq;
+            cnt[p] += qq < 0.0;
+        }
+    };
+    // eight entries of (d, e^2) read ahead of their use
+    int j = 1;
+    for (; j + 8 <= n; j += 8) {
+        double dv[8], ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dv[u] = d[j + u];
+            ev[u] = e2[j + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) step(dv[u], ev[u]);
+    }
+    for (; j < n; ++j) step(d[j], e2[j - 1]);
+}
+
+// Eigenvalue e (ascending) of the tridiagonal matrix inside [a, b] by
+// multisection: the g lanes of a group (g = 1, 2, 4 or 8 adjacent lanes) each
+// place NP of the g NP interior points that cut [a, b] into equal parts, and
+// the group keeps the part holding the eigenvalue.  Stops at a width of
+// 2 eps max(|a|, |b|) + atol, or when the interval no longer shrinks.  Every
+// lane of the wave takes part (live = false for lanes without an eigenvalue).
+template <int NP>
+__device__ double multisect(const double* d, const double* e2, int n, int e, int s, int g,
+                            double a, double b, double pivmin, double atol, bool live) {
+    const int M = g * NP;
+    for (int it = 0; it < 256; ++it) {
+        live = live && (b - a > 2.0 * 2.2e-16 * fmax(fabs(a), fabs(b)) + atol);
+        if (!__any(live)) break;
+        const double h = (b - a) / (M + 1);
+        double x[NP];
+        int cnt[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) x[p] = a + (double)(s * NP + p + 1) * h;
+        sturm_counts<NP>(d, e2, n, x, pivmin, cnt);
+        double na = a, nb = b;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (cnt[p] > e) nb = fmin(nb, x[p]);
+            else na = fmax(na, x[p]);
+        }
+        if (g >= 2) {
+            na = fmax(na, dpp_perm<0xB1>(na));
+            nb = fmin(nb, dpp_perm<0xB1>(nb));
+        }
+        if (g >= 4) {
+            na = fmax(na, dpp_perm<0x4E>(na));
+            nb = fmin(nb, dpp_perm<0x4E>(nb));
+        }
+        if (g >= 8) {
+            na = fmax(na, dpp_perm<0x141>(na));
+            nb = fmin(nb, dpp_perm<0x141>(nb));
+        }
+        if (live) {
+            if (na == a && nb == b) live = false;
+            a = na;
+            b = nb;
+        }
+    }
+    return 0.5 * (a + b);
+}
+
+// Lower triangle of the symmetric matrix: rows of a row-major n x n array in
+// global scratch, or the packed triangle in LDS (row i at i(i+1)/2).
 struct GlobalSym {
     double* S;
     int n;
-    __device__ double get(int i, int j) const { return S[(size_t)i * n + j]; }
-    __device__ void sub(int i, int j, double v) { S[(size_t)i * n + j] -= v; }
-    __device__ void set(int i, int j, double v) { S[(size_t)i * n + j] = v; }
-    static constexpr bool kBothTriangles = true;
+    __device__ double* row(int i) const { return S + (size_t)i * n; }
+    static constexpr bool kInLds = false;
 };
 struct LdsSym {
     double* S;
     int n;
-    __device__ static int idx(int i, int j) { return i * (i + 1) / 2 + j; }
-    __device__ double get(int i, int j) const { return i >= j ? S[idx(i, j)] : S[idx(j, i)]; }
-    __device__ void sub(int i, int j, double v) { S[idx(i, j)] -= v; }
-    __device__ void set(int i, int j, double v) { S[idx(i, j)] = v; }
-    static constexpr bool kBothTriangles = false;
+    __device__ double* row(int i) const { return S + i * (i + 1) / 2; }
+    static constexpr bool kInLds = true;
 };
 
-constexpr int kLdsMaxN = 176;
 
 template <class Store, int MAXN>
 __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __restrict__ C, int n,
                                                                 double* Sg, const double* s_prev,
                                                                 int n_prev, double* s_out,
                                                                 double* delta_out) {
-    __shared__ double v[MAXN], p[MAXN], dd[MAXN], ee[MAXN], lam[MAXN], red[kSpecThreads];
+    constexpr int R = (MAXN + kSpecThreads - 1) / kSpecThreads;  // rows / eigenvalues per thread
+    constexpr int NC = (MAXN + 63) / 64;                            // 64-column chunks of a row
+    // vp, wp: the reflection whose rank-2 update is still pending; vk: the
+    // current reflection; prow: row part of A v; dd, ee: the tridiagonal matrix
+    __shared__ double vp[MAXN], wp[MAXN], vk[MAXN], prow[MAXN], dd[MAXN], ee[MAXN];
+    __shared__ double part[2][kSpecWaves];
+    __shared__ double alpha_sh;
     extern __shared__ double dyn[];
+    double* pcol = dyn;  // [kSpecWaves][n]: column part of A v, one row per wave
     Store A;
-    A.S = Store::kBothTriangles ? Sg : dyn;
+    A.S = Store::kInLds ? dyn + (size_t)kSpecWaves * n : Sg;
     A.n = n;
-    const int t = threadIdx.x;
-    for (long long q = t; q < (long long)n * n; q += kSpecThreads) {
-        const int i = (int)(q / n), j = (int)(q % n);
-        if (Store::kBothTriangles || i >= j) A.set(i, j, 0.5 * (C[q] + C[(size_t)j * n + i]));
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int pb = 0;
+
+    for (int i = wv; i < n; i += kSpecWaves) {
+        double* ri = A.row(i);
+        for (int j = lane; j <= i; j += 64) ri[j] = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+    }
+    for (int i = t; i < n; i += kSpecThreads) {
+        vp[i] = 0.0;
+        wp[i] = 0.0;
     }
     __syncthreads();
 
+    // Reflection k zeroes column k below the subdiagonal of the current matrix
+    // A_k = S - vp wp^T - wp vp^T (on rows and columns > k-1); vph, wph are
+    // vp[k], wp[k], held by every thread.
+    double vph = 0.0, wph = 0.0;
     for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;
-        // x = column k below the diagonal (rows k+1 .. n-1)
-        double part = 0.0;
-        for (int i = 1 + t; i < m; i += kSpecThreads) {
-            const double xi = A.get(k + 1 + i, k);
-            part += xi * xi;
+        double x[R];
+        double s2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = t + r * kSpecThreads;
+            x[r] = 0.0;
+            if (i > k && i < n) {
+                const double c = A.row(i)[k] - vp[i] * wph - wp[i] * vph;
+                x[r] = c;
+                if (i > k + 1) s2 += c * c;
+                else alpha_sh = c;
+            }
         }
-        const double sigma2 = block_sum(part, red);
-        const double alpha = A.get(k + 1, k);
-        if (t == 0) dd[k] = A.get(k, k);
-        if (sigma2 == 0.0) {
-            if (t == 0) ee[k] = alpha;
-            __syncthreads();
-            continue;
+        if (t == 0) dd[k] = A.row(k)[k] - 2.0 * vph * wph;
+        const double sigma2 = block_sum(s2, part[pb]);
+        pb ^= 1;
+        const double alpha = alpha_sh;
+        double tau = 0.0, scal = 0.0, beta = alpha;
+        if (sigma2 != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
         }
-        const double beta = -copysign(sqrt(alpha * alpha + sigma2), alpha);
-        const double tau = (beta - alpha) / beta;
-        const double scal = 1.0 / (alpha - beta);
-        for (int i = t; i < m; i += kSpecThreads) v[i] = (i == 0) ? 1.0 : A.get(k + 1 + i, k) * scal;
         if (t == 0) ee[k] = beta;
-        __syncthreads();
-        // p = tau * A22 v (A22 symmetric; the global store reads column i as row i):
-        // row i is split into nc chunks handled by different threads, the
-        // chunk sums are combined through LDS in a fixed order
-        {
-            const int nc = max(1, min(kSpecThreads / m, 32));
-            const int len = (m + nc - 1) / nc;
-            const int i = t % m, c = t / m;
-            if (c < nc) {
-                const int j0 = c * len, j1 = min(m, j0 + len);
-                double acc = 0.0;
-                for (int jx = j0; jx < j1; ++jx) acc += A.get(k + 1 + jx, k + 1 + i) * v[jx];
-                red[c * m + i] = acc;
-            }
-            __syncthreads();
-            for (int ii = t; ii < m; ii += kSpecThreads) {
-                double acc = 0.0;
-                for (int cc = 0; cc < nc; ++cc) acc += red[cc * m + ii];
-                p[ii] = tau * acc;
-            }
-            __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = t + r * kSpecThreads;
+            if (i > k && i < n) vk[i] = (i == k + 1) ? 1.0 : x[r] * scal;
         }
+        __syncthreads();
+
+        // one sweep of the trailing triangle (rows, columns > k): apply the
+        // pending update, store, and accumulate A_{k+1} v by rows (prow) and,
+        // for the strictly lower part, by columns (pc, per lane).  A wave takes
+        // its rows eight at a time, every 64-column chunk of the eight loaded
+        // together, and sums the eight row parts in one reduction.
+        // (for the widest rows the column parts stay in the wave's pcol row:
+        // lane (j - k - 1) % 64 alone touches entry j)
+        constexpr bool kPcInLds = MAXN > 512;
+        double pc[kPcInLds ? 1 : NC];
+        if (kPcInLds) {
+            for (int j = k + 1 + lane; j < n; j += 64) pcol[wv * n + j] = 0.0;
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pc[c] = 0.0;
+        }
+        for (int i0 = k + 1 + wv; i0 < n; i0 += 8 * kSpecWaves) {
+            double acc[8], vi[8], wi[8], vki[8];
+            int nchm = 0;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int i = i0 + b * kSpecWaves;
+                const int ii = i < n ? i : k + 1;
+                vi[b] = vp[ii];
+                wi[b] = wp[ii];
+                vki[b] = vk[ii];
+                acc[b] = 0.0;
+                if (i < n) nchm = (i - k - 1) / 64 + 1;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c < nchm) {
+                    const int j = k + 1 + c * 64 + lane;
+                    const int jj = j < n ? j : n - 1;
+                    const double vpj = vp[jj], wpj = wp[jj], vkj = vk[jj];
+                    double a[8];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) {
+                        const int i = i0 + b * kSpecWaves;
+                        if (i < n && j <= i) a[b] = A.row(i)[j];
+                    }
+                    double col = 0.0;
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) {
+                        const int i = i0 + b * kSpecWaves;
+                        if (i < n && j <= i) {
+                            const double y = a[b] - vi[b] * wpj - wi[b] * vpj;
+                            A.row(i)[j] = y;
+                            acc[b] += y * vkj;
+                            if (j < i) col += y * vki[b];
+                        }
+                    }
+                    if (kPcInLds) {
+                        if (j < n) pcol[wv * n + j] += col;
+                    } else {
+                        pc[c] += col;
+                    }
+                }
+            }
+            const double rs = sum8(acc);
+            const int i = i0 + row8(lane & 15) * kSpecWaves;
+            if (lane < 16 && (lane & 1) == 0 && i < n) prow[i] = rs;
+        }
+        if (!kPcInLds) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int j = k + 1 + c * 64 + lane;
+                if (j < n) pcol[wv * n + j] = pc[kPcInLds ? 0 : c];
+            }
+        }
+        __syncthreads();
+
+        // p = tau A_{k+1} v, K = tau p^T v / 2, w = p - K v becomes the pending update
+        double pr[R];
         double pv = 0.0;
-        for (int i = t; i < m; i += kSpecThreads) pv += p[i] * v[i];
-        const double K = 0.5 * tau * block_sum(pv, red);
-        for (int i = t; i < m; i += kSpecThreads) p[i] -= K * v[i];  // w
-        __syncthreads();
-        {   // rank-2 update, 32 column lanes x 32 row groups
-            const int cl = t % 32, rg = t / 32;
-            for (int i = rg; i < m; i += kSpecThreads / 32) {
-                const int jend = Store::kBothTriangles ? m : i + 1;
-                const double vi = v[i], pi = p[i];
-                for (int jx = cl; jx < jend; jx += 32)
-                    A.sub(k + 1 + i, k + 1 + jx, vi * p[jx] + pi * v[jx]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = t + r * kSpecThreads;
+            pr[r] = 0.0;
+            if (i > k && i < n) {
+                double sum = prow[i];
+#pragma unroll
+                for (int w = 0; w < kSpecWaves; ++w) sum += pcol[w * n + i];
+                pr[r] = tau * sum;
+                pv += pr[r] * vk[i];
             }
         }
-        __syncthreads();
+        double head = prow[k + 1];
+#pragma unroll
+        for (int w = 0; w < kSpecWaves; ++w) head += pcol[w * n + k + 1];
+        const double K = 0.5 * tau * block_sum(pv, part[pb]);
+        pb ^= 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = t + r * kSpecThreads;
+            if (i > k && i < n) {
+                const double v = vk[i];
+                vp[i] = v;
+                wp[i] = pr[r] - K * v;
+            }
+        }
+        vph = 1.0;  // vk[k+1]
+        wph = tau * head - K;
     }
+    __syncthreads();
     if (t == 0) {
         if (n >= 2) {
-            dd[n - 2] = A.get(n - 2, n - 2);
-            dd[n - 1] = A.get(n - 1, n - 1);
-            ee[n - 2] = A.get(n - 1, n - 2);
+            const double va = vp[n - 2], vb = vp[n - 1], wa = wp[n - 2], wb = wp[n - 1];
+            dd[n - 2] = A.row(n - 2)[n - 2] - 2.0 * va * wa;
+            dd[n - 1] = A.row(n - 1)[n - 1] - 2.0 * vb * wb;
+            ee[n - 2] = A.row(n - 1)[n - 2] - vb * wa - wb * va;
         } else {
-            dd[0] = A.get(0, 0);
+            dd[0] = A.row(0)[0];
         }
     }
     __syncthreads();
@@ -167,44 +396,54 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
     const double span = fmax(fabs(lo), fabs(hi));
     lo -= 2.2e-16 * span * n + pivmin;
     hi += 2.2e-16 * span * n + pivmin;
-    if (t < n) {
-        double a = lo, b = hi;
-        for (int it = 0; it < 256; ++it) {
-            const double mid = 0.5 * (a + b);
-            if (mid == a || mid == b) break;
-            if (sturm_count(dd, ee, n, mid, pivmin) > t) b = mid;
-            else a = mid;
-            if (b - a <= 2.0 * 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+    // each eigenvalue to a relative 2 eps or an absolute 4 eps |T|, whichever is larger
+    const double atol = 4.0 * 2.2e-16 * span + pivmin;
+    double* lam = prow;
+    {
+        // lanes per eigenvalue and points per lane: fill the workgroup, two
+        // interleaved recurrences per lane while a wave per SIMD suffices
+        const int g = n <= 64 ? 8 : n <= 128 ? 4 : n <= 256 ? 2 : 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int slot = t + r * kSpecThreads;
+            const int e = slot / g, sl = slot % g;
+            const bool live = e < n;
+            const double ev = n <= 256 ? multisect<2>(dd, ee, n, e, sl, g, lo, hi, pivmin, atol, live)
+                                       : multisect<1>(dd, ee, n, e, sl, g, lo, hi, pivmin, atol, live);
+            if (live && sl == 0) lam[e] = fabs(ev);
         }
-        lam[t] = fabs(0.5 * (a + b));
     }
     __syncthreads();
     // rank by |lambda| descending, ties by index
-    double mine = 0.0;
-    int rank = 0;
-    if (t < n) {
-        mine = lam[t];
-        for (int jx = 0; jx < n; ++jx) {
-            const double o = lam[jx];
-            rank += (o > mine) || (o == mine && jx < t);
+    double* sorted = vk;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = t + r * kSpecThreads;
+        if (e < n) {
+            const double mine = lam[e];
+            int rank = 0;
+            for (int jx = 0; jx < n; ++jx) {
+                const double o = lam[jx];
+                rank += (o > mine) || (o == mine && jx < e);
+            }
+            sorted[rank] = mine;
         }
     }
     __syncthreads();
-    if (t < n) v[rank] = mine;
-    __syncthreads();
     double ps = 0.0;
-    for (int i = t; i < n; i += kSpecThreads) ps += v[i];
-    const double total = block_sum(ps, red);
+    for (int i = t; i < n; i += kSpecThreads) ps += sorted[i];
+    const double total = block_sum(ps, part[pb]);
+    pb ^= 1;
     const double inv = 1.0 / total;
     double dl = 0.0;
     const int nmax = n > n_prev ? n : n_prev;
     for (int i = t; i < nmax; i += kSpecThreads) {
-        const double si = i < n ? v[i] * inv : 0.0;
+        const double si = i < n ? sorted[i] * inv : 0.0;
         const double sp = (s_prev != nullptr && i < n_prev) ? s_prev[i] : 0.0;
         if (i < n) s_out[i] = si;
         dl += (si - sp) * (si - sp);
     }
-    const double dsum = block_sum(dl, red);
+    const double dsum = block_sum(dl, part[pb]);
     if (t == 0) *delta_out = sqrt(dsum);
 }
 
@@ -220,18 +459,17 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
         s.msg = "spectrum: chi must be in [1, 1024]";
         return s;
     }
-    if (n <= kLdsMaxN) {
-        const size_t lds = sizeof(double) * (size_t)n * (n + 1) / 2;
-        auto kern = spectrum_kernel<LdsSym, kLdsMaxN>;
+    auto launch = [&](auto kern, size_t tri_doubles) -> Status {
+        const size_t dyn = sizeof(double) * ((size_t)kSpecWaves * n + tri_doubles);
         QRCTM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds));
-        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), lds, st, C, n, S, s_prev, n_prev, s_out,
+                                      (int)dyn));
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), dyn, st, C, n, S, s_prev, n_prev, s_out,
                            delta_out);
-    } else {
-        hipLaunchKernelGGL((spectrum_kernel<GlobalSym, kMaxN>), dim3(1), dim3(kSpecThreads), 0, st, C, n,
-                           S, s_prev, n_prev, s_out, delta_out);
-    }
-    return launch_check("spectrum_kernel");
+        return launch_check("spectrum_kernel");
+    };
+    if (n <= kLdsMaxN) return launch(spectrum_kernel<LdsSym, kLdsMaxN>, (size_t)n * (n + 1) / 2);
+    if (n <= 512) return launch(spectrum_kernel<GlobalSym, 512>, 0);
+    return launch(spectrum_kernel<GlobalSym, kMaxN>, 0);
 }
 
 }  // namespace qrctm
