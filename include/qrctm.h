@@ -109,6 +109,8 @@ size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts);
  *          contracting ket with bra on the open legs (footnote on the initial
  *          boundary), and runs the standard-CTMRG warm-up steps (eigh of the
  *          enlarged corner, Fig. 1d) that grow chi to its target.
+ *   chi    target boundary dimension, Dab <= chi <= 512 (the QR kernel's
+ *          column limit; CTM_EINVAL beyond).
  *   ws     device workspace of at least ctm_workspace_bytes(d, D, chi, opts).
  *   stream hipStream_t as void*.
  * Returns CTM_OK, CTM_EINVAL, CTM_EWORKSPACE, CTM_ENONFINITE or CTM_EHIP.

@@ -132,13 +132,25 @@ __device__ __forceinline__ void ll_get(const Addr& addr, int n, unsigned tag, do
     }
 }
 
-// Sum of v over the four lanes of a wave that share lane % 16 (the four row
-// groups of a wave), in a fixed order; every lane gets the sum.
-__device__ __forceinline__ double quarter_sum(double v) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+// v + (v of the lane 16 or 32 apart): the row swap of gfx950 applied to v and
+// itself leaves lane l's value and its partner's in the two results.
+template <bool BY32>
+__device__ __forceinline__ double fold_rows(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned l = (unsigned)b, h = (unsigned)(b >> 32);
+    const auto lo = BY32 ? __builtin_amdgcn_permlane32_swap(l, l, false, false)
+                         : __builtin_amdgcn_permlane16_swap(l, l, false, false);
+    const auto hi = BY32 ? __builtin_amdgcn_permlane32_swap(h, h, false, false)
+                         : __builtin_amdgcn_permlane16_swap(h, h, false, false);
+    const double a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    const double c = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+    return a + c;
 }
+
+// Sum of v over the four lanes of a wave that share lane % 16 (the four row
+// groups of a wave), in a fixed order; every lane gets the sum.  All lanes of
+// the wave must be active.
+__device__ __forceinline__ double quarter_sum(double v) { return fold_rows<true>(fold_rows<false>(v)); }
 
 // Everything a workgroup needs to address its rows.
 struct Rows {
@@ -362,6 +374,10 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(
     double* Ys = Pn + (size_t)rbmax * kPb;     // 16 x n
     double* Gs = Ys + (size_t)kPb * n;         // 16 x 16
     double* red = Gs + kPb * kPb;              // 32 x 16
+    // within the column loop: red (first 8 x 16) for the combine, reda (next
+    // 8 x 16) for the partial sums of the next column, so that no barrier is
+    // needed between one column's last reads and the next column's writes
+    double* reda = red + kWaves * kPb;
     double* wv = red + kRowGroups * kPb;       // 16
     double* rowj = wv + kPb;                   // 16
     double* tau = rowj + kPb;                  // n
@@ -400,18 +416,17 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(
                 if (gi == c0) ll_put(a.rowbuf + 2 * ((size_t)(c0 & 1) * kPb + cl), v, tag_round(c0));
             }
             acc = quarter_sum(acc);
-            if (lane < kPb) red[wave * kPb + lane] = acc;
+            if (lane < kPb) reda[wave * kPb + lane] = acc;
             __syncthreads();
             if (tid < kPb) {
                 double s = 0.0;
-                for (int w = 0; w < kWaves; ++w) s += red[w * kPb + tid];
+                for (int w = 0; w < kWaves; ++w) s += reda[w * kPb + tid];
                 ll_put(a.part + 2 * (((size_t)(c0 & 1) * P + p) * kPb + tid), s, tag_round(c0));
             }
         }
         for (int q = 0; q < nb; ++q) {
             const int j = c0 + q;
             const int buf = j & 1;
-            __syncthreads();  // the previous reduction's reads of red are done
             // combine: slot s = column j + s (slot 0: squared norm below j)
             {
                 // row group rg sums workgroups rg, rg + 32, ... (all loads
@@ -502,11 +517,11 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(
             }
             if (next) {
                 acc = quarter_sum(acc);
-                if (lane < kPb) red[wave * kPb + lane] = acc;
+                if (lane < kPb) reda[wave * kPb + lane] = acc;
                 __syncthreads();
                 if (tid < kPb && tid > q) {
                     double s = 0.0;
-                    for (int w = 0; w < kWaves; ++w) s += red[w * kPb + tid];
+                    for (int w = 0; w < kWaves; ++w) s += reda[w * kPb + tid];
                     // slot tid - (q + 1) for column j + 1 + (tid - q - 1)
                     ll_put(a.part + 2 * (((size_t)((j + 1) & 1) * P + p) * kPb + (tid - q - 1)), s,
                            tag_round(j + 1));
