@@ -109,8 +109,9 @@ size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts);
  *          contracting ket with bra on the open legs (footnote on the initial
  *          boundary), and runs the standard-CTMRG warm-up steps (eigh of the
  *          enlarged corner, Fig. 1d) that grow chi to its target.
- *   chi    target boundary dimension, Dab <= chi <= 512 (the QR kernel's
- *          column limit; CTM_EINVAL beyond).
+ *   chi    target boundary dimension, Dab <= chi <= 1024, as far as the QR's
+ *          workgroups hold their rows and the panel state in LDS (e.g. chi up to
+ *          1024 at Dab = 4, 600 at Dab = 36, 512 at Dab = 64); CTM_EINVAL beyond.
  *   ws     device workspace of at least ctm_workspace_bytes(d, D, chi, opts).
  *   stream hipStream_t as void*.
  * Returns CTM_OK, CTM_EINVAL, CTM_EWORKSPACE, CTM_ENONFINITE or CTM_EHIP.

@@ -56,11 +56,10 @@ constexpr int kPb = 16;                        // panel width (one MFMA tile)
 constexpr int kRowGroups = kQrThreads / kPb;   // 32 row groups x 16 column lanes
 constexpr int kRowsPerWg = 32;                 // target rows per workgroup (measured best)
 constexpr int kMaxWg = 256;
-constexpr int kMaxN = 512;
+constexpr int kMaxN = 1024;                    // columns (the LDS budget may allow fewer)
 constexpr unsigned kSpinLimit = 1u << 17;      // polls of about a microsecond: ~0.1 s
 constexpr size_t kQrLdsBudget = 150 * 1024;
 static_assert(kMaxWg == 8 * kRowGroups, "the combine sums eight workgroups per row group");
-static_assert(kMaxN <= kQrThreads, "form_y gives one column of W to each thread");
 
 struct QrPlan {
     int P;   // workgroups
@@ -305,8 +304,9 @@ __device__ __forceinline__ void reduce_chunk(const u64* part, u64* sum, int P, i
 //   (T W)[q]   = tau_q (W[q] - sum_{l>q} G[q][l] (T W)[l])     (backward).
 // The reduced products redsum (16 x L, L = 16 + nx, sent with tag) hold G in
 // their first 16 columns and W after them: G goes to LDS and column tid of W to
-// registers in one round of loads; thread tid < nx then writes column tid of Y
-// into Ys (16 x nx, row stride nx).  nx <= the thread count.
+// registers in one round of loads; thread tid then writes columns tid, tid +
+// 512, ... of Y into Ys (16 x nx, row stride nx), receiving the later columns
+// of W as it goes.
 __device__ __forceinline__ void form_y(const u64* redsum, int L, int nx, unsigned tag,
                                        const double* tau, int nb, bool trans, double* Gs,
                                        double* Ys, int* err) {
@@ -317,10 +317,13 @@ __device__ __forceinline__ void form_y(const u64* redsum, int L, int nx, unsigne
                   w, err);
         Gs[tid] = w[0];
     }
-    if (tid < nx)
-        ll_get<kPb>([&](int r) { return redsum + 2 * ((size_t)r * L + kPb + tid); }, kPb, tag, w, err);
+    auto get_w = [&](int c) {
+        ll_get<kPb>([&](int r) { return redsum + 2 * ((size_t)r * L + kPb + c); }, kPb, tag, w, err);
+    };
+    if (tid < nx) get_w(tid);
     __syncthreads();
-    if (tid < nx) {
+    for (int c = tid; c < nx; c += kQrThreads) {
+        if (c != tid) get_w(c);
         double y[kPb];
         if (trans) {
 #pragma unroll
@@ -340,7 +343,7 @@ __device__ __forceinline__ void form_y(const u64* redsum, int L, int nx, unsigne
             }
         }
 #pragma unroll
-        for (int q = 0; q < kPb; ++q) Ys[(size_t)q * nx + tid] = y[q];
+        for (int q = 0; q < kPb; ++q) Ys[(size_t)q * nx + c] = y[q];
     }
     __syncthreads();
 }
@@ -619,7 +622,7 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     Status s;
     if (!qr_fits(m, n)) {
         s.code = -1;
-        s.msg = "qr: shape not supported (need m >= n >= 1, n <= 512)";
+        s.msg = "qr: shape not supported (need m >= n >= 1, n <= 1024, rows and panel state within LDS)";
         return s;
     }
     const QrScratch S = qr_scratch_layout(m, n);

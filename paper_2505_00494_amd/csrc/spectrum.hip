@@ -20,7 +20,7 @@ namespace {
 
 constexpr int kSpecThreads = 512;
 constexpr int kSpecWaves = kSpecThreads / 64;
-constexpr int kMaxN = 512;  // the corner never exceeds the QR's 512 columns
+constexpr int kMaxN = 1024;
 constexpr int kLdsMaxN = 176;
 
 // lane permutation of a double within rows of 16 lanes (DPP control word CTRL)
@@ -270,9 +270,16 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
         // for the strictly lower part, by columns (pc, per lane).  A wave takes
         // its rows eight at a time, every 64-column chunk of the eight loaded
         // together, and sums the eight row parts in one reduction.
-        double pc[NC];
+        // (for the widest rows the column parts stay in the wave's pcol row:
+        // lane (j - k - 1) % 64 alone touches entry j)
+        constexpr bool kPcInLds = MAXN > 512;
+        double pc[kPcInLds ? 1 : NC];
+        if (kPcInLds) {
+            for (int j = k + 1 + lane; j < n; j += 64) pcol[wv * n + j] = 0.0;
+        } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) pc[c] = 0.0;
+            for (int c = 0; c < NC; ++c) pc[c] = 0.0;
+        }
         for (int i0 = k + 1 + wv; i0 < n; i0 += 8 * kSpecWaves) {
             double acc[8], vi[8], wi[8], vki[8];
             int nchm = 0;
@@ -309,17 +316,23 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
                             if (j < i) col += y * vki[b];
                         }
                     }
-                    pc[c] += col;
+                    if (kPcInLds) {
+                        if (j < n) pcol[wv * n + j] += col;
+                    } else {
+                        pc[c] += col;
+                    }
                 }
             }
             const double rs = sum8(acc);
             const int i = i0 + row8(lane & 15) * kSpecWaves;
             if (lane < 16 && (lane & 1) == 0 && i < n) prow[i] = rs;
         }
+        if (!kPcInLds) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int j = k + 1 + c * 64 + lane;
-            if (j < n) pcol[wv * n + j] = pc[c];
+            for (int c = 0; c < NC; ++c) {
+                const int j = k + 1 + c * 64 + lane;
+                if (j < n) pcol[wv * n + j] = pc[kPcInLds ? 0 : c];
+            }
         }
         __syncthreads();
 
@@ -443,7 +456,7 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
     Status s;
     if (n < 1 || n > kMaxN) {
         s.code = -1;
-        s.msg = "spectrum: chi must be in [1, 512]";
+        s.msg = "spectrum: chi must be in [1, 1024]";
         return s;
     }
     auto launch = [&](auto kern, size_t tri_doubles) -> Status {
@@ -455,6 +468,7 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
         return launch_check("spectrum_kernel");
     };
     if (n <= kLdsMaxN) return launch(spectrum_kernel<LdsSym, kLdsMaxN>, (size_t)n * (n + 1) / 2);
+    if (n <= 512) return launch(spectrum_kernel<GlobalSym, 512>, 0);
     return launch(spectrum_kernel<GlobalSym, kMaxN>, 0);
 }
 

@@ -3,7 +3,8 @@
 * The spectrum of a corner set with ctm_set_env against the oracle's sorted,
   normalised |eigvalsh|, at sizes on both sides of every storage and work-split
   boundary of the kernel (packed triangle in LDS up to 176, global rows beyond;
-  eigenvalues shared by 8, 4, 2 or 1 lanes up to 64, 128, 256, 512), and for
+  eigenvalues shared by 8, 4, 2 or 1 lanes up to 64, 128, 256, 1024; column
+  parts in registers up to 512, in LDS beyond), and for
   matrices with repeated eigenvalues, zero columns (a reflection that is the
   identity), a zero block and negative eigenvalues.
 * QR steps where the QR's cooperative grid covers nearly every CU (d=2, D=4,
@@ -37,7 +38,8 @@ def _sym_edge(rng, chi, Dab):
 
 def _corners(rng):
     out = []
-    for n in [1, 2, 3, 17, 63, 64, 65, 128, 129, 176, 177, 255, 256, 257, 400, 512]:
+    for n in [1, 2, 3, 17, 63, 64, 65, 128, 129, 176, 177, 255, 256, 257, 400, 512, 513, 600,
+              1024]:
         out.append((f"random{n}", rng.standard_normal((n, n))))
     out.append(("identity9", np.eye(9)))
     z = rng.standard_normal((40, 40))
@@ -56,8 +58,8 @@ def _corners(rng):
 
 def test_spectrum_matches_eigvalsh_at_every_size():
     rng = np.random.default_rng(11)
-    A = inp.random_site_tensor(2, 1, 3)  # D = 1: Dab = 1, so any chi <= 512 is allowed
-    ctx = P.Context(_dev(A), 512, n_warmup=0)
+    A = inp.random_site_tensor(2, 1, 3)  # D = 1: Dab = 1, so any chi <= 1024 is allowed
+    ctx = P.Context(_dev(A), 1024, n_warmup=0)
     for name, C in _corners(rng):
         n = C.shape[0]
         print(f"spectrum {name} n={n}", flush=True)
