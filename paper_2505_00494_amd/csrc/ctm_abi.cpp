@@ -315,6 +315,8 @@ struct ctm_ctx {
         int target = 0;  // environment buffer it reads
     } owed;
     int last_slot = 0;
+    // QR launches on the context's QR workspace (numbers their exchange tags)
+    unsigned long long qr_launches = 0;
     ~ctm_ctx() {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -473,7 +475,7 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     QRCTM_TRY(G(g_reduced_corner(p, chi, Dab)));                                       // a5
     QRCTM_TRY(mark(1));
     QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
-                     c->st, c->small() + SL_RATIO, c->bad()));                      // a6
+                     c->st, c->small() + SL_RATIO, c->bad(), c->qr_launches++));    // a6
     if (after_qr) QRCTM_HIP(hipEventRecord(after_qr, c->st));
     QRCTM_TRY(mark(2));
     {
@@ -903,10 +905,8 @@ int guarded(ctm_ctx* c, F&& f) {
 
 // Algorithmic flops of one QR step (Dab = D^2): reduced corner 2 chi^3 Dab,
 // Householder QR 4 m n^2 - 4 n^3 / 3 with m = chi Dab, n = chi, edge
-// renormalisation 2 chi^3 Dab^2 + 2 chi^2 Dab^4 + 2 chi^3 Dab^2, accelerated
-// corner 4 chi^3 Dab.
-// Algorithmic flops of one QR step; 3b is 2 chi^2 Dab^4 with the double layer,
-// 4 d chi^2 Dab^3 with the ket/bra split (d > 0).
+// renormalisation 2 chi^3 Dab^2 + 3b + 2 chi^3 Dab^2 with 3b 2 chi^2 Dab^4 (double
+// layer) or 4 d chi^2 Dab^3 (ket/bra split, d > 0), accelerated corner 4 chi^3 Dab.
 double step_flops(int chi, int Dab, int d_split) {
     const double c = chi, Db = Dab, Db2 = Db * Db;
     const double f3b = d_split > 0 ? 4.0 * d_split * c * c * Db2 * Db : 2 * c * c * Db2 * Db2;

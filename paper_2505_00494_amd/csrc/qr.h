@@ -17,8 +17,11 @@ int qr_grid(int m, int n);
 // Q (m x n) and R (n x n) from M (m x n), all device, row-major.  diag_ratio_dev
 // (device, may be null) receives min|R_ii| / max|R_ii|; err_dev (device int, may
 // be null) is or-ed with 2 if a grid barrier timed out.  Q may alias M.  One cooperative
-// kernel (after a kernel that clears its exchange buffers); no scratch but ws.
+// kernel; no scratch but ws.  epoch numbers the launches on one ws: 0 (always
+// allowed) clears the exchange buffers first; a caller that passes 0, 1, 2, ...
+// to consecutive launches on the same ws (in stream order) has them cleared
+// only when the count passes a multiple of 2^21.
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
-              hipStream_t st, double* diag_ratio_dev, int* err_dev);
+              hipStream_t st, double* diag_ratio_dev, int* err_dev, unsigned long long epoch = 0);
 
 }  // namespace qrctm

@@ -31,8 +31,9 @@
 // Workgroups exchange data without grid barriers or cache flushes: every
 // double sent to another workgroup travels as two 64-bit words, each holding
 // 32 bits of the value and a 32-bit tag naming the exchange it belongs to
-// (tags grow through the kernel; the buffers are cleared to tag 0 before the
-// launch).  Writers and readers use relaxed agent-scope atomics, so each word
+// (tags grow through the kernel from a base that differs between launches on
+// the same buffers; the buffers are cleared to tag 0 when the caller asks,
+// which it must on their first use and whenever the base starts over).  Writers and readers use relaxed agent-scope atomics, so each word
 // is read whole; a reader polls its words until both carry the expected tag.
 // Every exchange only waits for data of the previous one, all workgroups are
 // co-resident (cooperative launch), and every wait is bounded (on timeout an
@@ -59,6 +60,10 @@ constexpr int kMaxWg = 256;
 constexpr int kMaxN = 1024;                    // columns (the LDS budget may allow fewer)
 constexpr unsigned kSpinLimit = 1u << 17;      // polls of about a microsecond: ~0.1 s
 constexpr size_t kQrLdsBudget = 150 * 1024;
+// tags per launch (more than the n + 4 n / 16 + 3 one launch uses for n <=
+// 1024) and launches before the tag bases start over
+constexpr unsigned kQrTagSpan = 2048;
+constexpr unsigned long long kQrEpochs = (1ull << 32) / kQrTagSpan;
 static_assert(kMaxWg == 8 * kRowGroups, "the combine sums eight workgroups per row group");
 
 struct QrPlan {
@@ -307,6 +312,29 @@ __device__ __forceinline__ void reduce_chunk(const u64* part, u64* sum, int P, i
 // registers in one round of loads; thread tid then writes columns tid, tid +
 // 512, ... of Y into Ys (16 x nx, row stride nx), receiving the later columns
 // of W as it goes.
+// Column c of Y from column c of W (in w) and G (in Gs).
+__device__ __forceinline__ void y_column(const double* w, const double* tau, int nb, bool trans,
+                                         const double* Gs, double* y) {
+    if (trans) {
+#pragma unroll
+        for (int q = 0; q < kPb; ++q) {
+            double s = w[q];
+#pragma unroll
+            for (int l = 0; l < q; ++l) s -= Gs[l * kPb + q] * y[l];
+            y[q] = q < nb ? tau[q] * s : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int q = kPb - 1; q >= 0; --q) {
+            double s = w[q];
+#pragma unroll
+            for (int l = q + 1; l < kPb; ++l) s -= Gs[q * kPb + l] * y[l];
+            y[q] = q < nb ? tau[q] * s : 0.0;
+        }
+    }
+}
+
+template <bool kWide>
 __device__ __forceinline__ void form_y(const u64* redsum, int L, int nx, unsigned tag,
                                        const double* tau, int nb, bool trans, double* Gs,
                                        double* Ys, int* err) {
@@ -322,26 +350,17 @@ __device__ __forceinline__ void form_y(const u64* redsum, int L, int nx, unsigne
     };
     if (tid < nx) get_w(tid);
     __syncthreads();
-    for (int c = tid; c < nx; c += kQrThreads) {
-        if (c != tid) get_w(c);
-        double y[kPb];
-        if (trans) {
+    double y[kPb];
+    if (tid < nx) {
+        y_column(w, tau, nb, trans, Gs, y);
 #pragma unroll
-            for (int q = 0; q < kPb; ++q) {
-                double s = w[q];
-#pragma unroll
-                for (int l = 0; l < q; ++l) s -= Gs[l * kPb + q] * y[l];
-                y[q] = q < nb ? tau[q] * s : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int q = kPb - 1; q >= 0; --q) {
-                double s = w[q];
-#pragma unroll
-                for (int l = q + 1; l < kPb; ++l) s -= Gs[q * kPb + l] * y[l];
-                y[q] = q < nb ? tau[q] * s : 0.0;
-            }
-        }
+        for (int q = 0; q < kPb; ++q) Ys[(size_t)q * nx + tid] = y[q];
+    }
+    // columns beyond the thread count (nx > 512: the kernel built for n > 512)
+    if (kWide)
+    for (int c = tid + kQrThreads; c < nx; c += kQrThreads) {
+        get_w(c);
+        y_column(w, tau, nb, trans, Gs, y);
 #pragma unroll
         for (int q = 0; q < kPb; ++q) Ys[(size_t)q * nx + c] = y[q];
     }
@@ -363,10 +382,12 @@ struct QrArgs {
     int* err;
 };
 
+// kWide: built for n > 512 (more columns of Y than threads)
+template <bool kWide>
 __global__ __launch_bounds__(kQrThreads) void qr_kernel(
     const double* M, int m_, int n_, double* __restrict__ Aw, double* Qo, double* __restrict__ Ro,
     u64* __restrict__ part, u64* __restrict__ rowbuf, u64* __restrict__ redp,
-    u64* __restrict__ redsum, double* __restrict__ ratio, int* __restrict__ err) {
+    u64* __restrict__ redsum, double* __restrict__ ratio, int* __restrict__ err, unsigned tag_base) {
     QrArgs a{M, m_, n_, Aw, Qo, Ro, part, rowbuf, redp, redsum, ratio, err};
     extern __shared__ double lds[];
     const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
@@ -388,9 +409,11 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(
     const int npanel = (n + kPb - 1) / kPb;
     // exchange tags: column round j, then two per panel for the trailing
     // updates and two per panel for the formation of Q
-    auto tag_round = [&](int j) { return (unsigned)(1 + j); };
-    auto tag_trail = [&](int pk) { return (unsigned)(n + 1 + 2 * pk); };
-    auto tag_q = [&](int pk) { return (unsigned)(n + 1 + 2 * npanel + 2 * pk); };
+    // (offset by the launch's tag base, so words left by earlier launches on
+    // the same buffers never carry a tag this launch waits for)
+    auto tag_round = [&](int j) { return tag_base + (unsigned)(1 + j); };
+    auto tag_trail = [&](int pk) { return tag_base + (unsigned)(n + 1 + 2 * pk); };
+    auto tag_q = [&](int pk) { return tag_base + (unsigned)(n + 1 + 2 * npanel + 2 * pk); };
 
     // working copy of this workgroup's rows
     for (int e = tid; e < rows.nr * n; e += kQrThreads) {
@@ -543,7 +566,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(
             panel_vt_x(V, rows, ilo, a.A, n, c1, nt, a.red + 2 * (size_t)p * kPb * L, tag_trail(pk));
             reduce_chunk(a.red, a.redsum, P, p, kPb * L, tag_trail(pk), tag_trail(pk) + 1, red, a.err);
             // Y = T^T W, W = V^T A_trail
-            form_y(a.redsum, L, nt, tag_trail(pk) + 1, tau + c0, nb, true, Gs, Ys, a.err);
+            form_y<kWide>(a.redsum, L, nt, tag_trail(pk) + 1, tau + c0, nb, true, Gs, Ys, a.err);
             panel_update(V, rows, ilo, a.A, n, c1, nt, Ys);
             __syncthreads();
             // rows c0..c1-1 are final beyond the panel: they are R's rows there
@@ -571,7 +594,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_kernel(
         panel_vt_x(VG, rows, ilo, a.Q, n, c0, nq, a.red + 2 * (size_t)p * kPb * L, tag_q(pk));
         reduce_chunk(a.red, a.redsum, P, p, kPb * L, tag_q(pk), tag_q(pk) + 1, red, a.err);
         // Y = T W, W = V^T Q
-        form_y(a.redsum, L, nq, tag_q(pk) + 1, tau + c0, nb, false, Gs, Ys, a.err);
+        form_y<kWide>(a.redsum, L, nq, tag_q(pk) + 1, tau + c0, nb, false, Gs, Ys, a.err);
         panel_update(VG, rows, ilo, a.Q, n, c0, nq, Ys);
         __syncthreads();
     }
@@ -618,7 +641,7 @@ bool qr_fits(int m, int n) {
 }
 
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
-              hipStream_t st, double* diag_ratio_dev, int* err_dev) {
+              hipStream_t st, double* diag_ratio_dev, int* err_dev, unsigned long long epoch) {
     Status s;
     if (!qr_fits(m, n)) {
         s.code = -1;
@@ -647,13 +670,12 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     a.ratio = diag_ratio_dev ? diag_ratio_dev : reinterpret_cast<double*>(base + S.off_ratio);
     a.err = err_dev ? err_dev : reinterpret_cast<int*>(base + S.off_err);
 
+    const void* kern = n > kQrThreads ? (const void*)qr_kernel<true> : (const void*)qr_kernel<false>;
     int dev = 0;
     QRCTM_HIP(hipGetDevice(&dev));
-    QRCTM_HIP(hipFuncSetAttribute((const void*)qr_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes));
+    QRCTM_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes));
     int nblk = 0;
-    QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, qr_kernel, kQrThreads,
-                                                           L.lds_bytes));
+    QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, kern, kQrThreads, L.lds_bytes));
     int ncu = 0;
     QRCTM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     if ((long long)nblk * ncu < L.P) {
@@ -661,15 +683,20 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
         s.msg = "qr: cooperative grid does not fit on the device";
         return s;
     }
-    const long long nwords = (long long)((S.off_xend - S.off_part) / sizeof(u64));
-    hipLaunchKernelGGL(clear_words_kernel, dim3((unsigned)std::min<long long>(ceil_div(nwords, 256), 2048)),
-                       dim3(256), 0, st, a.part, nwords);
-    QRCTM_TRY(launch_check("clear_words_kernel"));
+    const unsigned long long e = epoch % kQrEpochs;
+    if (e == 0) {
+        const long long nwords = (long long)((S.off_xend - S.off_part) / sizeof(u64));
+        hipLaunchKernelGGL(clear_words_kernel,
+                           dim3((unsigned)std::min<long long>(ceil_div(nwords, 256), 2048)), dim3(256), 0,
+                           st, a.part, nwords);
+        QRCTM_TRY(launch_check("clear_words_kernel"));
+    }
+    unsigned tag_base = (unsigned)e * kQrTagSpan;
     void* args[] = {(void*)&a.M,    (void*)&a.m,     (void*)&a.n,   (void*)&a.A,
                     (void*)&a.Q,    (void*)&a.R,     (void*)&a.part, (void*)&a.rowbuf,
-                    (void*)&a.red,  (void*)&a.redsum, (void*)&a.ratio, (void*)&a.err};
-    QRCTM_HIP(hipLaunchCooperativeKernel((const void*)qr_kernel, dim3(L.P), dim3(kQrThreads), args,
-                                         L.lds_bytes, st));
+                    (void*)&a.red,  (void*)&a.redsum, (void*)&a.ratio, (void*)&a.err,
+                    (void*)&tag_base};
+    QRCTM_HIP(hipLaunchCooperativeKernel(kern, dim3(L.P), dim3(kQrThreads), args, L.lds_bytes, st));
     return s;
 }
 
