@@ -391,6 +391,7 @@ def main():
             sctx.step(nt)
             sst = sctx.stats()
             sctx.close()
+            torch.cuda.empty_cache()  # the next, larger chi needs its own workspace
             sps = args.steps / el_s
             sweep.append({"chi": c, "steps_per_s": sps, "ms_per_step": 1e3 * el_s / args.steps,
                           "tflops": sst["flops_per_step"] * sps / 1e12,
