@@ -148,7 +148,7 @@ int ctm_step(ctm_ctx* ctx, int nsteps, double* delta);
 
 /*
  * ctm_converge: QR steps until delta < tol or max_steps steps were taken
- * (standard-CTMRG paragraph: "repeated until convergence").  steps / delta are
+ * (the standard-CTMRG paragraph iterates the step to convergence).  steps / delta are
  * host outputs (may be NULL).  Returns CTM_NOTCONV when max_steps is reached.
  */
 int ctm_converge(ctm_ctx* ctx, double tol, int max_steps, int* steps, double* delta);

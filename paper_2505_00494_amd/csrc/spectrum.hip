@@ -1,6 +1,6 @@
 // Corner spectrum and its change, the convergence measure of the CTMRG loop
-// (standard-CTMRG paragraph: iterate "until convergence"; the change in the
-// normalised corner spectrum is the measure used here).
+// (the standard-CTMRG paragraph iterates the step to convergence; the change
+// in the normalised corner spectrum is the measure used here).
 //
 // One workgroup of 512 threads.  Householder tridiagonalisation of the
 // symmetric chi x chi corner, keeping only its lower triangle (packed in LDS
@@ -8,7 +8,7 @@
 // rank-2 update of each reflection is applied lazily, in the same sweep of the
 // trailing triangle that forms the next reflection's product A v, so each
 // reflection reads and writes the triangle once.  Eigenvalues of the
-// tridiagonal matrix by Sturm-sequence bisection (one eigenvalue per thread),
+// tridiagonal matrix by Sturm-sequence multisection (1-8 lanes per eigenvalue),
 // |lambda| ranked in descending order (ties by index), normalised by their sum,
 // and delta = || s - s_prev ||_2 with the shorter spectrum padded by zeros.
 // Every reduction has a fixed order, so the result does not vary between runs.
