@@ -462,7 +462,8 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     const size_t skb = c->plan.splitk_bytes;
     // mixed forms (prec 1, 2): the contractions on the FP32 matrix cores, or
     // 3a/3b as split-BF16 products through bf16 planes of Y and of the double
-    // layer; QR, normalisation and the spectrum stay FP64
+    // layer; the fused split 3b on the FP32 matrix cores in both; QR,
+    // normalisation and the spectrum stay FP64
     auto G = [&](GemmDesc g) {
         g.prec = prec;
         return gemm_f64(g, sk, skb, c->st);
@@ -488,8 +489,8 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     }
     QRCTM_TRY(mark(3));
     if (split) {
-        QRCTM_TRY(edge_split_3b(p.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi, p.Z,
-                                c->st));                                               // a7 3b
+        QRCTM_TRY(edge_split_3b(p.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi, p.Z, c->st,
+                                prec > 0));                                            // a7 3b
     } else {
         GemmDesc gb = g_edge_b(p, chi, chi, Dab);                                      // a7 3b
         if (planes) {

@@ -27,9 +27,10 @@ Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_
 // Z (chio x D^2 x chi x D^2, layout [al][r][f][dd]) from Y (chio x chi x D^2 x
 // D^2, layout [al][f][u][l]) and the prepared operand, whose counters the launch
 // uses (launches on one Bk must be ordered, e.g. on one stream).  Y and Z must
-// not overlap.
+// not overlap.  fp32: products on the FP32 matrix cores (Y and Bk rounded to
+// FP32, FP32 accumulation; Y and Z stay double in memory), for the mixed forms.
 Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chio, double* Z,
-                     hipStream_t st);
+                     hipStream_t st, bool fp32 = false);
 // (d, D) for which the fused reverse is built: d = 2, 1 <= D <= 8.
 bool edge_split_bw_supported(int d, int D);
 // Doubles of the partial-sum scratch edge_split_3b_backward needs.

@@ -60,18 +60,40 @@ struct Shape3b {
     static_assert(MT % G == 0, "row tiles split evenly over the groups");
 };
 
-template <int D, int DP>
+// The products on the FP64 matrix cores (CT = double) or, for the mixed
+// forms, on the FP32 ones (CT = float: Y and Bk rounded to FP32 in LDS and
+// registers, FP32 accumulation, Z stored as double).
+template <class CT> struct SplitMma;
+template <> struct SplitMma<double> {
+    typedef dbl4 acc_t;
+    __device__ static acc_t run(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row (within the 16-row tile) of accumulator element r of quarter-wave q
+    __device__ static int row(int r, int q) { return 4 * r + q; }
+};
+template <> struct SplitMma<float> {
+    typedef flt4 acc_t;
+    __device__ static acc_t run(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int r, int q) { return 4 * q + r; }
+};
+
+template <class CT, int D, int DP>
 __global__ __launch_bounds__(Shape3b<D>::NT)
 __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
     const double* __restrict__ Y, const double* __restrict__ Bk, int chi, int npairs,
     double* __restrict__ Z, unsigned* ticket) {
     using S = Shape3b<D>;
+    using M = SplitMma<CT>;
+    typedef typename M::acc_t acc_t;
     constexpr int R = S::R, KP = S::KP, NP = S::NP, NB = S::NB, P = S::P, MTW = S::MTW;
     constexpr int LDM = S::LDM, NT = S::NT, NY = S::NY, NL = S::NL, KS = KP / 4;
-    __shared__ double ys[KP * LDM];  // ys[(u_k l_k)][(p u_b l_b)]
-    __shared__ double xs[KP * LDM];  // xs[(u_b l_b)][(p r_k d_k)]
+    __shared__ CT ys[KP * LDM];  // ys[(u_k l_k)][(p u_b l_b)]
+    __shared__ CT xs[KP * LDM];  // xs[(u_b l_b)][(p r_k d_k)]
     __shared__ int next_batch;
-    __shared__ double bs[S::NBS];    // Bk (when S::BLDS)
+    __shared__ CT bs[S::NBS];    // Bk (when S::BLDS)
     constexpr bool BLDS = S::BLDS;
     constexpr int KU = S::KU;
 
@@ -95,22 +117,22 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
 
     // padding rows and columns stay zero for the whole launch
     for (int i = tid; i < KP * LDM; i += NT) {
-        ys[i] = 0.0;
-        xs[i] = 0.0;
+        ys[i] = (CT)0;
+        xs[i] = (CT)0;
     }
 
     // this wave's B fragments: k rows 4 kk .. 4 kk + 3, columns 16 nt .. 16 nt + 15 of Bk[s]
-    double bf[BLDS ? 1 : DP][BLDS ? 1 : KS];
+    CT bf[BLDS ? 1 : DP][BLDS ? 1 : KS];
     if constexpr (BLDS) {
-        for (int i = tid; i < DP * KP * NP; i += NT) bs[i] = Bk[i];
+        for (int i = tid; i < DP * KP * NP; i += NT) bs[i] = (CT)Bk[i];
     } else {
 #pragma unroll
         for (int s = 0; s < DP; ++s)
 #pragma unroll
             for (int kk = 0; kk < KS; ++kk)
-                bf[s][kk] = Bk[((long long)s * KP + 4 * kk + q) * NP + 16 * nt + l16];
+                bf[s][kk] = (CT)Bk[((long long)s * KP + 4 * kk + q) * NP + 16 * nt + l16];
     }
-    auto bfrag = [&](int s, int kk) -> double {
+    auto bfrag = [&](int s, int kk) -> CT {
         if constexpr (BLDS) return bs[(s * KP + 4 * kk + q) * NP + 16 * nt + l16];
         else return bf[s][kk];
     };
@@ -133,7 +155,7 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
             if (e < NY) {
                 const int p = e / (R * R), v = e % (R * R);
                 const int uk = v / (D * R), ub = (v / R) % D, lk = (v / D) % D, lb = v % D;
-                ys[(uk * D + lk) * LDM + p * R + ub * D + lb] = pre[i];
+                ys[(uk * D + lk) * LDM + p * R + ub * D + lb] = (CT)pre[i];
             }
         }
     };
@@ -146,39 +168,37 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
         __syncthreads();  // ys holds batch b; xs reads of the previous batch are done
         const int bn = next_batch;  // read before the next barrier; rewritten after it
 
-        dbl4 z[MTW];
+        acc_t z[MTW];
 #pragma unroll
-        for (int i = 0; i < MTW; ++i) z[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < MTW; ++i) z[i] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < DP; ++s) {
-            dbl4 x[MTW];
+            acc_t x[MTW];
 #pragma unroll
-            for (int i = 0; i < MTW; ++i) x[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < MTW; ++i) x[i] = acc_t{0, 0, 0, 0};
 #pragma unroll KU
             for (int kk = 0; kk < KS; ++kk) {
-                const double* row = ys + (4 * kk + q) * LDM + 16 * mt0 + l16;
-                const double bv = bfrag(s, kk);
+                const CT* row = ys + (4 * kk + q) * LDM + 16 * mt0 + l16;
+                const CT bv = bfrag(s, kk);
 #pragma unroll
-                for (int i = 0; i < MTW; ++i)
-                    x[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * i], bv, x[i], 0, 0, 0);
+                for (int i = 0; i < MTW; ++i) x[i] = M::run(row[16 * i], bv, x[i]);
             }
             if (s > 0) __syncthreads();  // xs reads of the previous s are done
 #pragma unroll
             for (int i = 0; i < MTW; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int m = 16 * (mt0 + i) + 4 * r + q, c = 16 * nt + l16;
+                    const int m = 16 * (mt0 + i) + M::row(r, q), c = 16 * nt + l16;
                     if (m < P * R && c < R) xs[(m % R) * LDM + (m / R) * R + c] = x[i][r];
                 }
             __syncthreads();  // xs complete; every wave is past its last read of ys
             if (s == DP - 1 && bn < nbatch) load(bn);
 #pragma unroll KU
             for (int kk = 0; kk < KS; ++kk) {
-                const double* row = xs + (4 * kk + q) * LDM + 16 * mt0 + l16;
-                const double bv = bfrag(s, kk);
+                const CT* row = xs + (4 * kk + q) * LDM + 16 * mt0 + l16;
+                const CT bv = bfrag(s, kk);
 #pragma unroll
-                for (int i = 0; i < MTW; ++i)
-                    z[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(row[16 * i], bv, z[i], 0, 0, 0);
+                for (int i = 0; i < MTW; ++i) z[i] = M::run(row[16 * i], bv, z[i]);
             }
         }
 
@@ -189,13 +209,13 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
             for (int i = 0; i < MTW; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int m = 16 * (mt0 + i) + 4 * r + q;
+                    const int m = 16 * (mt0 + i) + M::row(r, q);
                     if (m >= P * R) continue;
                     const int pg = b * P + m / R;
                     if (pg >= npairs) continue;
                     const int c = m % R, al = pg / chi, f = pg - al * chi;
                     const int rk = c / D, dk = c % D;
-                    Z[(al * R + rk * D + rb) * chi * R + f * R + dk * D + db] = z[i][r];
+                    Z[(al * R + rk * D + rb) * chi * R + f * R + dk * D + db] = (double)z[i][r];
                 }
         }
         if (bn >= nbatch) break;
@@ -515,24 +535,30 @@ Status launch_3b_bw(const double* Y, const double* Zb, const double* Bk, const d
     return launch_check("edge_split_bw_reduce_kernel");
 }
 
-template <int D>
-Status launch_3b(const double* Y, const double* Bk, unsigned* ticket, int chi, int npairs,
-                 double* Z, hipStream_t st) {
+template <class CT, int D>
+Status launch_3b_t(const double* Y, const double* Bk, unsigned* ticket, int chi, int npairs,
+                   double* Z, hipStream_t st) {
     using S = Shape3b<D>;
     static int per_cu = -1, cus = 0;
     if (per_cu < 0) {
         int dev = 0;
         QRCTM_HIP(hipGetDevice(&dev));
         QRCTM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_split_kernel<D, 2>,
+        QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_split_kernel<CT, D, 2>,
                                                                S::NT, 0));
         if (per_cu < 1) per_cu = 1;
     }
     const long long nbatch = ceil_div(npairs, S::P);
     const int grid = (int)std::min<long long>(nbatch, (long long)per_cu * cus);
-    hipLaunchKernelGGL((edge_split_kernel<D, 2>), dim3(grid), dim3(S::NT), 0, st, Y, Bk, chi,
+    hipLaunchKernelGGL((edge_split_kernel<CT, D, 2>), dim3(grid), dim3(S::NT), 0, st, Y, Bk, chi,
                        npairs, Z, ticket);
     return launch_check("edge_split_kernel");
+}
+template <int D>
+Status launch_3b(const double* Y, const double* Bk, unsigned* ticket, int chi, int npairs,
+                 double* Z, bool fp32, hipStream_t st) {
+    return fp32 ? launch_3b_t<float, D>(Y, Bk, ticket, chi, npairs, Z, st)
+                : launch_3b_t<double, D>(Y, Bk, ticket, chi, npairs, Z, st);
 }
 
 int kp_of(int D) { return (D * D + 3) / 4 * 4; }
@@ -565,7 +591,7 @@ Status edge_split_prepare(const double* As, int d, int D, double* Bk, hipStream_
 }
 
 Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chio, double* Z,
-                     hipStream_t st) {
+                     hipStream_t st, bool fp32) {
     Status s;
     if (!edge_split_supported(d, D) || chi < 0 || chio < 0 ||
         (long long)chi * chio * D * D * D * D + (1LL << 16) >= (1LL << 31)) {
@@ -577,14 +603,14 @@ Status edge_split_3b(const double* Y, double* Bk, int d, int D, int chi, int chi
     if (npairs == 0) return s;
     unsigned* tk = reinterpret_cast<unsigned*>(Bk + 2 * (size_t)d * kp_of(D) * np_of(D));
     switch (D) {
-        case 1: return launch_3b<1>(Y, Bk, tk, chi, npairs, Z, st);
-        case 2: return launch_3b<2>(Y, Bk, tk, chi, npairs, Z, st);
-        case 3: return launch_3b<3>(Y, Bk, tk, chi, npairs, Z, st);
-        case 4: return launch_3b<4>(Y, Bk, tk, chi, npairs, Z, st);
-        case 5: return launch_3b<5>(Y, Bk, tk, chi, npairs, Z, st);
-        case 6: return launch_3b<6>(Y, Bk, tk, chi, npairs, Z, st);
-        case 7: return launch_3b<7>(Y, Bk, tk, chi, npairs, Z, st);
-        default: return launch_3b<8>(Y, Bk, tk, chi, npairs, Z, st);
+        case 1: return launch_3b<1>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        case 2: return launch_3b<2>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        case 3: return launch_3b<3>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        case 4: return launch_3b<4>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        case 5: return launch_3b<5>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        case 6: return launch_3b<6>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        case 7: return launch_3b<7>(Y, Bk, tk, chi, npairs, Z, fp32, st);
+        default: return launch_3b<8>(Y, Bk, tk, chi, npairs, Z, fp32, st);
     }
 }
 
