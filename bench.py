@@ -300,12 +300,12 @@ def main():
         conv_ref = {}
         for key, prec, desc in (
                 ("mixed", P.PREC_FP32_MFMA,
-                 "GEMMs on the fp32 matrix cores (FP32 products and accumulation); 3b the "
-                 "fused FP64 split kernel; QR, normalisation, spectrum FP64"),
+                 "GEMMs and the fused split 3b on the fp32 matrix cores (FP32 products and "
+                 "accumulation); QR, normalisation, spectrum FP64"),
                 ("mixed_bf16x6", P.PREC_BF16X6_MFMA,
                  "split-BF16 form: large GEMMs as six bf16 products of three-part operands "
-                 "with FP32 accumulation, the rest on the fp32 matrix cores; 3b the fused "
-                 "FP64 split kernel; QR, normalisation, spectrum FP64")):
+                 "with FP32 accumulation, the rest (the fused split 3b included) on the fp32 "
+                 "matrix cores; QR, normalisation, spectrum FP64")):
             mctx = P.Context(A, chi, precision=prec, n_warmup=0)
             mctx.set_env(C0, T0)
             if args.warmup:
