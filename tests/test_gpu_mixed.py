@@ -123,3 +123,30 @@ def test_mixed_converge_refines_to_fp64_fixed_point(prec):
     assert abs(em - e64) < 1e-10 * abs(e64)
     ref.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("D,chi", [(1, 4), (3, 18), (5, 50), (7, 49), (8, 64)])
+def test_fp32_split_3b_close_to_fp64_split(D, chi):
+    """The FP32 build of the fused split 3b at the bond dimensions whose batch
+    and wave layouts the tests above do not reach: one step of the FP32 form
+    against one FP64 step from the same random environment (the FP64 split
+    path is checked against the oracle in test_gpu_ctm)."""
+    print(f"fp32 split 3b D={D} chi={chi}", flush=True)
+    rng = np.random.default_rng(100 + D)
+    A = inp.random_site_tensor(2, D, 7)
+    C = rng.standard_normal((chi, chi))
+    C = 0.5 * (C + C.T)
+    T = rng.standard_normal((chi, D * D, chi))
+    T = 0.5 * (T + T.transpose(2, 1, 0))
+    out = []
+    for prec in (P.PREC_FP64, P.PREC_FP32_MFMA):
+        ctx = P.Context(_dev(A), chi, n_warmup=0, precision=prec, edge_split=1)
+        ctx.set_env(_dev(C), _dev(T))
+        ctx.step(1)
+        out.append([x.cpu().numpy() for x in ctx.get_env()])
+        ctx.close()
+    (C64, T64), (C32, T32) = out
+    assert np.abs(C32 - C64).max() / np.abs(C64).max() < 1e-4
+    assert np.abs(T32 - T64).max() / np.abs(T64).max() < 1e-4
+    # not the FP64 result: the FP32 products did run
+    assert np.abs(T32 - T64).max() > 0.0
