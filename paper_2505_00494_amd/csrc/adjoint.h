@@ -18,7 +18,10 @@ Status sq_norm(const double* Cb, const double* Tb, long long nC, long long nT, d
 // *out (host) = |C1 - C0|^2 + |T1 - T0|^2; synchronises the stream.
 Status sq_diff(const double* C1, const double* C0, const double* T1, const double* T0,
                long long nC, long long nT, double* part, double* out, hipStream_t st);
-Status tri_inv_upper(const double* R, int n, double* Ri, hipStream_t st);
+// Ri = R^{-1} for the upper-triangular n x n R (row-major).  scratch (n x n
+// doubles, overwritten; may be null) holds R^T when R's triangle does not fit
+// in LDS.
+Status tri_inv_upper(const double* R, int n, double* Ri, double* scratch, hipStream_t st);
 // Asb += reverse of a_int = sum_s As (x) As (a_int layout [U][L][R][Dn])
 Status double_layer_backward(const double* abar, const double* As, int d, int D, double* Asb,
                              hipStream_t st);

@@ -5,7 +5,7 @@
 //   copyltu             tril(M) + tril(M,-1)^T for the thin-QR adjoint
 //                       Abar = (Qbar + Q copyltu(R Rbar^T - Qbar^T Q)) R^{-T},
 //   tri_inv_upper       R^{-1} of the upper-triangular R (one workgroup per column,
-//                       the triangle of R in LDS; one column per thread for large n),
+//                       the triangle of R in LDS, or for large n R^T read from L2),
 //   double_layer_backward, c4v_backward (reverse of a2 and a1),
 //   ratio_min           running minimum of min|R_ii|/max|R_ii| over tracked steps.
 #include "adjoint.h"
@@ -138,6 +138,60 @@ __global__ __launch_bounds__(kTriThreads) void tri_inv_col_kernel(const double* 
         if (k < i) b -= tri[(size_t)k * n - (size_t)k * (k - 1) / 2 + (i - k)] * x[i];
     }
     for (int i = k; i < n; i += kTriThreads) Ri[(size_t)i * n + j] = i <= j ? x[i] : 0.0;
+}
+
+// Rt = R^T (n x n, row-major), 16 x 16 tiles through LDS.
+__global__ void transpose_kernel(const double* __restrict__ R, int n, double* __restrict__ Rt) {
+    __shared__ double tile[16][17];
+    const int bx = blockIdx.x * 16, by = blockIdx.y * 16, tx = threadIdx.x, ty = threadIdx.y;
+    if (by + ty < n && bx + tx < n) tile[ty][tx] = R[(size_t)(by + ty) * n + bx + tx];
+    __syncthreads();
+    if (bx + ty < n && by + tx < n) Rt[(size_t)(bx + ty) * n + by + tx] = tile[tx][ty];
+}
+
+// Column j of R^{-1} by one workgroup when R's triangle does not fit in LDS:
+// the same back substitution, with column i of R read as row i of Rt (in L2,
+// one coalesced read per step, issued a step ahead).  b lives in LDS (thread
+// k owns entries k, k + 256, ...), x_i is handed over through a double buffer,
+// so one barrier per step suffices.  n <= 1024.
+__global__ __launch_bounds__(kTriThreads) void tri_inv_col_l2_kernel(const double* __restrict__ Rt,
+                                                                     int n, double* Ri) {
+    __shared__ double bs[1024];
+    __shared__ double xs[2];
+    const int j = blockIdx.x, t = threadIdx.x;
+    for (int k = t; k < n; k += kTriThreads) {
+        bs[k] = k == j ? 1.0 : 0.0;
+        if (k > j) Ri[(size_t)k * n + j] = 0.0;
+    }
+    constexpr int KPT = 1024 / kTriThreads;
+    double r[KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+        const int k = t + u * kTriThreads;
+        r[u] = k < j ? Rt[(size_t)j * n + k] : 0.0;
+    }
+    __syncthreads();
+    for (int i = j; i >= 0; --i) {
+        if (t == i % kTriThreads) {
+            const double x = bs[i] / Rt[(size_t)i * n + i];
+            xs[i & 1] = x;
+            Ri[(size_t)i * n + j] = x;
+        }
+        __syncthreads();
+        const double x = xs[i & 1];
+        double rn[KPT];
+#pragma unroll
+        for (int u = 0; u < KPT; ++u) {
+            const int k = t + u * kTriThreads;
+            rn[u] = (i > 0 && k < i - 1) ? Rt[(size_t)(i - 1) * n + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < KPT; ++u) {
+            const int k = t + u * kTriThreads;
+            if (k < i) bs[k] -= r[u] * x;
+            r[u] = rn[u];
+        }
+    }
 }
 
 // Asb[s,u,l,d,r] += sum_{u',l',d',r'} (abar[(u u'),(l l'),(r r'),(d d')] +
@@ -299,13 +353,20 @@ Status copyltu(const double* M, int n, double* Ms, hipStream_t st) {
     return launch_check("copyltu_kernel");
 }
 
-Status tri_inv_upper(const double* R, int n, double* Ri, hipStream_t st) {
+Status tri_inv_upper(const double* R, int n, double* Ri, double* scratch, hipStream_t st) {
     const size_t lds = sizeof(double) * ((size_t)n * (n + 1) / 2 + (size_t)n);
     if (n <= kTriThreads && lds <= (size_t)kTriMaxLds) {
         QRCTM_HIP(hipFuncSetAttribute((const void*)tri_inv_col_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(tri_inv_col_kernel, dim3(n), dim3(kTriThreads), lds, st, R, n, Ri);
         return launch_check("tri_inv_col_kernel");
+    }
+    if (scratch != nullptr && n <= 1024) {
+        const int nb = (int)ceil_div(n, 16);
+        hipLaunchKernelGGL(transpose_kernel, dim3(nb, nb), dim3(16, 16), 0, st, R, n, scratch);
+        QRCTM_TRY(launch_check("transpose_kernel"));
+        hipLaunchKernelGGL(tri_inv_col_l2_kernel, dim3(n), dim3(kTriThreads), 0, st, scratch, n, Ri);
+        return launch_check("tri_inv_col_l2_kernel");
     }
     hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, R, n, Ri);
     return launch_check("tri_inv_upper_kernel");

@@ -676,7 +676,7 @@ Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, int i, const double* Ci, 
     QRCTM_TRY(run(11));
     QRCTM_TRY(copyltu(g.Mm, chi, g.Ms, c->st));
     QRCTM_TRY(run(12));                                    // Qbar + Q copyltu(M)
-    QRCTM_TRY(tri_inv_upper(p.R, chi, g.Rinv, c->st));
+    QRCTM_TRY(tri_inv_upper(p.R, chi, g.Rinv, g.Mm, c->st));  // M is dead once Ms holds copyltu(M)
     QRCTM_TRY(run(13));                                    // ... R^{-T}
     QRCTM_TRY(run(14));                                    // a5
     QRCTM_TRY(run(15));
