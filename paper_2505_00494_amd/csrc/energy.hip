@@ -35,14 +35,23 @@ struct PermArgs {
     long long total;
 };
 
+// One output element per thread, written in order; its source offset from the
+// output index, axis by axis.  I = unsigned when every offset fits in 32 bits
+// (32-bit division is several times cheaper than 64-bit).
+template <class I>
 __global__ void permute_kernel(const double* __restrict__ in, double* out, PermArgs p) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < p.total;
-         e += (long long)gridDim.x * blockDim.x) {
-        long long rem = e, src = 0;
+    I dims[kMaxDims], strides[kMaxDims];
+    for (int q = 0; q < p.nd; ++q) {
+        dims[q] = (I)p.out_dims[q];
+        strides[q] = (I)p.in_strides[q];
+    }
+    const I total = (I)p.total;
+    for (I e = (I)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (I)gridDim.x * blockDim.x) {
+        I rem = e, src = 0;
         for (int q = p.nd - 1; q >= 0; --q) {
-            const long long i = rem % p.out_dims[q];
-            rem /= p.out_dims[q];
-            src += i * p.in_strides[q];
+            const I i = rem % dims[q];
+            rem /= dims[q];
+            src += i * strides[q];
         }
         out[e] = in[src];
     }
@@ -65,7 +74,11 @@ Status permute(const double* in, double* out, int nd, const long long* dims, con
         p.in_strides[q] = stride[axes[q]];
     }
     const int blocks = (int)std::min<long long>(ceil_div(p.total, 256), 65536);
-    hipLaunchKernelGGL(permute_kernel, dim3(blocks), dim3(256), 0, st, in, out, p);
+    if (p.total < (1LL << 31)) {
+        hipLaunchKernelGGL(permute_kernel<unsigned>, dim3(blocks), dim3(256), 0, st, in, out, p);
+    } else {
+        hipLaunchKernelGGL(permute_kernel<long long>, dim3(blocks), dim3(256), 0, st, in, out, p);
+    }
     return launch_check("permute_kernel");
 }
 
