@@ -42,7 +42,7 @@ def _rel(x, y):
 @pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("d,D,chi,nsteps", [(2, 2, 16, 6), (2, 3, 36, 4), (2, 4, 64, 3),
                                             (2, 5, 75, 2), (2, 6, 144, 2), (2, 7, 98, 1),
-                                            (2, 8, 128, 1), (2, 2, 600, 1)])
+                                            (2, 8, 128, 1), (2, 2, 600, 1), (2, 2, 1024, 1)])
 def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps, split):
     print(f"steps d={d} D={D} chi={chi} edge_split={split}", flush=True)
     A, As, a, C, T = _oracle_setup(d, D, chi, seed=1)
