@@ -374,6 +374,20 @@ def main():
         out["grad"] = {"ms": 1e3 * (time.perf_counter() - t0), "k_tracked": args.k,
                        "energy": e, "grad_norm": float(g.norm())}
         gctx.close()
+        # the same with each tracked step's Y and Z kept (2 k chi^2 D^4 doubles
+        # more workspace, no recomputation of 3a and 3b in the reverse sweep)
+        kctx = P.Context(A, chi, n_warmup=0, k_tracked=args.k, grad_keep_yz=1)
+        kctx.set_env(C0, T0)
+        kctx.energy_grad(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ek, gk = kctx.energy_grad(h)
+        torch.cuda.synchronize()
+        out["grad"]["ms_kept_yz"] = 1e3 * (time.perf_counter() - t0)
+        out["grad"]["kept_yz_rel_diff"] = float((gk - g).norm() / g.norm())
+        kctx.close()
+        del gk
+        torch.cuda.empty_cache()
     ctx.close()
     if args.chi_sweep:
         # time per step against chi (same tensor, default form), cf. the paper's Fig. 2b

@@ -76,7 +76,8 @@ typedef struct ctm_opts {
     int edge_split;     /* 1: the edge contraction T a of the QR step applies the ket
                            layer A and then the bra layer A (Fig. 1b) instead of the
                            double-layer tensor a: 4 d chi^2 D^6 in place of 2 chi^2 D^8
-                           flops, FP64 in every precision, same result up to rounding.
+                           flops, same result up to rounding (FP64, or the FP32
+                           matrix cores in the mixed precisions).
                            Used where available (quantum contexts with d = 2, D <= 8
                            and chi^2 D^4 < 2^31 - 2^16), otherwise ignored.  0: always
                            the double-layer product.                                     */
@@ -85,11 +86,15 @@ typedef struct ctm_opts {
                            fp_tol times the norm of dE/d(C, T)                        */
     int fp_max_iter;    /* fixed point: at most this many reversed steps (rounded up
                            to even); ctm_energy_grad returns CTM_NOTCONV beyond it     */
+    int grad_keep_yz;   /* 1: ctm_energy_grad keeps each tracked step's Y and Z (3a and
+                           3b outputs, chi^2 D^4 doubles each) instead of recomputing
+                           them in the reverse sweep: 2 max(k_tracked, 2) chi^2 D^4
+                           doubles more workspace, the same result.  0: recompute.    */
 } ctm_opts;
 
 /* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = 10, qr_sing_tol = 1e-14,
    mixed_tol = 1e-6, edge_split = 1, grad_mode = CTM_GRAD_CHECKPOINT, fp_tol = 1e-10,
-   fp_max_iter = 1000. */
+   fp_max_iter = 1000, grad_keep_yz = 0. */
 void ctm_default_opts(ctm_opts* o);
 
 /*

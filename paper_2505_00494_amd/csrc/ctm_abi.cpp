@@ -132,8 +132,10 @@ struct GradLayout {
     size_t ckC, ckT, Cb, Tb, Cb2, Tb2, Ctmp, Ttmp, Cpb, Tpb, Wb, Rb, Qb, Zg, Mm, Ms, Rinv, ctb, abar,
         Asb, part, ratio, splitk, bwpart;
     // per reversed step: the forward step's Q, R, T', W and its two norms, kept
-    // so that the reverse sweep recomputes only Y and Z (3a, 3b)
-    size_t sQ, sR, sTp, sW, sN;
+    // so that the reverse sweep recomputes only Y and Z (3a, 3b); with
+    // grad_keep_yz, Y and Z too (sY, sZ, else empty)
+    size_t sQ, sR, sTp, sW, sN, sY = 0, sZ = 0;
+    bool keep_yz = false;
     size_t splitk_bytes = 0, bwpart_doubles = 0, total = 0;
 };
 
@@ -148,7 +150,7 @@ bool use_split_bw(const Shape& sh, const ctm_opts& o) {
     return use_split(sh, o) && edge_split_bw_supported(sh.d, sh.D);
 }
 
-GradLayout grad_layout(const Shape& sh, int k, bool split_bw) {
+GradLayout grad_layout(const Shape& sh, int k, bool split_bw, bool keep_yz) {
     GradLayout L;
     if (!sh.quantum) return L;
     size_t off = 0;
@@ -171,6 +173,11 @@ GradLayout grad_layout(const Shape& sh, int k, bool split_bw) {
     const size_t nslot = (size_t)std::max(k, 2);
     L.sQ = take(nslot * c2 * Db); L.sR = take(nslot * c2); L.sTp = take(nslot * c2 * Db);
     L.sW = take(nslot * c2 * Db); L.sN = take(nslot * 8);
+    if (keep_yz) {
+        L.keep_yz = true;
+        L.sY = take(nslot * c2 * Db * Db);
+        L.sZ = take(nslot * c2 * Db * Db);
+    }
     L.abar = take(Db * Db * Db * Db);
     L.Asb = take((size_t)sh.d * sh.D * sh.D * sh.D * sh.D);
     L.part = take(sym_norm_backward_scratch_bytes() / sizeof(double) + 1);
@@ -240,7 +247,7 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     P.energy_bytes = sh.quantum ? energy_scratch_bytes(sh.d, sh.D, sh.chi)
                                 : classical_scratch_bytes(sh.Dab, sh.chi);
     take(P.energy, P.energy_bytes);
-    P.grad_bytes = grad_layout(sh, o.k_tracked, use_split_bw(sh, o)).total;
+    P.grad_bytes = grad_layout(sh, o.k_tracked, use_split_bw(sh, o), o.grad_keep_yz != 0).total;
     take(P.grad, P.grad_bytes);
     // planes need the contraction length Dab^2 to be a multiple of 8 (D even)
     const bool planes = o.precision == CTM_PREC_BF16X6_MFMA && (Dab * Dab) % 8 == 0;
@@ -448,11 +455,14 @@ Status refresh_planes(ctm_ctx* c) {
 // a5-a9 from (Cin, Tin) into (Cout, Tout); intermediates stay in the step
 // buffers (Q, R, Y, Z, Tp, W, Cp) and the norms in the small-scalar slots.
 Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Cout, double* Tout,
-                    bool timed, int prec, hipEvent_t after_qr = nullptr) {
+                    bool timed, int prec, hipEvent_t after_qr = nullptr, double* Yo = nullptr,
+                    double* Zo = nullptr) {
     const int chi = c->chi_cur, Dab = c->sh.Dab;
     StepPtrs p = step_ptrs(c);
     p.C = Cin;
     p.T = Tin;
+    if (Yo) p.Y = Yo;  // Y and Z into caller buffers (the gradient keeping them)
+    if (Zo) p.Z = Zo;
     const bool tm = timed && c->timing;
     auto mark = [&](int i) -> Status {
         if (!tm) return Status{};
@@ -590,12 +600,14 @@ Status eigh_step_once(ctm_ctx* c) {
 struct GradPtrs {
     double *ckC, *ckT, *Cb, *Tb, *Cb2, *Tb2, *Ctmp, *Ttmp, *Cpb, *Tpb, *Wb, *Rb, *Qb, *Zg, *Mm, *Ms,
         *Rinv, *ctb, *abar, *Asb, *part, *ratio, *bwpart, *sQ, *sR, *sTp, *sW, *sN;
+    double *sY = nullptr, *sZ = nullptr;  // kept Y and Z per step (grad_keep_yz)
     void* splitk;
     size_t splitk_bytes, bwpart_doubles;
 };
 
 GradPtrs grad_ptrs(ctm_ctx* c) {
-    const GradLayout L = grad_layout(c->sh, c->opts.k_tracked, use_split_bw(c->sh, c->opts));
+    const GradLayout L =
+        grad_layout(c->sh, c->opts.k_tracked, use_split_bw(c->sh, c->opts), c->opts.grad_keep_yz != 0);
     char* b = c->ptr<char>(c->plan.grad);
     auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
     GradPtrs g;
@@ -609,13 +621,13 @@ GradPtrs grad_ptrs(ctm_ctx* c) {
     g.bwpart = P(L.bwpart);
     g.bwpart_doubles = L.bwpart_doubles;
     g.sQ = P(L.sQ); g.sR = P(L.sR); g.sTp = P(L.sTp); g.sW = P(L.sW); g.sN = P(L.sN);
+    if (L.keep_yz) {
+        g.sY = P(L.sY);
+        g.sZ = P(L.sZ);
+    }
     return g;
 }
 
-// Reverse of one QR step (a5-a9) from (Ci, Ti), given the cotangents (Cb, Tb)
-// of its normalised outputs; writes the cotangents of (Ci, Ti) into (Cb2, Tb2)
-// and accumulates that of the double layer into abar.  The step's forward
-// intermediates are recomputed first (only (C_i, T_i) are stored).
 // Keep the forward step's Q, R, T', W and norms (just computed by qr_step_core)
 // in reverse-pass slot i.
 Status save_step(ctm_ctx* c, const GradPtrs& g, int i) {
@@ -633,8 +645,9 @@ Status save_step(ctm_ctx* c, const GradPtrs& g, int i) {
 }
 
 // Reverse of the QR step kept in slot i, which mapped (Ci, Ti) to (Co, To).
-// Only Y and Z are recomputed (3a from the kept Q, then 3b); the cotangents
-// (g.Cb, g.Tb) of (Co, To) become (g.Cb2, g.Tb2) of (Ci, Ti).
+// Only Y and Z are recomputed (3a from the kept Q, then 3b), unless they were
+// kept too; the cotangents (g.Cb, g.Tb) of (Co, To) become (g.Cb2, g.Tb2) of
+// (Ci, Ti).
 Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, int i, const double* Ci, const double* Ti,
                         const double* Co, const double* To) {
     const int chi = c->chi_cur, Dab = c->sh.Dab;
@@ -643,19 +656,28 @@ Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, int i, const double* Ci, 
     sp.C = Ci;
     sp.T = Ti;
     const double* Qi = g.sQ + i * nQ;
-    QRCTM_TRY(gemm_f64(g_edge_a(sp, Qi, chi, chi, Dab), c->ptr<void>(c->plan.splitk),
-                       c->plan.splitk_bytes, c->st));
-    if (c->plan.Bk.bytes > 0)
-        QRCTM_TRY(edge_split_3b(sp.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi, sp.Z, c->st));
-    else
-        QRCTM_TRY(gemm_f64(g_edge_b(sp, chi, chi, Dab), c->ptr<void>(c->plan.splitk),
+    // scratch for Ybar: the step buffer Z (dead once Zbar and Qbar += Z^T Tpbar
+    // are formed when Z is recomputed there; unused when Z is kept)
+    double* ybar = sp.Z;
+    if (g.sY != nullptr) {
+        const size_t nY = nQ * Dab;
+        sp.Y = g.sY + i * nY;
+        sp.Z = g.sZ + i * nY;
+    } else {
+        QRCTM_TRY(gemm_f64(g_edge_a(sp, Qi, chi, chi, Dab), c->ptr<void>(c->plan.splitk),
                            c->plan.splitk_bytes, c->st));
+        if (c->plan.Bk.bytes > 0)
+            QRCTM_TRY(edge_split_3b(sp.Y, c->ptr(c->plan.Bk), c->sh.d, c->sh.D, chi, chi, sp.Z, c->st));
+        else
+            QRCTM_TRY(gemm_f64(g_edge_b(sp, chi, chi, Dab), c->ptr<void>(c->plan.splitk),
+                               c->plan.splitk_bytes, c->st));
+    }
     BwPtrs p;
     p.C = Ci; p.T = Ti; p.a = sp.a; p.Q = Qi; p.R = g.sR + i * c2; p.Y = sp.Y; p.Z = sp.Z;
     p.Tp = g.sTp + i * nQ;
     p.W = g.sW + i * nQ;
     p.Cpb = g.Cpb; p.Tpb = g.Tpb; p.Wb = g.Wb; p.Rb = g.Rb; p.Qb = g.Qb; p.Zg = g.Zg;
-    p.Y2 = sp.Z;  // Z is dead once Zbar and Qbar += Z^T Tpbar are formed
+    p.Y2 = ybar;
     p.abar = g.abar; p.Mm = g.Mm; p.Ms = g.Ms; p.Rinv = g.Rinv; p.ctb = g.ctb;
     p.Cb2 = g.Cb2; p.Tb2 = g.Tb2;
     auto run = [&](int id) { return gemm_f64(bw_gemm(id, p, chi, Dab), g.splitk, g.splitk_bytes, c->st); };
@@ -700,9 +722,11 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
     const int nfwd = fixed_point ? 2 : k;
     QRCTM_HIP(hipMemcpyAsync(g.ckC, c->C(), nC * 8, hipMemcpyDeviceToDevice, c->st));
     QRCTM_HIP(hipMemcpyAsync(g.ckT, c->T(), nT * 8, hipMemcpyDeviceToDevice, c->st));
+    const size_t nY = nT * Dab;
     for (int i = 0; i < nfwd; ++i) {
         QRCTM_TRY(qr_step_core(c, g.ckC + i * nC, g.ckT + i * nT, g.ckC + (i + 1) * nC,
-                               g.ckT + (i + 1) * nT, false, 0));
+                               g.ckT + (i + 1) * nT, false, 0, nullptr,
+                               g.sY ? g.sY + i * nY : nullptr, g.sZ ? g.sZ + i * nY : nullptr));
         QRCTM_TRY(ratio_min(c->small() + SL_RATIO, g.ratio, i == 0, c->st));
         QRCTM_TRY(save_step(c, g, i));
     }
@@ -850,7 +874,7 @@ bool valid_opts(const ctm_opts& o) {
             o.precision == CTM_PREC_BF16X6_MFMA) &&
            o.k_tracked >= 0 && (o.edge_split == 0 || o.edge_split == 1) &&
            (o.grad_mode == CTM_GRAD_CHECKPOINT || o.grad_mode == CTM_GRAD_FIXED_POINT) &&
-           o.fp_tol > 0.0 && o.fp_max_iter >= 2;
+           o.fp_tol > 0.0 && o.fp_max_iter >= 2 && (o.grad_keep_yz == 0 || o.grad_keep_yz == 1);
 }
 
 int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_t ws_bytes,
@@ -930,6 +954,7 @@ void ctm_default_opts(ctm_opts* o) {
     o->grad_mode = CTM_GRAD_CHECKPOINT;
     o->fp_tol = 1e-10;
     o->fp_max_iter = 1000;
+    o->grad_keep_yz = 0;
 }
 
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {

@@ -34,7 +34,8 @@ class CTMError(RuntimeError):
 class CtmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("n_warmup", c_int), ("k_tracked", c_int),
                 ("qr_sing_tol", c_double), ("mixed_tol", c_double), ("edge_split", c_int),
-                ("grad_mode", c_int), ("fp_tol", c_double), ("fp_max_iter", c_int)]
+                ("grad_mode", c_int), ("fp_tol", c_double), ("fp_max_iter", c_int),
+                ("grad_keep_yz", c_int)]
 
 
 class CtmStats(ctypes.Structure):
@@ -127,7 +128,7 @@ def _dev_f64(x, dev):
 
 def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-14,
                  mixed_tol=None, edge_split=None, grad_mode=None, fp_tol=None,
-                 fp_max_iter=None) -> CtmOpts:
+                 fp_max_iter=None, grad_keep_yz=None) -> CtmOpts:
     o = CtmOpts()
     lib().ctm_default_opts(byref(o))
     o.precision, o.n_warmup, o.k_tracked, o.qr_sing_tol = precision, n_warmup, k_tracked, qr_sing_tol
@@ -141,6 +142,8 @@ def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-
         o.fp_tol = float(fp_tol)
     if fp_max_iter is not None:
         o.fp_max_iter = int(fp_max_iter)
+    if grad_keep_yz is not None:
+        o.grad_keep_yz = int(grad_keep_yz)
     return o
 
 
@@ -150,11 +153,11 @@ class Context:
     def __init__(self, A=None, chi: int = 16, *, a=None, bvec=None, device="cuda:0",
                  n_warmup: int = -1, precision: int = PREC_FP64, k_tracked: int = 10,
                  qr_sing_tol: float = 1e-14, mixed_tol=None, edge_split=None,
-                 grad_mode=None, fp_tol=None, fp_max_iter=None):
+                 grad_mode=None, fp_tol=None, fp_max_iter=None, grad_keep_yz=None):
         torch = _torch()
         self.device = torch.device(device)
         self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol,
-                                 edge_split, grad_mode, fp_tol, fp_max_iter)
+                                 edge_split, grad_mode, fp_tol, fp_max_iter, grad_keep_yz)
         self.chi = chi
         L = lib()
         ctx = c_void_p()

@@ -23,6 +23,18 @@ def test_default_opts():
     assert o.qr_sing_tol == 1e-14 and o.mixed_tol == 1e-6
     assert o.edge_split == 1 and o.grad_mode == B.GRAD_CHECKPOINT
     assert o.fp_tol == 1e-10 and o.fp_max_iter == 1000
+    assert o.grad_keep_yz == 0
+
+
+def test_kept_yz_adds_two_slots_per_tracked_step():
+    # keeping Y and Z costs 2 max(k, 2) chi^2 D^4 doubles more, nothing else
+    L = P.lib()
+    for d, D, chi, k in [(2, 4, 64, 3), (2, 6, 144, 1), (2, 2, 16, 10)]:
+        keep, rec = B.default_opts(k_tracked=k, grad_keep_yz=1), B.default_opts(k_tracked=k)
+        extra = (L.ctm_workspace_bytes(d, D, chi, ctypes.byref(keep))
+                 - L.ctm_workspace_bytes(d, D, chi, ctypes.byref(rec)))
+        want = 2 * max(k, 2) * chi * chi * D**4 * 8
+        assert want <= extra < want + 4096
 
 
 def test_split_operand_planned_only_where_the_kernels_apply():

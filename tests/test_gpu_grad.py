@@ -137,3 +137,33 @@ def test_split_reverse_matches_double_layer_reverse(D, chi):
     assert abs(e1 - e0) < 1e-12 * abs(e0)
     assert np.linalg.norm(g1 - g0) / np.linalg.norm(g0) < 1e-10
     ctx.close()
+
+
+@pytest.mark.parametrize("mode,D,chi,k", [("checkpoint", 4, 64, 2), ("checkpoint", 6, 72, 3),
+                                          ("fixed_point", 4, 32, 0), ("checkpoint", 3, 27, 0)])
+def test_kept_yz_equals_recomputed_yz(mode, D, chi, k):
+    # keeping each tracked step's Y and Z from the forward sweep gives the same
+    # gradient as recomputing them in the reverse sweep (same kernels, same order)
+    print(f"keep_yz {mode} D={D} chi={chi} k={k}", flush=True)
+    A = _dev(inp.random_site_tensor(2, D, 1))
+    h = inp.heisenberg_bond_rotated()
+    ctx = P.Context(A, chi)
+    if mode == "fixed_point":  # converged elementwise, as for the fixed-point scheme's tests
+        ctx.converge(1e-13, 3000)
+        ctx.step(2500)
+    else:
+        ctx.step(10)
+    C, T = ctx.get_env()
+    extra = dict(grad_mode=P.GRAD_FIXED_POINT, fp_tol=1e-11, fp_max_iter=3000) \
+        if mode == "fixed_point" else {}
+    out = {}
+    for keep in (0, 1):
+        c = P.Context(A, chi, n_warmup=0, k_tracked=k, grad_keep_yz=keep, **extra)
+        c.set_env(C, T)
+        e, g = c.energy_grad(h)
+        out[keep] = (e, g.cpu().numpy())
+        c.close()
+    (e0, g0), (e1, g1) = out[0], out[1]
+    assert e1 == e0
+    assert np.linalg.norm(g1 - g0) <= 1e-13 * np.linalg.norm(g0)
+    ctx.close()
