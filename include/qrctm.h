@@ -187,14 +187,15 @@ int ctm_energy(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
  *     adjoint, the double layer and the C4v average).  (C_i, T_i) and each
  *     tracked step's Q, R, T', W are kept (k (4 chi^2 D^2 + 2 chi^2) doubles);
  *     the large intermediates Y and Z (chi^2 D^4 each) are recomputed in the
- *     reverse sweep.
+ *     reverse sweep, or kept too when opts.grad_keep_yz = 1.
  *   CTM_GRAD_FIXED_POINT: the fixed-point scheme (Discussion paragraph): the
  *     current environment must be converged.  With F one QR step and G = F o F
  *     (T may alternate between two gauges from step to step; the pair of
  *     steps is a fixed point in either case), dE/dA follows from the implicit
  *     function theorem, lam = ebar (I - dG/denv)^{-1} being summed as a
  *     Neumann series of reversed step pairs until a term's norm is below
- *     opts.fp_tol times |ebar|.  Memory: two environments, no checkpoints.
+ *     opts.fp_tol times |ebar|.  Memory: two environments, no checkpoints
+ *     (with opts.grad_keep_yz = 1, the two steps' Y and Z as well).
  *     The environment must be a fixed point of G elementwise: CTM_ESTATE when
  *     |G(env) - env| / |env| > 1e-8 (the corner spectrum can converge while
  *     C and T still drift; the series then need not converge).  Returns
