@@ -139,12 +139,13 @@ def test_split_reverse_matches_double_layer_reverse(D, chi):
     ctx.close()
 
 
-@pytest.mark.parametrize("mode,D,chi,k", [("checkpoint", 4, 64, 2), ("checkpoint", 6, 72, 3),
-                                          ("fixed_point", 4, 32, 0), ("checkpoint", 3, 27, 0)])
-def test_kept_yz_equals_recomputed_yz(mode, D, chi, k):
+@pytest.mark.parametrize("mode,D,chi,k,split", [("checkpoint", 4, 64, 2, 1), ("checkpoint", 6, 72, 3, 1),
+                                                ("checkpoint", 4, 64, 2, 0), ("fixed_point", 4, 32, 0, 1),
+                                                ("checkpoint", 3, 27, 0, 1)])
+def test_kept_yz_equals_recomputed_yz(mode, D, chi, k, split):
     # keeping each tracked step's Y and Z from the forward sweep gives the same
     # gradient as recomputing them in the reverse sweep (same kernels, same order)
-    print(f"keep_yz {mode} D={D} chi={chi} k={k}", flush=True)
+    print(f"keep_yz {mode} D={D} chi={chi} k={k} edge_split={split}", flush=True)
     A = _dev(inp.random_site_tensor(2, D, 1))
     h = inp.heisenberg_bond_rotated()
     ctx = P.Context(A, chi)
@@ -158,7 +159,7 @@ def test_kept_yz_equals_recomputed_yz(mode, D, chi, k):
         if mode == "fixed_point" else {}
     out = {}
     for keep in (0, 1):
-        c = P.Context(A, chi, n_warmup=0, k_tracked=k, grad_keep_yz=keep, **extra)
+        c = P.Context(A, chi, n_warmup=0, k_tracked=k, grad_keep_yz=keep, edge_split=split, **extra)
         c.set_env(C, T)
         e, g = c.energy_grad(h)
         out[keep] = (e, g.cpu().numpy())
