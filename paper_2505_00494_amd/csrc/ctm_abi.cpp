@@ -52,9 +52,19 @@ struct Shape {
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
-size_t step_splitk_bytes(int chi, int Dab) {
+// split-K scratch of the step's GEMMs; the mixed forms (FP32 accumulation) split
+// long contractions further
+size_t step_splitk_bytes(int chi, int Dab, bool mixed) {
     StepPtrs p{};
     size_t s = 0;
+    auto gemm_splitk_bytes = [mixed](GemmDesc g) {
+        size_t b = qrctm::gemm_splitk_bytes(g);
+        if (mixed) {
+            g.prec = 1;
+            b = std::max(b, qrctm::gemm_splitk_bytes(g));
+        }
+        return b;
+    };
     for (int c = 1; c <= chi; ++c) {
         s = std::max(s, gemm_splitk_bytes(g_reduced_corner(p, c, Dab)));
         s = std::max(s, gemm_splitk_bytes(g_edge_a(p, nullptr, c, c, Dab)));
@@ -228,7 +238,7 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     for (int c = 1; c <= sh.chi; ++c)
         P.qr_bytes = std::max(P.qr_bytes, qr_scratch_layout(c * sh.Dab, c).total);
     take(P.qr, P.qr_bytes);
-    P.splitk_bytes = step_splitk_bytes(sh.chi, sh.Dab);
+    P.splitk_bytes = step_splitk_bytes(sh.chi, sh.Dab, o.precision != CTM_PREC_FP64);
     take(P.splitk, P.splitk_bytes);
     // warm-up eigensolver scratch: order chi_in * Dab of the largest warm-up step
     {

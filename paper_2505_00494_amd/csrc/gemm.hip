@@ -291,6 +291,9 @@ struct Plan {
 };
 
 constexpr int kTargetBlocks = 512;
+// FP32 accumulation (mixed forms): the longest K range one block sums in FP32;
+// longer contractions are split and their partial sums added in FP64
+constexpr long long kF32Chunk = 1024;
 
 // Tile choice measured on the step's shapes: large M and N take 128x128; a
 // skinny N (the edge contraction 3c, N = chi) takes 128x48 tiles with split-K;
@@ -325,6 +328,12 @@ Plan make_plan(const GemmDesc& g) {
             pl.splits = (int)ceil_div(g.K, kc);
             pl.kchunk = kc;
         }
+    }
+    if (g.prec != 0 && g.C16 == nullptr && pl.kchunk > kF32Chunk) {
+        const long long s = std::min<long long>(ceil_div(g.K, kF32Chunk), 64);
+        const long long kc = ceil_div(ceil_div(g.K, s), 16) * 16;
+        pl.splits = (int)ceil_div(g.K, kc);
+        pl.kchunk = kc;
     }
     return pl;
 }
