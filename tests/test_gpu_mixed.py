@@ -150,3 +150,26 @@ def test_fp32_split_3b_close_to_fp64_split(D, chi):
     assert np.abs(T32 - T64).max() / np.abs(T64).max() < 1e-4
     # not the FP64 result: the FP32 products did run
     assert np.abs(T32 - T64).max() > 0.0
+
+
+@pytest.mark.parametrize("D,chi", [(6, 144), (8, 256)])
+def test_mixed_energy_error_within_1e7(D, chi):
+    # the mixed forms' energy after 20 steps against 20 FP64 steps from the same
+    # environment (FP32 block sums over at most 512 of K, longer contractions
+    # split with FP64 partial sums): within 1e-7 relative
+    A = torch.as_tensor(inp.random_site_tensor(2, D, 1), device="cuda:0")
+    h = inp.heisenberg_bond_rotated()
+    ctx = P.Context(A, chi)
+    ctx.step(10)
+    C0, T0 = ctx.get_env()
+    ctx.step(20)
+    e64 = ctx.energy(h)
+    for prec in (P.PREC_FP32_MFMA, P.PREC_BF16X6_MFMA):
+        m = P.Context(A, chi, precision=prec, n_warmup=0)
+        m.set_env(C0, T0)
+        m.step(20)
+        em = m.energy(h)
+        print(f"D={D} chi={chi} prec={prec}: energy error {abs(em - e64) / abs(e64):.2e}", flush=True)
+        assert abs(em - e64) < 1e-7 * abs(e64)
+        m.close()
+    ctx.close()
