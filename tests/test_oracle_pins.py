@@ -317,6 +317,75 @@ def test_eigh_and_qr_agree_on_ising_peps():
     assert abs(e["qr"] - e["eigh"]) < 1e-10
 
 
+def _heisenberg_energy(D, chi, seed, variant, max_steps):
+    A = inp.random_site_tensor(2, D, seed)
+    As = ctm.prepare_site_tensor(A)
+    a = ctm.double_layer(As)
+    r = ctm.ctmrg(a, chi, ctm.identity_boundary_vector(D), tol=1e-12, max_steps=max_steps,
+                  variant=variant)
+    return obs.energy_nn(r.C, r.T, As, inp.heisenberg_bond_rotated()), r
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_eigh_and_qr_agree_on_heisenberg_d4_chi64(seed):
+    # Heisenberg-results paragraph and Fig. 2(a): the QR scheme reaches the
+    # accuracy of the eigh scheme.  Random C4v tensors, D = 4, chi = 64, the
+    # rotated nearest-neighbour Heisenberg bond.  Eigh-CTMRG converges to 1e-12
+    # in 22-32 steps for every seed; QR-CTMRG only for seed 4 within 400 steps
+    # (seeds 1-3 end at a spectrum change of 2.8e-7, 2.0e-10 and 1.5e-5), yet
+    # the energies agree to <= 6e-8 relative (measured 3.4e-10, 5.7e-9, 5.8e-8,
+    # 5e-15).
+    e_eigh, r_eigh = _heisenberg_energy(4, 64, seed, "eigh", 100)
+    e_qr, r_qr = _heisenberg_energy(4, 64, seed, "qr", 400)
+    assert r_eigh.converged
+    assert abs(e_qr - e_eigh) <= 1e-6 * abs(e_eigh)
+    if seed == 4:
+        assert r_qr.converged and abs(e_qr - e_eigh) <= 1e-12 * abs(e_eigh)
+
+
+def test_eigh_and_qr_energy_gap_shrinks_with_chi():
+    # D = 2: the two truncations keep different chi-dimensional subspaces, so at
+    # finite chi their converged energies differ; the difference vanishes as chi
+    # grows.  Seeds 1 and 3 (short correlation length) agree at chi = 32 to
+    # rounding; seed 2 (longer) differs by 9.0e-5, 1.5e-5 and 2.6e-6 at
+    # chi = 16, 32 and 128 (1.2e-6 at chi = 256, measured).
+    for seed in (1, 3):
+        e1, r1 = _heisenberg_energy(2, 32, seed, "eigh", 200)
+        e2, r2 = _heisenberg_energy(2, 32, seed, "qr", 2000)
+        assert r1.converged and r2.converged
+        assert abs(e1 - e2) <= 1e-12 * abs(e1)
+    gap = {}
+    for chi in (16, 32, 128):
+        e1, r1 = _heisenberg_energy(2, chi, 2, "eigh", 200)
+        e2, r2 = _heisenberg_energy(2, chi, 2, "qr", 2000)
+        assert r1.converged and r2.converged
+        gap[chi] = abs(e1 - e2)
+    assert gap[128] < gap[32] < gap[16] and gap[128] < 5e-6
+
+
+def test_corner_spectrum_and_delta_by_hand():
+    # a10, written out for known eigenvalues: C = O diag(3, -1, 0.5, 0.5) O^T has
+    # |eig| sorted (3, 1, 0.5, 0.5), sum 5, so s = (0.6, 0.2, 0.1, 0.1); a 2x2
+    # corner with eigenvalues (-2, 2) has s = (0.5, 0.5), padded with zeros:
+    # delta^2 = 0.1^2 + 0.3^2 + 0.1^2 + 0.1^2 = 0.12.
+    rng = np.random.default_rng(5)
+    O, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    C = O @ np.diag([3.0, -1.0, 0.5, 0.5]) @ O.T
+    s = ctm.spectrum(C)
+    assert np.abs(s - np.array([0.6, 0.2, 0.1, 0.1])).max() < 1e-15
+    O2, _ = np.linalg.qr(rng.standard_normal((2, 2)))
+    s2 = ctm.spectrum(O2 @ np.diag([-2.0, 2.0]) @ O2.T)
+    assert np.abs(s2 - 0.5).max() < 1e-15
+    assert abs(ctm.spectrum_delta(s, s2) - np.sqrt(0.12)) < 1e-15
+    assert abs(ctm.spectrum_delta(s2, s) - np.sqrt(0.12)) < 1e-15
+    # invariant under scaling of C and its sign; zero change against itself
+    assert np.abs(ctm.spectrum(-7.0 * C) - s).max() < 1e-15
+    assert ctm.spectrum_delta(s, s) == 0.0
+    # a non-symmetric input is symmetrised first: the antisymmetric part is ignored
+    K = rng.standard_normal((4, 4))
+    assert np.abs(ctm.spectrum(C + (K - K.T)) - s).max() < 1e-14
+
+
 # --------------------------------------------------------------------------
 # a12: adjoint.
 # --------------------------------------------------------------------------
