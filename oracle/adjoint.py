@@ -6,7 +6,10 @@ The differentiated function (automatic-differentiation paragraph: untracked
 steps, then k steps with gradient tracking, then the energy) is
 
     E(A) = e( C_k, T_k, As ),  As = P(A) / max|P(A)|,  a = sum_s As (x) As,
-    (C_{i+1}, T_{i+1}) = sym_norm( QR-step(C_i, T_i, a) ),  (C_0, T_0) held fixed.
+    (C_{i+1}, T_{i+1}) = sym_norm( QR-step(C_i, T_i, a) ),  (C_0, T_0) held fixed,
+
+with e the nearest-neighbour energy 2<h>, or the J1-J2 energy 2<h> + 2 J2 <h_nnn>
+(J1-J2 paragraph; the diagonal pair from the 2x2 plaquette).
 
 Every adjoint below is written by hand from the forward formula it reverses.
 The QR adjoint (thin QR, m >= n, diag R > 0) is
@@ -144,6 +147,79 @@ def energy_nn_backward(C, T, A, h):
     return e, Cb, Tb, Ab
 
 
+def open_double_layer_backward(A, aobar):
+    """Cotangent of A from that of a_open[s,t,(u u'),(l l'),(d d'),(r r')] =
+    A[s,u,l,d,r] A[t,u',l',d',r'] (ket s, bra t)."""
+    d, D = A.shape[0], A.shape[1]
+    aob8 = aobar.reshape(d, d, D, D, D, D, D, D, D, D)  # [s,t,u,u',l,l',d,d',r,r']
+    return (np.einsum("staebfcgdh,tefgh->sabcd", aob8, A, optimize=True)
+            + np.einsum("tsaebfcgdh,tabcd->sefgh", aob8, A, optimize=True))
+
+
+def _bond_rdm_bar(rho, h, scale):
+    """(e, rhobar) for e = scale Tr(rm h) / Tr(rm), rm = rho as [(s1 s2),(s1' s2')]."""
+    d = rho.shape[0]
+    rm = rho.transpose(0, 2, 1, 3).reshape(d * d, d * d)
+    num = float(np.trace(rm @ h))
+    den = float(np.trace(rm))
+    rmb = (scale / den) * h.T - (scale * num / den ** 2) * np.eye(d * d)
+    return scale * num / den, rmb.reshape(d, d, d, d).transpose(0, 2, 1, 3)
+
+
+def energy_nnn_backward(C, T, A, h, J2):
+    """Return (e2, Cbar, Tbar, Abar) for the next-nearest-neighbour part
+    e2 = 2 J2 Tr(rho h)/Tr rho of the J1-J2 energy, rho from the 2x2 plaquette
+    (J1-J2 paragraph), reversing observables.rdm_nnn step by step:
+
+        ct3[y,u,c]   = sum_x C[y,x] T[x,u,c]                 (reduced corner)
+        G[l,e,u,c]   = sum_y T[y,l,e] ct3[y,u,c]
+        Cc           = sym( G . a       -> [(e,dn),(c,r)] )  (closed enlarged corner)
+        Co[s,t]      = sym( G . a_open  -> [(e,dn),(c,r)] )  (open enlarged corner)
+        X[s,t]       = Co[s,t] Cc,   rho[s1,t1,s2,t2] = Tr(X[s1,t1] X[s2,t2]).
+    """
+    from .ctmrg import double_layer, open_double_layer
+    d = A.shape[0]
+    chi, Dab, _ = T.shape
+    n = chi * Dab
+    a = double_layer(A)
+    ao = open_double_layer(A)
+    ct3 = (C @ T.reshape(chi, Dab * chi)).reshape(chi, Dab, chi)
+    G = np.einsum("yle,yuc->leuc", T, ct3, optimize=True)
+    Ct4 = np.einsum("leuc,ulnr->ecnr", G, a, optimize=True)
+    Cc = Ct4.transpose(0, 2, 1, 3).reshape(n, n)
+    Cc = 0.5 * (Cc + Cc.T)
+    Co6 = np.einsum("leuc,stulnr->stencr", G, ao, optimize=True)
+    Co = Co6.reshape(d, d, n, n)
+    Co = 0.5 * (Co + Co.transpose(0, 1, 3, 2))
+    X = np.einsum("abij,jk->abik", Co, Cc, optimize=True)
+    rho = np.einsum("abij,cdji->abcd", X, X, optimize=True)
+    e2, rhob = _bond_rdm_bar(rho, h, 2.0 * J2)
+
+    Xb = (np.einsum("abcd,cdji->abij", rhob, X, optimize=True)
+          + np.einsum("cdab,cdji->abij", rhob, X, optimize=True))
+    Cob = np.einsum("abik,jk->abij", Xb, Cc, optimize=True)       # Xb Cc^T
+    Ccb = np.einsum("abij,abik->jk", Co, Xb, optimize=True)        # sum Co^T Xb
+    Cob = 0.5 * (Cob + Cob.transpose(0, 1, 3, 2))
+    Ccb = 0.5 * (Ccb + Ccb.T)
+    Co6b = Cob.reshape(d, d, chi, Dab, chi, Dab)
+    Gb1, aob = einsum_vjp("leuc,stulnr->stencr", G, ao, Co6b)
+    Ct4b = Ccb.reshape(chi, Dab, chi, Dab).transpose(0, 2, 1, 3)
+    Gb2, ab = einsum_vjp("leuc,ulnr->ecnr", G, a, Ct4b)
+    Tb, ct3b = einsum_vjp("yle,yuc->leuc", T, ct3, Gb1 + Gb2)
+    Cb, Tb2 = einsum_vjp("yx,xuc->yuc", C, T, ct3b)
+    Ab = open_double_layer_backward(A, aob) + double_layer_backward(A, ab)
+    return e2, Cb, Tb + Tb2, Ab
+
+
+def energy_backward(C, T, A, h, h_nnn=None, J2=0.0):
+    """(e, Cbar, Tbar, Abar) of e = 2 <h> (+ 2 J2 <h_nnn>) (observables.energy_j1j2)."""
+    e, Cb, Tb, Ab = energy_nn_backward(C, T, A, h)
+    if h_nnn is not None and J2 != 0.0:
+        e2, Cb2, Tb2, Ab2 = energy_nnn_backward(C, T, A, h_nnn, J2)
+        e, Cb, Tb, Ab = e + e2, Cb + Cb2, Tb + Tb2, Ab + Ab2
+    return e, Cb, Tb, Ab
+
+
 def double_layer_backward(A, abar):
     """a[(u u'),(l l'),(d d'),(r r')] = sum_s A[s,u,l,d,r] A[s,u',l',d',r']."""
     D = A.shape[1]
@@ -172,17 +248,23 @@ def prepare_backward(A_raw, Asbar):
 # ----------------------------------------------------------------------------
 
 
-def energy_k(A_raw, C0, T0, k, h):
+def _energy(C, T, As, h, h_nnn, J2):
+    if h_nnn is not None and J2 != 0.0:
+        return obs.energy_j1j2(C, T, As, h, h_nnn, J2)
+    return obs.energy_nn(C, T, As, h)
+
+
+def energy_k(A_raw, C0, T0, k, h, h_nnn=None, J2=0.0):
     """Forward only: E(A) as defined in the module docstring."""
     As = ctm.prepare_site_tensor(A_raw)
     a = ctm.double_layer(As)
     C, T = C0, T0
     for _ in range(k):
         C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
-    return obs.energy_nn(C, T, As, h)
+    return _energy(C, T, As, h, h_nnn, J2)
 
 
-def energy_grad_k(A_raw, C0, T0, k, h):
+def energy_grad_k(A_raw, C0, T0, k, h, h_nnn=None, J2=0.0):
     """(E, dE/dA_raw) with the k tracked steps reversed from stored (C_i, T_i)."""
     As = ctm.prepare_site_tensor(A_raw)
     a = ctm.double_layer(As)
@@ -191,7 +273,7 @@ def energy_grad_k(A_raw, C0, T0, k, h):
     for _ in range(k):
         C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
         env.append((C, T))
-    e, Cb, Tb, Asb = energy_nn_backward(C, T, As, h)
+    e, Cb, Tb, Asb = energy_backward(C, T, As, h, h_nnn, J2)
     ab = np.zeros_like(a)
     for i in range(k - 1, -1, -1):
         Ci, Ti = env[i]
@@ -206,7 +288,7 @@ def energy_grad_k(A_raw, C0, T0, k, h):
 # ----------------------------------------------------------------------------
 
 
-def energy_grad_fixed_point(A_raw, C, T, h, tol=1e-12, max_iter=2000):
+def energy_grad_fixed_point(A_raw, C, T, h, tol=1e-12, max_iter=2000, h_nnn=None, J2=0.0):
     """(E, dE/dA_raw, n_iter) by differentiating the fixed-point condition.
 
     Discussion paragraph: the fixed-point AD scheme of Liao et al. (2019).
@@ -228,7 +310,7 @@ def energy_grad_fixed_point(A_raw, C, T, h, tol=1e-12, max_iter=2000):
     As = ctm.prepare_site_tensor(A_raw)
     a = ctm.double_layer(As)
     C1, T1 = ctm.sym_norm(*ctm.qr_step(C, T, a))
-    e, Cb, Tb, Asb = energy_nn_backward(C, T, As, h)
+    e, Cb, Tb, Asb = energy_backward(C, T, As, h, h_nnn, J2)
     n0 = np.sqrt(np.sum(Cb * Cb) + np.sum(Tb * Tb))
     ab = np.zeros_like(a)
     n_iter = None

@@ -434,6 +434,66 @@ def test_energy_gradient_matches_finite_differences():
     assert np.abs(ctm.c4v_average(g) - g).max() < 1e-14
 
 
+def test_j1j2_energy_backward_matches_finite_differences():
+    # J1-J2 paragraph: e = 2<h_nn> + 2 J2 <h_nnn>; the hand-written reverse of
+    # the 2x2 plaquette against central differences along random directions of
+    # C, T and A (the energy as a function of an arbitrary environment)
+    rng = np.random.default_rng(11)
+    d, D, chi = 2, 2, 6
+    A = ctm.prepare_site_tensor(inp.random_site_tensor(d, D, 4))
+    C = rng.standard_normal((chi, chi))
+    C = C + C.T + 8 * np.eye(chi)
+    T = rng.standard_normal((chi, D * D, chi))
+    T = T + T.transpose(2, 1, 0)
+    h1, h2, J2 = inp.heisenberg_bond_rotated(), inp.heisenberg_bond(), 0.5
+    e, Cb, Tb, Ab = adj.energy_backward(C, T, A, h1, h2, J2)
+    assert abs(e - obs.energy_j1j2(C, T, A, h1, h2, J2)) < 1e-14 * abs(e)
+    f = lambda Cx, Tx, Ax: obs.energy_j1j2(Cx, Tx, Ax, h1, h2, J2)
+    hh = 1e-6
+    for _ in range(3):
+        dC, dT, dA = (rng.standard_normal(x.shape) for x in (C, T, A))
+        fd = (f(C + hh * dC, T + hh * dT, A + hh * dA)
+              - f(C - hh * dC, T - hh * dT, A - hh * dA)) / (2 * hh)
+        an = np.sum(Cb * dC) + np.sum(Tb * dT) + np.sum(Ab * dA)
+        assert abs(fd - an) < 1e-7 * max(abs(an), 1e-3)
+    # the next-nearest-neighbour part alone, along each argument separately
+    e2, Cb2, Tb2, Ab2 = adj.energy_nnn_backward(C, T, A, h2, J2)
+    g2 = lambda Cx, Tx, Ax: f(Cx, Tx, Ax) - obs.energy_nn(Cx, Tx, Ax, h1)
+    for k, (bar, x) in enumerate(((Cb2, C), (Tb2, T), (Ab2, A))):
+        dx = rng.standard_normal(x.shape)
+        args_p = [C, T, A]
+        args_m = [C, T, A]
+        args_p[k] = x + hh * dx
+        args_m[k] = x - hh * dx
+        fd = (g2(*args_p) - g2(*args_m)) / (2 * hh)
+        assert abs(fd - np.sum(bar * dx)) < 1e-7 * max(abs(fd), 1e-3), k
+
+
+def test_j1j2_energy_gradient_through_tracked_steps_matches_finite_differences():
+    d, D, chi, k = 2, 2, 8, 2
+    A = inp.random_site_tensor(d, D, 2)
+    a = ctm.double_layer(ctm.prepare_site_tensor(A))
+    C, T = ctm.warmup_env(a, chi, ctm.identity_boundary_vector(D))
+    for _ in range(6):
+        C, T = ctm.sym_norm(*ctm.qr_step(C, T, a))
+    h1, h2, J2 = inp.heisenberg_bond_rotated(), inp.heisenberg_bond(), 0.5
+    e, g = adj.energy_grad_k(A, C, T, k, h1, h2, J2)
+    idx = inp.fd_entries(d, D, 2, n=10)
+    fd = []
+    for i in idx:
+        Ap = A.ravel().copy()
+        Am = A.ravel().copy()
+        Ap[i] += 1e-6
+        Am[i] -= 1e-6
+        fd.append((adj.energy_k(Ap.reshape(A.shape), C, T, k, h1, h2, J2)
+                   - adj.energy_k(Am.reshape(A.shape), C, T, k, h1, h2, J2)) / 2e-6)
+    fd = np.array(fd)
+    ga = g.ravel()[idx]
+    assert np.linalg.norm(fd - ga) / np.linalg.norm(ga) < 1e-6
+    assert abs(np.sum(g * A)) < 1e-10 * np.linalg.norm(g) * np.linalg.norm(A)
+    assert np.abs(ctm.c4v_average(g) - g).max() < 1e-14
+
+
 def _converged_pair_env(a, chi, D, tol):
     """Environment converged under G = F o F (F one QR step + sym_norm) to max |change| < tol."""
     r = ctm.ctmrg(a, chi, ctm.identity_boundary_vector(D), tol=1e-14, max_steps=3000)
