@@ -66,9 +66,13 @@ typedef struct ctm_opts {
     int precision;      /* CTM_PREC_*; QR, normalisation and the spectrum stay FP64 */
     int n_warmup;       /* standard (eigh) warm-up steps; -1 = as many as needed for
                            chi to reach its target (QR-CTMRG paragraph: 1-4 steps) */
-    int k_tracked;      /* tracked QR steps in ctm_energy_grad (AD paragraph)       */
+    int k_tracked;      /* tracked QR steps in ctm_energy_grad (AD paragraph); -1 =
+                           the per-D choice of the paper's timing study (Fig. 3
+                           caption): 10, 12, 14, 16, 20, 24 for D = 2..7, 28 for
+                           D >= 8 (not given there), 10 for D = 1                   */
     double qr_sing_tol; /* ctm_energy_grad fails with CTM_ESINGULAR when
-                           min|R_ii| / max|R_ii| of a tracked step is below this    */
+                           min|R_ii| / max|R_ii| of a tracked step is below this
+                           (unless qr_reg_eps > 0)                                  */
     double mixed_tol;   /* mixed precisions only: ctm_converge takes mixed steps until
                            the spectrum change is below max(tol, mixed_tol), then FP64
                            steps until it is below tol, so the converged environment is
@@ -90,17 +94,23 @@ typedef struct ctm_opts {
                            3b outputs, chi^2 D^4 doubles each) instead of recomputing
                            them in the reverse sweep: 2 max(k_tracked, 2) chi^2 D^4
                            doubles more workspace, the same result.  0: recompute.    */
+    double qr_reg_eps;  /* QR adjoint: 0 = the exact R^{-1}; > 0 = a Tikhonov-regularised
+                           one, each division by R_ii in the back substitution
+                           replaced by a product with R_ii / (R_ii^2 + eps^2),
+                           eps = qr_reg_eps * max|R_ii|, so that a rank-deficient
+                           reduced corner gives a finite (regularised) gradient
+                           instead of CTM_ESINGULAR                                   */
 } ctm_opts;
 
-/* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = 10, qr_sing_tol = 1e-14,
-   mixed_tol = 1e-6, edge_split = 1, grad_mode = CTM_GRAD_CHECKPOINT, fp_tol = 1e-10,
-   fp_max_iter = 1000, grad_keep_yz = 0. */
+/* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = -1 (per D), qr_sing_tol =
+   1e-14, mixed_tol = 1e-6, edge_split = 1, grad_mode = CTM_GRAD_CHECKPOINT, fp_tol =
+   1e-10, fp_max_iter = 1000, grad_keep_yz = 0, qr_reg_eps = 0. */
 void ctm_default_opts(ctm_opts* o);
 
 /*
  * Workspace sizes in bytes for a context built by ctm_init (site tensor, d, D,
  * target chi) or by ctm_init_dl (double-layer / classical tensor of bond Dab).
- * opts may be NULL (defaults).  Returns 0 for invalid sizes.
+ * opts may be NULL (defaults).  Returns 0 for invalid sizes or options.
  */
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts);
 size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts);
@@ -180,7 +190,10 @@ int ctm_energy(ctm_ctx* ctx, const double* h_nn, const double* h_nnn, double J2,
  * ctm_energy_grad: E and dE/dA (AD paragraph).  dA is a device array of d*D^4
  * entries, the gradient with respect to the raw A given to ctm_init /
  * ctm_set_tensor; E is a host output.  The environment is left unchanged.
- * h_nnn must be NULL (nearest-neighbour models).  Two schemes (opts.grad_mode):
+ * h_nn, h_nnn, J2 as in ctm_energy: with h_nnn (J1-J2 paragraph) the
+ * plaquette term and its reverse are included (d <= 4; chi >= D^2; four open
+ * enlarged corners of (chi D^2)^2 doubles in the workspace's energy part).
+ * Two schemes (opts.grad_mode):
  *   CTM_GRAD_CHECKPOINT: starting from the current environment, held fixed,
  *     run opts.k_tracked QR steps, evaluate E, and reverse the whole
  *     computation by hand-written adjoints (contraction adjoints, the thin-QR

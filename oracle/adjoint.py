@@ -38,9 +38,25 @@ def copyltu(M: np.ndarray) -> np.ndarray:
     return np.tril(M) + np.tril(M, -1).T
 
 
-def qr_backward(Q, R, Qbar, Rbar):
+def regularized_inverse(R, eps_rel):
+    """Inverse of the upper-triangular R by back substitution in which each
+    division by R_ii becomes a product with d_i = R_ii / (R_ii^2 + eps^2),
+    eps = eps_rel max|R_ii| (Tikhonov form of 1/R_ii).  With N the strictly
+    upper part of R and Dl = diag(d), the substitution R x = e_j reads
+    x = Dl (e_j - N x), so the result is (I + Dl N)^{-1} Dl; eps_rel = 0 gives
+    R^{-1}."""
+    r = np.diag(R)
+    eps = eps_rel * np.abs(r).max()
+    dl = np.diag(r / (r * r + eps * eps))
+    n = R.shape[0]
+    return np.linalg.solve(np.eye(n) + dl @ np.triu(R, 1), dl)
+
+
+def qr_backward(Q, R, Qbar, Rbar, eps_rel=0.0):
     M = R @ Rbar.T - Qbar.T @ Q
     B = Qbar + Q @ copyltu(M)
+    if eps_rel > 0.0:
+        return B @ regularized_inverse(R, eps_rel).T
     # B R^{-T}: solve R X^T = B^T
     return np.linalg.solve(R, B.T).T
 
@@ -70,9 +86,9 @@ def sym_norm_backward(Cp, Tp, Cbar, Tbar):
 # ----------------------------------------------------------------------------
 
 
-def qr_step_backward(C, T, a, Cnbar, Tnbar):
+def qr_step_backward(C, T, a, Cnbar, Tnbar, eps_rel=0.0):
     """Given the step's inputs and cotangents of its normalised outputs,
-    return (Cbar, Tbar, abar)."""
+    return (Cbar, Tbar, abar); eps_rel > 0 regularises R^{-1} of the QR adjoint."""
     chi, Dab, _ = T.shape
     p = ctm.qr_step_parts(C, T, a)
     Q, R, Y, Z, Tp, Cp = p["Q"], p["R"], p["Y"], p["Z"], p["Tp"], p["Cp"]
@@ -97,7 +113,7 @@ def qr_step_backward(C, T, a, Cnbar, Tnbar):
     Q3b = Q3b + Q3b3
 
     # a6: QR
-    ctb = qr_backward(Q, R, Q3b.reshape(chi * Dab, chin), Rb)
+    ctb = qr_backward(Q, R, Q3b.reshape(chi * Dab, chin), Rb, eps_rel)
 
     # a5: ct = C . T (as chi x (Dab chi))
     ctb2 = ctb.reshape(C.shape[0], Dab * T.shape[2])
@@ -264,8 +280,9 @@ def energy_k(A_raw, C0, T0, k, h, h_nnn=None, J2=0.0):
     return _energy(C, T, As, h, h_nnn, J2)
 
 
-def energy_grad_k(A_raw, C0, T0, k, h, h_nnn=None, J2=0.0):
-    """(E, dE/dA_raw) with the k tracked steps reversed from stored (C_i, T_i)."""
+def energy_grad_k(A_raw, C0, T0, k, h, h_nnn=None, J2=0.0, qr_reg_eps=0.0):
+    """(E, dE/dA_raw) with the k tracked steps reversed from stored (C_i, T_i);
+    qr_reg_eps > 0 uses the regularised R^{-1} in every QR adjoint."""
     As = ctm.prepare_site_tensor(A_raw)
     a = ctm.double_layer(As)
     env = [(C0, T0)]
@@ -277,7 +294,7 @@ def energy_grad_k(A_raw, C0, T0, k, h, h_nnn=None, J2=0.0):
     ab = np.zeros_like(a)
     for i in range(k - 1, -1, -1):
         Ci, Ti = env[i]
-        Cb, Tb, abi = qr_step_backward(Ci, Ti, a, Cb, Tb)
+        Cb, Tb, abi = qr_step_backward(Ci, Ti, a, Cb, Tb, qr_reg_eps)
         ab += abi
     Asb = Asb + double_layer_backward(As, ab)
     return e, prepare_backward(A_raw, Asb)

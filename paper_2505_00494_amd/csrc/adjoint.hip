@@ -102,15 +102,40 @@ __global__ void copyltu_kernel(const double* __restrict__ M, int n, double* Ms) 
     }
 }
 
+// x / R_ii, or x dinv[i] for the regularised inverse
+__device__ __forceinline__ double div_diag(double x, double rii, const double* dinv, int i) {
+    return dinv ? x * dinv[i] : x / rii;
+}
+
 // column j of R^{-1}: back substitution R x = e_j, x_i = 0 for i > j
-__global__ void tri_inv_upper_kernel(const double* __restrict__ R, int n, double* Ri) {
+__global__ void tri_inv_upper_kernel(const double* __restrict__ R, int n, double* Ri,
+                                     const double* __restrict__ dinv) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     for (int i = n - 1; i > j; --i) Ri[(size_t)i * n + j] = 0.0;
     for (int i = j; i >= 0; --i) {
         double acc = (i == j) ? 1.0 : 0.0;
         for (int k = i + 1; k <= j; ++k) acc -= R[(size_t)i * n + k] * Ri[(size_t)k * n + j];
-        Ri[(size_t)i * n + j] = acc / R[(size_t)i * n + i];
+        Ri[(size_t)i * n + j] = div_diag(acc, R[(size_t)i * n + i], dinv, i);
+    }
+}
+
+// Tikhonov-regularised reciprocals of R's diagonal (one workgroup)
+__global__ __launch_bounds__(256) void reg_recip_diag_kernel(const double* __restrict__ R, int n,
+                                                             double eps_rel, double* dinv) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(R[(size_t)i * n + i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double eps = eps_rel * red[0];
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double r = R[(size_t)i * n + i];
+        dinv[i] = r / (r * r + eps * eps);
     }
 }
 
@@ -122,7 +147,8 @@ constexpr int kTriThreads = 256;
 constexpr int kTriMaxLds = 150 * 1024;
 
 __global__ __launch_bounds__(kTriThreads) void tri_inv_col_kernel(const double* __restrict__ R,
-                                                                  int n, double* Ri) {
+                                                                  int n, double* Ri,
+                                                                  const double* __restrict__ dinv) {
     extern __shared__ double tri[];
     double* x = tri + (size_t)n * (n + 1) / 2;
     const int j = blockIdx.x, k = threadIdx.x;
@@ -133,7 +159,7 @@ __global__ __launch_bounds__(kTriThreads) void tri_inv_col_kernel(const double* 
     double b = (k == j) ? 1.0 : 0.0;
     __syncthreads();
     for (int i = j; i >= 0; --i) {
-        if (k == i) x[i] = b / tri[(size_t)i * n - (size_t)i * (i - 1) / 2];
+        if (k == i) x[i] = div_diag(b, tri[(size_t)i * n - (size_t)i * (i - 1) / 2], dinv, i);
         __syncthreads();
         if (k < i) b -= tri[(size_t)k * n - (size_t)k * (k - 1) / 2 + (i - k)] * x[i];
     }
@@ -155,7 +181,8 @@ __global__ void transpose_kernel(const double* __restrict__ R, int n, double* __
 // k owns entries k, k + 256, ...), x_i is handed over through a double buffer,
 // so one barrier per step suffices.  n <= 1024.
 __global__ __launch_bounds__(kTriThreads) void tri_inv_col_l2_kernel(const double* __restrict__ Rt,
-                                                                     int n, double* Ri) {
+                                                                     int n, double* Ri,
+                                                                     const double* __restrict__ dinv) {
     __shared__ double bs[1024];
     __shared__ double xs[2];
     const int j = blockIdx.x, t = threadIdx.x;
@@ -173,7 +200,7 @@ __global__ __launch_bounds__(kTriThreads) void tri_inv_col_l2_kernel(const doubl
     __syncthreads();
     for (int i = j; i >= 0; --i) {
         if (t == i % kTriThreads) {
-            const double x = bs[i] / Rt[(size_t)i * n + i];
+            const double x = div_diag(bs[i], Rt[(size_t)i * n + i], dinv, i);
             xs[i & 1] = x;
             Ri[(size_t)i * n + j] = x;
         }
@@ -224,6 +251,38 @@ __global__ void dl_backward_kernel(const double* __restrict__ abar, const double
         }
         Asb[e] += acc;
     }
+}
+
+// Reverse of a_open[(u u'),(l l'),(r r'),(d d')] = As[s,u,l,d,r] As[t,u',l',d',r']
+// (ket s, bra t; a_int layout): bra = 0 adds sum over the bra indices of
+// aob * As[t] to Asb[s] (the ket factor's cotangent), bra = 1 adds sum over
+// the ket indices of aob * As[s] to Asb[t].
+__global__ void open_layer_bw_kernel(const double* __restrict__ aob, const double* __restrict__ As,
+                                     int D, int s, int t, int bra, double* Asb) {
+    const int D4 = D * D * D * D, D2 = D * D;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D4) return;
+    int rem = e;
+    const int r = rem % D; rem /= D;
+    const int dn = rem % D; rem /= D;
+    const int l = rem % D; rem /= D;
+    const int u = rem;
+    const double* other = As + (size_t)(bra ? s : t) * D4;
+    double acc = 0.0;
+    for (int q = 0; q < D4; ++q) {
+        int w = q;
+        const int r2 = w % D; w /= D;
+        const int d2 = w % D; w /= D;
+        const int l2 = w % D; w /= D;
+        const int u2 = w;
+        // (this element, the other factor's element q) in ket-bra order
+        const int U = bra ? u2 * D + u : u * D + u2;
+        const int L = bra ? l2 * D + l : l * D + l2;
+        const int R = bra ? r2 * D + r : r * D + r2;
+        const int Dn = bra ? d2 * D + dn : dn * D + d2;
+        acc += aob[(((size_t)U * D2 + L) * D2 + R) * D2 + Dn] * other[q];
+    }
+    Asb[(size_t)(bra ? t : s) * D4 + e] += acc;
 }
 
 __device__ __forceinline__ int c4v_pos(int g, int i) {
@@ -353,22 +412,30 @@ Status copyltu(const double* M, int n, double* Ms, hipStream_t st) {
     return launch_check("copyltu_kernel");
 }
 
-Status tri_inv_upper(const double* R, int n, double* Ri, double* scratch, hipStream_t st) {
+Status reg_recip_diag(const double* R, int n, double eps_rel, double* dinv, hipStream_t st) {
+    hipLaunchKernelGGL(reg_recip_diag_kernel, dim3(1), dim3(256), 0, st, R, n, eps_rel, dinv);
+    return launch_check("reg_recip_diag_kernel");
+}
+
+Status tri_inv_upper(const double* R, int n, double* Ri, double* scratch, hipStream_t st,
+                     const double* dinv) {
     const size_t lds = sizeof(double) * ((size_t)n * (n + 1) / 2 + (size_t)n);
     if (n <= kTriThreads && lds <= (size_t)kTriMaxLds) {
         QRCTM_HIP(hipFuncSetAttribute((const void*)tri_inv_col_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(tri_inv_col_kernel, dim3(n), dim3(kTriThreads), lds, st, R, n, Ri);
+        hipLaunchKernelGGL(tri_inv_col_kernel, dim3(n), dim3(kTriThreads), lds, st, R, n, Ri, dinv);
         return launch_check("tri_inv_col_kernel");
     }
     if (scratch != nullptr && n <= 1024) {
         const int nb = (int)ceil_div(n, 16);
         hipLaunchKernelGGL(transpose_kernel, dim3(nb, nb), dim3(16, 16), 0, st, R, n, scratch);
         QRCTM_TRY(launch_check("transpose_kernel"));
-        hipLaunchKernelGGL(tri_inv_col_l2_kernel, dim3(n), dim3(kTriThreads), 0, st, scratch, n, Ri);
+        hipLaunchKernelGGL(tri_inv_col_l2_kernel, dim3(n), dim3(kTriThreads), 0, st, scratch, n, Ri,
+                           dinv);
         return launch_check("tri_inv_col_l2_kernel");
     }
-    hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, R, n, Ri);
+    hipLaunchKernelGGL(tri_inv_upper_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, R, n, Ri,
+                       dinv);
     return launch_check("tri_inv_upper_kernel");
 }
 
@@ -378,6 +445,17 @@ Status double_layer_backward(const double* abar, const double* As, int d, int D,
     hipLaunchKernelGGL(dl_backward_kernel, dim3((int)ceil_div(n, 64)), dim3(64), 0, st, abar, As, d,
                        D, Asb);
     return launch_check("dl_backward_kernel");
+}
+
+Status open_layer_backward(const double* aob, const double* As, int D, int s, int t, double* Asb,
+                           hipStream_t st) {
+    const int D4 = D * D * D * D;
+    for (int bra = 0; bra < 2; ++bra) {
+        hipLaunchKernelGGL(open_layer_bw_kernel, dim3((int)ceil_div(D4, 64)), dim3(64), 0, st, aob, As,
+                           D, s, t, bra, Asb);
+        QRCTM_TRY(launch_check("open_layer_bw_kernel"));
+    }
+    return Status{};
 }
 
 Status c4v_backward(const double* Asb, const double* As, const double* scale, const int* imax,

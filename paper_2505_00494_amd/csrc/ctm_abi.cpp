@@ -140,7 +140,7 @@ GemmDesc bw_gemm(int id, const BwPtrs& p, int chi, int Dab) {
 
 struct GradLayout {
     size_t ckC, ckT, Cb, Tb, Cb2, Tb2, Ctmp, Ttmp, Cpb, Tpb, Wb, Rb, Qb, Zg, Mm, Ms, Rinv, ctb, abar,
-        Asb, part, ratio, splitk, bwpart;
+        Asb, part, ratio, dinv, splitk, bwpart;
     // per reversed step: the forward step's Q, R, T', W and its two norms, kept
     // so that the reverse sweep recomputes only Y and Z (3a, 3b); with
     // grad_keep_yz, Y and Z too (sY, sZ, else empty)
@@ -192,6 +192,7 @@ GradLayout grad_layout(const Shape& sh, int k, bool split_bw, bool keep_yz) {
     L.Asb = take((size_t)sh.d * sh.D * sh.D * sh.D * sh.D);
     L.part = take(sym_norm_backward_scratch_bytes() / sizeof(double) + 1);
     L.ratio = take(8);
+    L.dinv = take(c);
     BwPtrs p{};
     size_t sk = 0;
     for (int cc = 1; cc <= sh.chi; ++cc)
@@ -416,6 +417,24 @@ Status clear_bad(ctm_ctx* c) {
     return hip_status(hipMemsetAsync(c->bad(), 0, sizeof(int), c->st), "hipMemsetAsync");
 }
 
+// The device error word, read after the stream's work: bit 2 (an exchange of
+// the QR's workgroups timed out; its results are zeros) is a runtime error,
+// bit 1 (a non-finite or zero tensor where a norm was taken) a numerical one.
+Status check_bad(ctm_ctx* c, const char* where) {
+    int h = 0;
+    QRCTM_HIP(hipMemcpyAsync(&h, c->bad(), sizeof(int), hipMemcpyDeviceToHost, c->st));
+    QRCTM_TRY(sync(c->st));
+    Status s;
+    if (h & 2) {
+        s.code = CTM_EHIP;
+        s.msg = std::string(where) + ": an exchange between the QR's workgroups timed out";
+    } else if (h & 1) {
+        s.code = CTM_ENONFINITE;
+        s.msg = std::string(where) + ": non-finite or zero environment";
+    }
+    return s;
+}
+
 // One renormalisation of (C, T) with isometry Q (chi*Dab x chio) into Tp, W, Cp.
 Status renormalise_edge(ctm_ctx* c, const StepPtrs& p, const double* Q, int chi, int chio) {
     const int Dab = c->sh.Dab;
@@ -609,7 +628,7 @@ Status eigh_step_once(ctm_ctx* c) {
 
 struct GradPtrs {
     double *ckC, *ckT, *Cb, *Tb, *Cb2, *Tb2, *Ctmp, *Ttmp, *Cpb, *Tpb, *Wb, *Rb, *Qb, *Zg, *Mm, *Ms,
-        *Rinv, *ctb, *abar, *Asb, *part, *ratio, *bwpart, *sQ, *sR, *sTp, *sW, *sN;
+        *Rinv, *ctb, *abar, *Asb, *part, *ratio, *dinv, *bwpart, *sQ, *sR, *sTp, *sW, *sN;
     double *sY = nullptr, *sZ = nullptr;  // kept Y and Z per step (grad_keep_yz)
     void* splitk;
     size_t splitk_bytes, bwpart_doubles;
@@ -626,6 +645,7 @@ GradPtrs grad_ptrs(ctm_ctx* c) {
     g.Wb = P(L.Wb); g.Rb = P(L.Rb); g.Qb = P(L.Qb); g.Zg = P(L.Zg); g.Mm = P(L.Mm); g.Ms = P(L.Ms);
     g.Rinv = P(L.Rinv); g.ctb = P(L.ctb); g.abar = P(L.abar); g.Asb = P(L.Asb); g.part = P(L.part);
     g.ratio = P(L.ratio);
+    g.dinv = P(L.dinv);
     g.splitk = b + L.splitk;
     g.splitk_bytes = L.splitk_bytes;
     g.bwpart = P(L.bwpart);
@@ -708,7 +728,14 @@ Status qr_step_backward(ctm_ctx* c, const GradPtrs& g, int i, const double* Ci, 
     QRCTM_TRY(run(11));
     QRCTM_TRY(copyltu(g.Mm, chi, g.Ms, c->st));
     QRCTM_TRY(run(12));                                    // Qbar + Q copyltu(M)
-    QRCTM_TRY(tri_inv_upper(p.R, chi, g.Rinv, g.Mm, c->st));  // M is dead once Ms holds copyltu(M)
+    // R^{-1}, or its regularised form (opts.qr_reg_eps > 0; M is dead once Ms
+    // holds copyltu(M))
+    double* dinv = nullptr;
+    if (c->opts.qr_reg_eps > 0.0) {
+        QRCTM_TRY(reg_recip_diag(p.R, chi, c->opts.qr_reg_eps, g.dinv, c->st));
+        dinv = g.dinv;
+    }
+    QRCTM_TRY(tri_inv_upper(p.R, chi, g.Rinv, g.Mm, c->st, dinv));
     QRCTM_TRY(run(13));                                    // ... R^{-T}
     QRCTM_TRY(run(14));                                    // a5
     QRCTM_TRY(run(15));
@@ -721,8 +748,10 @@ __global__ void zero_kernel(double* x, long long n) {
         x[e] = 0.0;
 }
 
-Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, bool* series_done) {
+Status energy_grad_impl(ctm_ctx* c, const double* h_nn, const double* h_nnn, double J2, double* E,
+                        double* dA, bool* series_done) {
     QRCTM_TRY(join_aux(c));
+    QRCTM_TRY(clear_bad(c));
     const bool fixed_point = c->opts.grad_mode == CTM_GRAD_FIXED_POINT;
     const int k = c->opts.k_tracked;
     const int chi = c->chi_cur, Dab = c->sh.Dab;
@@ -760,9 +789,13 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
     EnergyArgs ea{};
     ea.d = c->sh.d; ea.D = c->sh.D; ea.chi = chi;
     ea.C = g.ckC + ke * nC; ea.T = g.ckT + ke * nT; ea.As = c->ptr(c->plan.As);
+    // the plaquette term (h_nnn) builds enlarged corners in the step buffers,
+    // which hold nothing between the forward sweep and the reverse one
+    ea.a = c->ptr(c->plan.a);
+    ea.Qbuf = c->ptr(c->plan.Q); ea.Ybuf = c->ptr(c->plan.Y); ea.Zbuf = c->ptr(c->plan.Z);
     ea.ws = c->ptr<char>(c->plan.energy); ea.ws_bytes = c->plan.energy_bytes;
     ea.splitk = nullptr; ea.splitk_bytes = 0;
-    QRCTM_TRY(energy_grad_eval(ea, h_nn, E, g.Cb, g.Tb, g.Asb, c->st));
+    QRCTM_TRY(energy_grad_eval(ea, h_nn, h_nnn, J2, E, g.Cb, g.Tb, g.Asb, c->st));
     const long long na = (long long)Dab * Dab * Dab * Dab;
     hipLaunchKernelGGL(zero_kernel, dim3((int)std::min<long long>(ceil_div(na, 256), 4096)), dim3(256),
                        0, c->st, g.abar, na);
@@ -823,8 +856,8 @@ Status energy_grad_impl(ctm_ctx* c, const double* h_nn, double* E, double* dA, b
     double ratio = 1.0;
     if (nfwd > 0)
         QRCTM_HIP(hipMemcpyAsync(&ratio, g.ratio, sizeof(double), hipMemcpyDeviceToHost, c->st));
-    QRCTM_TRY(sync(c->st));
-    if (nfwd > 0 && !(ratio >= c->opts.qr_sing_tol)) {
+    QRCTM_TRY(check_bad(c, "ctm_energy_grad"));
+    if (nfwd > 0 && c->opts.qr_reg_eps == 0.0 && !(ratio >= c->opts.qr_sing_tol)) {
         Status s;
         s.code = CTM_ESINGULAR;
         s.msg = "reduced corner numerically rank deficient in a tracked step (min|R_ii|/max|R_ii| = " +
@@ -882,9 +915,24 @@ Status start_environment(ctm_ctx* c) {
 bool valid_opts(const ctm_opts& o) {
     return (o.precision == CTM_PREC_FP64 || o.precision == CTM_PREC_FP32_MFMA ||
             o.precision == CTM_PREC_BF16X6_MFMA) &&
-           o.k_tracked >= 0 && (o.edge_split == 0 || o.edge_split == 1) &&
+           o.k_tracked >= -1 && (o.edge_split == 0 || o.edge_split == 1) &&
            (o.grad_mode == CTM_GRAD_CHECKPOINT || o.grad_mode == CTM_GRAD_FIXED_POINT) &&
-           o.fp_tol > 0.0 && o.fp_max_iter >= 2 && (o.grad_keep_yz == 0 || o.grad_keep_yz == 1);
+           o.fp_tol > 0.0 && o.fp_max_iter >= 2 && (o.grad_keep_yz == 0 || o.grad_keep_yz == 1) &&
+           o.qr_reg_eps >= 0.0 && std::isfinite(o.qr_reg_eps);
+}
+
+// Tracked steps per bond dimension when opts.k_tracked = -1: the paper's timing
+// study (Fig. 3 caption) uses 10, 12, 14, 16, 20, 24 for D = 2..7; D = 8 is not
+// listed there and continues the step of 4 (28), which also covers larger D.
+int default_k_tracked(int D) {
+    static const int k[] = {10, 10, 10, 12, 14, 16, 20, 24, 28};
+    return D < 1 ? 10 : (D <= 8 ? k[D] : 28);
+}
+
+ctm_opts resolved(const Shape& sh, const ctm_opts& in) {
+    ctm_opts o = in;
+    if (o.k_tracked < 0) o.k_tracked = default_k_tracked(sh.quantum ? sh.D : 0);
+    return o;
 }
 
 int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_t ws_bytes,
@@ -895,6 +943,7 @@ int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_
     ctm_default_opts(&o);
     if (opts) o = *opts;
     if (!valid_opts(o)) return fail(nullptr, CTM_EINVAL, "invalid ctm_opts");
+    o = resolved(sh, o);
     if (sh.chi < 1 || sh.chi > 1024 || sh.Dab < 1)
         return fail(nullptr, CTM_EINVAL, "chi must be in [1, 1024] and Dab >= 1");
     if (sh.chi < sh.Dab)
@@ -957,7 +1006,7 @@ void ctm_default_opts(ctm_opts* o) {
     if (!o) return;
     o->precision = CTM_PREC_FP64;
     o->n_warmup = -1;
-    o->k_tracked = 10;
+    o->k_tracked = -1;
     o->qr_sing_tol = 1e-14;
     o->mixed_tol = 1e-6;
     o->edge_split = 1;
@@ -965,6 +1014,7 @@ void ctm_default_opts(ctm_opts* o) {
     o->fp_tol = 1e-10;
     o->fp_max_iter = 1000;
     o->grad_keep_yz = 0;
+    o->qr_reg_eps = 0.0;
 }
 
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
@@ -972,8 +1022,9 @@ size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
     ctm_opts o;
     ctm_default_opts(&o);
     if (opts) o = *opts;
+    if (!valid_opts(o)) return 0;
     Shape sh{d, D, D * D, chi, true};
-    return plan_workspace(sh, o).total;
+    return plan_workspace(sh, resolved(sh, o)).total;
 }
 
 size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts) {
@@ -981,8 +1032,9 @@ size_t ctm_workspace_bytes_dl(int Dab, int chi, const ctm_opts* opts) {
     ctm_opts o;
     ctm_default_opts(&o);
     if (opts) o = *opts;
+    if (!valid_opts(o)) return 0;
     Shape sh{0, 0, Dab, chi, false};
-    return plan_workspace(sh, o).total;
+    return plan_workspace(sh, resolved(sh, o)).total;
 }
 
 int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_opts* opts, void* ws,
@@ -1078,12 +1130,11 @@ int ctm_step(ctm_ctx* c, int nsteps, double* delta) {
         } else {
             h[0] = c->last_delta;
         }
-        bool bad = false;
-        QRCTM_TRY(read_bad(c, &bad));
         c->last_delta = h[0];
         if (delta) *delta = h[0];
+        QRCTM_TRY(check_bad(c, "ctm_step"));
         // nsteps = 0 reports the last step's change (NaN before the first step)
-        if (bad || (nsteps > 0 && !std::isfinite(h[0]))) {
+        if (nsteps > 0 && !std::isfinite(h[0])) {
             Status s;
             s.code = CTM_ENONFINITE;
             s.msg = "non-finite environment in ctm_step";
@@ -1147,10 +1198,9 @@ int ctm_converge(ctm_ctx* c, double tol, int max_steps, int* steps, double* delt
         } else {
             QRCTM_TRY(run(tol, max_steps));
         }
-        bool bad = false;
-        QRCTM_TRY(read_bad(c, &bad));
         c->last_delta = dl;
-        if (bad || !std::isfinite(dl)) {
+        QRCTM_TRY(check_bad(c, "ctm_converge"));
+        if (!std::isfinite(dl)) {
             Status s;
             s.code = CTM_ENONFINITE;
             s.msg = "non-finite environment in ctm_converge";
@@ -1220,10 +1270,10 @@ int ctm_energy_grad(ctm_ctx* c, const double* h_nn, const double* h_nnn, double 
                     double* dA) {
     if (!c || !h_nn || !E || !dA) return fail(c, CTM_EINVAL, "NULL argument");
     if (!c->sh.quantum) return fail(c, CTM_ESTATE, "gradient needs a site tensor (ctm_init)");
-    if (h_nnn != nullptr && J2 != 0.0)
-        return fail(c, CTM_EINVAL, "ctm_energy_grad supports nearest-neighbour models (h_nnn = NULL)");
     bool series_done = true;
-    const int rc = guarded(c, [&]() -> Status { return energy_grad_impl(c, h_nn, E, dA, &series_done); });
+    const int rc = guarded(c, [&]() -> Status {
+        return energy_grad_impl(c, h_nn, h_nnn, J2, E, dA, &series_done);
+    });
     return (rc == CTM_OK && !series_done) ? CTM_NOTCONV : rc;
 }
 

@@ -20,9 +20,10 @@ Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn
                    double* E, hipStream_t st);
 
 // E (host) and its cotangents with respect to C, T (device, chi x chi and
-// chi x Dab x chi, overwritten) and As (device, d D^4, overwritten).
-Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, double* E, double* Cb,
-                        double* Tb, double* Asb, hipStream_t st);
+// chi x Dab x chi, overwritten) and As (device, d D^4, overwritten); h_nnn
+// (nullable) with J2 adds the plaquette term, which needs a, Qbuf, Ybuf, Zbuf.
+Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
+                        double* E, double* Cb, double* Tb, double* Asb, hipStream_t st);
 
 struct ClassicalArgs {
     int Dab, chi;

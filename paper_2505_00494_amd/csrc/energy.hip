@@ -18,6 +18,7 @@
 //
 // Classical (Discussion paragraph: classical partition functions): ln kappa =
 // ln Z33 + ln Z22 - 2 ln Z32 and <O> = Z33(impurity) / Z33(a).
+#include "adjoint.h"
 #include "common.h"
 #include "energy.h"
 #include "step_gemms.h"
@@ -142,7 +143,7 @@ __global__ void bond_energy_kernel(const double* __restrict__ rho, const double*
 
 struct ELayout {
     size_t E1, F, E2, Yb, E3, E4, E4p, Left, Lp, Ak, rho, h, scal;
-    size_t Lpb, Leftb, E1b, Fb, Akb, rhob, rho2, red;
+    size_t Lpb, Leftb, E1b, Fb, Akb, rhob, rho2, rhob2, red;
     size_t splitk, total;
     size_t splitk_bytes;
 };
@@ -176,6 +177,7 @@ ELayout e_layout(int d, int D, int chi) {
     L.Akb = take(dd * D4);
     L.rhob = take(dd * dd * dd * dd);
     L.rho2 = take(dd * dd * dd * dd);
+    L.rhob2 = take(dd * dd * dd * dd);
     L.red = take(kRedBlocks);
     // split-K partials: the largest over every product of the forward and reverse
     // energy contractions (M, N, K as in nn_rho_forward, energy_grad_eval, nnn_rho)
@@ -211,6 +213,9 @@ ELayout e_layout(int d, int D, int chi) {
         add(q * cc, q * cc, cc);
         add(cc * cc, q * q, q * q);
         add(n, n, n);
+        // its reverse (plaquette cotangents, 3b and 3a reversed)
+        add(q * q, q * q, cc * cc);
+        add(q * cc, cc, cc * q);
     }
     L.splitk_bytes = sk + 256;
     L.splitk = take(L.splitk_bytes / sizeof(double) + 1);
@@ -219,7 +224,8 @@ ELayout e_layout(int d, int D, int chi) {
 }
 
 struct CLayout {
-    size_t F, E1, X1, X2, imp, part, scal, total;
+    size_t F, E1, X1, X2, imp, part, scal, splitk, total;
+    size_t splitk_bytes;
 };
 
 CLayout c_layout(int Dab, int chi) {
@@ -238,23 +244,40 @@ CLayout c_layout(int Dab, int chi) {
     L.imp = take(D * D * D * D);
     L.part = take(kRedBlocks);
     L.scal = take(16);
+    // split-K partials of the products below (left_column, z33, C C)
+    size_t sk = 0;
+    {
+        auto add = [&](long long M, long long N, long long K) {
+            GemmDesc g;
+            g.M = M; g.N = N; g.K = K;
+            sk = std::max(sk, gemm_splitk_bytes(g));
+        };
+        const long long cc = (long long)c, q = (long long)D, q2 = q * q;
+        add(cc, q * cc, cc);
+        add(cc * q, cc, cc);
+        add(q * cc, q * cc, cc);
+        add(cc * cc, q2, q2);
+        add(cc, cc, cc);
+    }
+    L.splitk_bytes = sk + 256;
+    L.splitk = take(L.splitk_bytes / sizeof(double) + 1);
     L.total = off;
     return L;
 }
 
-// E1[q,L,t] = sum C[q,p] T[p,L,r] C[r,t]
+// E1[q,L,t] = sum C[q,p] T[p,L,r] C[r,t]; sk: split-K scratch of skb bytes
 Status left_column(const double* C, const double* T, int chi, int Dab, double* F, double* E1,
-                   hipStream_t st) {
+                   void* sk, size_t skb, hipStream_t st) {
     GemmDesc g;
     g.M = chi; g.N = (long long)Dab * chi; g.K = chi;
     g.A = C; g.lda = chi; g.B = T; g.ldb = (long long)Dab * chi;
     g.C = F; g.map = OutMap::plain(g.M, g.N, g.N);
-    QRCTM_TRY(gemm_f64(g, nullptr, 0, st));
+    QRCTM_TRY(gemm_f64(g, sk, skb, st));
     GemmDesc h;
     h.M = (long long)chi * Dab; h.N = chi; h.K = chi;
     h.A = F; h.lda = chi; h.B = C; h.ldb = chi;
     h.C = E1; h.map = OutMap::plain(h.M, h.N, h.N);
-    return gemm_f64(h, nullptr, 0, st);
+    return gemm_f64(h, sk, skb, st);
 }
 
 // Z33 of the 3x3 network with centre tensor ct (internal layout a[U][L][R][Dn])
@@ -266,6 +289,8 @@ Status z33(const ClassicalArgs& ca, const CLayout& L, const double* ct, double* 
     double* E1 = reinterpret_cast<double*>(b + L.E1);
     double* X1 = reinterpret_cast<double*>(b + L.X1);
     double* X2 = reinterpret_cast<double*>(b + L.X2);
+    void* sk = b + L.splitk;
+    const size_t skb = L.splitk_bytes;
     // X1[w][t][U][L] = sum_q T[q,U,w] E1[q,L,t]
     GemmDesc g;
     g.trans_a = 1;
@@ -273,13 +298,13 @@ Status z33(const ClassicalArgs& ca, const CLayout& L, const double* ct, double* 
     g.A = ca.T; g.lda = (long long)Dab * chi; g.B = E1; g.ldb = (long long)Dab * chi;
     g.C = X1;
     g.map = OutMap{chi, Dab, (long long)chi * D2, chi, 1, D2};
-    QRCTM_TRY(gemm_f64(g, nullptr, 0, st));
+    QRCTM_TRY(gemm_f64(g, sk, skb, st));
     // X2[w][t][R][Dn] = X1[(w,t),(U,L)] ct[(U,L),(R,Dn)]
     GemmDesc h;
     h.M = (long long)chi * chi; h.N = D2; h.K = D2;
     h.A = X1; h.lda = D2; h.B = ct; h.ldb = D2;
     h.C = X2; h.map = OutMap::plain(h.M, h.N, h.N);
-    QRCTM_TRY(gemm_f64(h, nullptr, 0, st));
+    QRCTM_TRY(gemm_f64(h, sk, skb, st));
     // Y3[w][t][R][Dn] = sum_v E1[w,R,v] T[t,Dn,v]   (into X1)
     GemmDesc k;
     k.trans_b = 1;
@@ -287,7 +312,7 @@ Status z33(const ClassicalArgs& ca, const CLayout& L, const double* ct, double* 
     k.A = E1; k.lda = chi; k.B = ca.T; k.ldb = chi;
     k.C = X1;
     k.map = OutMap{Dab, (long long)chi * D2, Dab, Dab, D2, 1};
-    QRCTM_TRY(gemm_f64(k, nullptr, 0, st));
+    QRCTM_TRY(gemm_f64(k, sk, skb, st));
     return dot(X2, X1, (long long)chi * chi * D2, 0, 1, 0, reinterpret_cast<double*>(b + L.part),
                out, st);
 }
@@ -307,14 +332,14 @@ Status classical_parts(const ClassicalArgs& ca, double* z33v, double* z22v, doub
     double* E1 = reinterpret_cast<double*>(b + L.E1);
     double* part = reinterpret_cast<double*>(b + L.part);
     double* sc = reinterpret_cast<double*>(b + L.scal);
-    QRCTM_TRY(left_column(ca.C, ca.T, chi, Dab, F, E1, st));
+    QRCTM_TRY(left_column(ca.C, ca.T, chi, Dab, F, E1, b + L.splitk, L.splitk_bytes, st));
     if (z32v) QRCTM_TRY(dot(E1, E1, (long long)chi * Dab * chi, 0, 1, 0, part, sc + 0, st));
     if (z22v) {
         GemmDesc g;  // C2 = C C into F
         g.M = chi; g.N = chi; g.K = chi;
         g.A = ca.C; g.lda = chi; g.B = ca.C; g.ldb = chi;
         g.C = F; g.map = OutMap::plain(chi, chi, chi);
-        QRCTM_TRY(gemm_f64(g, nullptr, 0, st));
+        QRCTM_TRY(gemm_f64(g, b + L.splitk, L.splitk_bytes, st));
         QRCTM_TRY(dot(F, F, (long long)chi * chi, chi, chi, 1, part, sc + 1, st));
     }
     const double* ct = ca.a;
@@ -372,7 +397,7 @@ Status nn_rho_forward(const EnergyArgs& ea, const ELayout& L, hipStream_t st) {
     const long long c = chi, DD = D, D2 = (long long)D * D, dd = d;
     void* sk = b + L.splitk;
     const size_t skb = L.splitk_bytes;
-    QRCTM_TRY(left_column(ea.C, ea.T, chi, (int)D2, P(L.F), P(L.E1), st));
+    QRCTM_TRY(left_column(ea.C, ea.T, chi, (int)D2, P(L.F), P(L.E1), sk, skb, st));
     // E2[(U,w),(L,t)] = sum_q T[q,U,w] E1[q,L,t]   ([u][u'][w][l][l'][t])
     QRCTM_TRY(gemm_f64(gd(1, 0, D2 * c, D2 * c, c, ea.T, D2 * c, P(L.E1), D2 * c, P(L.E2),
                           plain(D2 * c, D2 * c)), sk, skb, st));
@@ -412,9 +437,12 @@ Status nn_rho_forward(const EnergyArgs& ea, const ELayout& L, hipStream_t st) {
     return Status{};
 }
 
-// rhob = dE/drho + (dE/drho)^T for E = 2 Tr(rm h)/Tr(rm) (rho layout [(s1 s1'),(s2 s2')])
+// rhob = dE/drho + (dE/drho)^T for E = scale Tr(rm h)/Tr(rm) (rho layout
+// [(s1 s1'),(s2 s2')]); the symmetrised form is what both densities need:
+// rho = Lp Lp^T (nearest neighbours) and rho[q1][q2] = Tr(X_q1 X_q2) (plaquette)
+// are symmetric functions of their two factors.
 __global__ void rho_bar_kernel(const double* __restrict__ rho, const double* __restrict__ h, int d,
-                               double* rhob) {
+                               double scale, double* rhob) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int d2 = d * d;
     double num = 0.0, den = 0.0;
@@ -426,16 +454,15 @@ __global__ void rho_bar_kernel(const double* __restrict__ rho, const double* __r
                     num += r * h[(size_t)(t1 * d + t2) * d2 + (s1 * d + s2)];
                     if (s1 == t1 && s2 == t2) den += r;
                 }
-    const double e = 2.0 * num / den;
+    const double ratio = num / den;
     for (int s1 = 0; s1 < d; ++s1)
         for (int t1 = 0; t1 < d; ++t1)
             for (int s2 = 0; s2 < d; ++s2)
                 for (int t2 = 0; t2 < d; ++t2) {
-                    const double g = (2.0 / den) * (h[(size_t)(t1 * d + t2) * d2 + (s1 * d + s2)] -
-                                                    ((s1 == t1 && s2 == t2) ? 0.5 * e : 0.0));
+                    const double g = (scale / den) * (h[(size_t)(t1 * d + t2) * d2 + (s1 * d + s2)] -
+                                                      ((s1 == t1 && s2 == t2) ? ratio : 0.0));
                     rhob[(size_t)(s1 * d + t1) * d2 + (s2 * d + t2)] = g;
                 }
-    // symmetrise: rho = Lp Lp^T uses Lp on both sides
     for (int i = 0; i < d2; ++i)
         for (int j = i; j < d2; ++j) {
             const double v = rhob[(size_t)i * d2 + j] + rhob[(size_t)j * d2 + i];
@@ -467,6 +494,49 @@ __global__ void sym_square_kernel(const double* __restrict__ Z, long long n, dou
          e += (long long)gridDim.x * blockDim.x) {
         const long long i = e / n, j = e % n;
         out[e] = 0.5 * (Z[e] + Z[j * n + i]);
+    }
+}
+
+// In place over the d^2 matrices X_q (n^2 entries each, q = s d + t):
+// X_q <- sum_q2 S[q][q2] X_q2, S = rhob of the plaquette density (d^2 <= 16).
+__global__ void mix_planes_kernel(double* X, long long nn, int d2, const double* __restrict__ S) {
+    double v[16];
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+        for (int q = 0; q < d2; ++q) v[q] = X[(size_t)q * nn + e];
+        for (int q = 0; q < d2; ++q) {
+            double a = 0.0;
+            for (int q2 = 0; q2 < d2; ++q2) a += S[q * d2 + q2] * v[q2];
+            X[(size_t)q * nn + e] = a;
+        }
+    }
+}
+
+// out[al][f][r][d] = (S[(al,r),(f,d)] + S[(f,d),(al,r)]) / 2 for the n x n
+// matrix S (n = chi Dab): the cotangent of an enlarged corner sym(Z), Z in the
+// layout of the step's 3b output, brought to the row order (al,f) x (r,d) of
+// the 3b GEMM.  32 x 32 tiles of S and of its transpose through LDS.
+constexpr int kSpTile = 32;
+__global__ __launch_bounds__(256) void sym_perm_kernel(const double* __restrict__ S, int chi,
+                                                       int Dab, double* __restrict__ out) {
+    __shared__ double a[kSpTile][kSpTile + 1];
+    __shared__ double b[kSpTile][kSpTile + 1];
+    const long long n = (long long)chi * Dab;
+    const long long i0 = (long long)blockIdx.y * kSpTile, j0 = (long long)blockIdx.x * kSpTile;
+    const int tx = threadIdx.x % kSpTile, ty = threadIdx.x / kSpTile;  // 32 x 8
+    for (int r = ty; r < kSpTile; r += 8) {
+        const long long i = i0 + r, j = j0 + tx;
+        a[r][tx] = (i < n && j < n) ? S[i * n + j] : 0.0;       // S[i0 + r][j0 + tx]
+        const long long i2 = j0 + r, j2 = i0 + tx;
+        b[r][tx] = (i2 < n && j2 < n) ? S[i2 * n + j2] : 0.0;   // S[j0 + r][i0 + tx]
+    }
+    __syncthreads();
+    const long long D2 = (long long)Dab * Dab;
+    for (int r = ty; r < kSpTile; r += 8) {
+        const long long i = i0 + r, j = j0 + tx;
+        if (i >= n || j >= n) continue;
+        const long long al = i / Dab, rr = i % Dab, f = j / Dab, dd = j % Dab;
+        out[al * (long long)chi * D2 + f * D2 + rr * Dab + dd] = 0.5 * (a[r][tx] + b[tx][r]);
     }
 }
 
@@ -527,6 +597,98 @@ Status nnn_rho(const EnergyArgs& ea, const ELayout& L, hipStream_t st) {
     return s;
 }
 
+// Reverse of the plaquette term e2 = 2 J2 Tr(rm2 h2)/Tr(rm2), after nnn_rho
+// (Cc in E2, Co_q in E4, X_q = Co_q Cc in E4p, the 3a output Y of the reduced
+// corner in Ybuf, the reduced corner in Qbuf) and after the nearest-neighbour
+// reverse (whose tape it reuses).  Adds to Cb, Tb (device) and Asb.
+// With S = rhob2 (symmetrised), the cotangent of X_q is (sum_q2 S[q][q2] X_q2)^T
+// = V_q^T (rho2[q1][q2] = Tr(X_q1 X_q2)); hence, Cc and Co_q being symmetric,
+//   Cobar_q = V_q^T Cc,   Ccbar = sum_q Co_q V_q^T,
+// each symmetrised (Co_q = sym(Z_q), Cc = sym(Z)), then the enlarged corners'
+// 3b (closed and open double layers), 3a and reduced corner are reversed.
+Status nnn_backward(const EnergyArgs& ea, const ELayout& L, double J2, double* Cb, double* Tb,
+                    double* Asb, hipStream_t st) {
+    char* b = ea.ws;
+    auto P = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
+    void* sk = b + L.splitk;
+    const size_t skb = L.splitk_bytes;
+    const int d = ea.d, D = ea.D, chi = ea.chi, Dab = D * D, d2 = d * d;
+    const long long c = chi, Db = Dab, n = c * Db, nn = n * n, Q2 = Db * Db;
+    if (d2 > 16) {
+        Status s;
+        s.code = -1;
+        s.msg = "energy gradient: the next-nearest-neighbour term supports d <= 4";
+        return s;
+    }
+    double* Cc = P(L.E2);
+    double* Co = P(L.E4);
+    double* X = P(L.E4p);
+    // S = symmetrised dE2/drho2, then X_q -> V_q = sum_q2 S[q][q2] X_q2 in place
+    hipLaunchKernelGGL(rho_bar_kernel, dim3(1), dim3(64), 0, st, P(L.rho2), P(L.h) + d2 * d2, d,
+                       2.0 * J2, P(L.rhob2));
+    QRCTM_TRY(launch_check("rho_bar_kernel"));
+    const int blocks = (int)std::min<long long>(ceil_div(nn, 256), 65536);
+    hipLaunchKernelGGL(mix_planes_kernel, dim3(blocks), dim3(256), 0, st, X, nn, d2, P(L.rhob2));
+    QRCTM_TRY(launch_check("mix_planes_kernel"));
+    // Ccbar (into Yb) = sum_q Co_q V_q^T; then Cobar_q = V_q^T Cc over Co_q
+    double* Ccb = P(L.Yb);
+    for (int q = 0; q < d2; ++q) {
+        GemmDesc g;
+        g.trans_b = 1;
+        g.M = n; g.N = n; g.K = n;
+        g.A = Co + (size_t)q * nn; g.lda = n; g.B = X + (size_t)q * nn; g.ldb = n;
+        g.C = Ccb; g.map = OutMap::plain(n, n, n); g.beta = q ? 1.0 : 0.0;
+        QRCTM_TRY(gemm_f64(g, sk, skb, st));
+    }
+    for (int q = 0; q < d2; ++q) {
+        GemmDesc g;
+        g.trans_a = 1;
+        g.M = n; g.N = n; g.K = n;
+        g.A = X + (size_t)q * nn; g.lda = n; g.B = Cc; g.ldb = n;
+        g.C = Co + (size_t)q * nn; g.map = OutMap::plain(n, n, n);
+        QRCTM_TRY(gemm_f64(g, sk, skb, st));
+    }
+    // reverse of 3b, Z_x[(al,f),(r,d)] = sum_(u,l) Y[(al,f),(u,l)] a_x[(u,l),(r,d)],
+    // for the closed corner and the d^2 open ones: Ybar (layout [u][al][f][l], in
+    // E3) accumulates Zbar'_x a_x^T, and a_x's cotangent Y^T Zbar'_x (D^8 <= n^2
+    // doubles over the dead V_0) goes to the site tensor's cotangent
+    double* Zb = ea.Zbuf;
+    double* Ybar = P(L.E3);
+    double* xbar = X;
+    const dim3 sp_grid((unsigned)ceil_div(n, kSpTile), (unsigned)ceil_div(n, kSpTile));
+    auto reverse_3b = [&](const double* Sx, const double* ax, bool first) -> Status {
+        hipLaunchKernelGGL(sym_perm_kernel, sp_grid, dim3(256), 0, st, Sx, chi, Dab, Zb);
+        QRCTM_TRY(launch_check("sym_perm_kernel"));
+        QRCTM_TRY(gemm_f64(gd(0, 1, c * c, Q2, Q2, Zb, Q2, ax, Q2, Ybar,
+                              OutMap{c, c * Db, Db, Db, c * c * Db, 1}, first ? 0.0 : 1.0),
+                           sk, skb, st));
+        return gemm_f64(gd(1, 0, Q2, Q2, c * c, ea.Ybuf, Q2, Zb, Q2, xbar, plain(Q2, Q2)), sk, skb,
+                        st);
+    };
+    QRCTM_TRY(reverse_3b(Ccb, ea.a, true));
+    QRCTM_TRY(double_layer_backward(xbar, ea.As, d, D, Asb, st));
+    double* aop = P(L.Yb);  // Ccbar is dead now
+    const long long D8 = Q2 * Q2;
+    for (int q = 0; q < d2; ++q) {
+        hipLaunchKernelGGL(open_layer_kernel, dim3((int)std::min<long long>(ceil_div(D8, 256), 65536)),
+                           dim3(256), 0, st, ea.As, D, q / d, q % d, aop);
+        QRCTM_TRY(launch_check("open_layer_kernel"));
+        QRCTM_TRY(reverse_3b(Co + (size_t)q * nn, aop, false));
+        QRCTM_TRY(open_layer_backward(xbar, ea.As, D, q / d, q % d, Asb, st));
+    }
+    // reverse of 3a, Y[al,f,u,l] = sum_e ct[(e,u),al] T[f,l,e]: ctbar (in Fb) and Tb
+    double* ctb = P(L.Fb);
+    QRCTM_TRY(gemm_f64(gd(0, 0, Db * c, c, c * Db, Ybar, c * Db, ea.T, c, ctb,
+                          OutMap{Db * c, 0, 1, c, 0, Db * c}), sk, skb, st));
+    QRCTM_TRY(gemm_f64(gd(1, 1, c * Db, c, Db * c, Ybar, c * Db, ea.Qbuf, Db * c, Tb,
+                          plain(c * Db, c), 1.0), sk, skb, st));
+    // reverse of the reduced corner ct = C T
+    QRCTM_TRY(gemm_f64(gd(0, 1, c, c, Db * c, ctb, Db * c, ea.T, Db * c, Cb, plain(c, c), 1.0), sk,
+                       skb, st));
+    return gemm_f64(gd(1, 0, c, Db * c, c, ea.C, c, ctb, Db * c, Tb, plain(c, Db * c), 1.0), sk, skb,
+                    st);
+}
+
 }  // namespace
 
 Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
@@ -562,8 +724,8 @@ Status energy_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn
     return s;
 }
 
-Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, double* E, double* Cb,
-                        double* Tb, double* Asb, hipStream_t st) {
+Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, const double* h_nnn, double J2,
+                        double* E, double* Cb, double* Tb, double* Asb, hipStream_t st) {
     Status s;
     const int d = ea.d, D = ea.D, chi = ea.chi;
     const ELayout L = e_layout(d, D, chi);
@@ -582,7 +744,7 @@ Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, double* E, dou
     hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, 2.0,
                        P(L.scal), 0);
     QRCTM_TRY(launch_check("bond_energy_kernel"));
-    hipLaunchKernelGGL(rho_bar_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, P(L.rhob));
+    hipLaunchKernelGGL(rho_bar_kernel, dim3(1), dim3(64), 0, st, P(L.rho), P(L.h), d, 2.0, P(L.rhob));
     QRCTM_TRY(launch_check("rho_bar_kernel"));
     const long long K = c * D2 * c;
     // Lpb = rhob_sym Lp
@@ -637,6 +799,16 @@ Status energy_grad_eval(const EnergyArgs& ea, const double* h_nn, double* E, dou
         const long long dims[5] = {DD, DD, dd, DD, DD};
         const int axes[5] = {2, 0, 1, 3, 4};
         QRCTM_TRY(permute(P(L.Akb), Asb, 5, dims, axes, st));
+    }
+    if (h_nnn != nullptr && J2 != 0.0) {
+        // 2 J2 <h_nnn> and its reverse (the plaquette reuses the tape above)
+        const int d4 = d * d * d * d;
+        QRCTM_TRY(nnn_rho(ea, L, st));
+        QRCTM_HIP(hipMemcpyAsync(P(L.h) + d4, h_nnn, sizeof(double) * d4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(bond_energy_kernel, dim3(1), dim3(64), 0, st, P(L.rho2), P(L.h) + d4, d,
+                           2.0 * J2, P(L.scal), 1);
+        QRCTM_TRY(launch_check("bond_energy_kernel"));
+        QRCTM_TRY(nnn_backward(ea, L, J2, Cb, Tb, Asb, st));
     }
     double hv = NAN;
     QRCTM_HIP(hipMemcpyAsync(&hv, P(L.scal), sizeof(double), hipMemcpyDeviceToHost, st));

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import warnings
 from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_size_t, c_void_p
 
 import numpy as np
@@ -35,7 +36,7 @@ class CtmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("n_warmup", c_int), ("k_tracked", c_int),
                 ("qr_sing_tol", c_double), ("mixed_tol", c_double), ("edge_split", c_int),
                 ("grad_mode", c_int), ("fp_tol", c_double), ("fp_max_iter", c_int),
-                ("grad_keep_yz", c_int)]
+                ("grad_keep_yz", c_int), ("qr_reg_eps", c_double)]
 
 
 class CtmStats(ctypes.Structure):
@@ -126,12 +127,20 @@ def _dev_f64(x, dev):
     return t.contiguous()
 
 
-def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-14,
+class ConvergenceWarning(UserWarning):
+    """The environment (or the fixed-point series) stopped before its tolerance."""
+
+
+def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=None, qr_sing_tol=1e-14,
                  mixed_tol=None, edge_split=None, grad_mode=None, fp_tol=None,
-                 fp_max_iter=None, grad_keep_yz=None) -> CtmOpts:
+                 fp_max_iter=None, grad_keep_yz=None, qr_reg_eps=None) -> CtmOpts:
+    """ctm_opts with the library's defaults, overridden where an argument is given
+    (k_tracked None or -1: the per-D default)."""
     o = CtmOpts()
     lib().ctm_default_opts(byref(o))
-    o.precision, o.n_warmup, o.k_tracked, o.qr_sing_tol = precision, n_warmup, k_tracked, qr_sing_tol
+    o.precision, o.n_warmup, o.qr_sing_tol = precision, n_warmup, qr_sing_tol
+    if k_tracked is not None:
+        o.k_tracked = int(k_tracked)
     if mixed_tol is not None:
         o.mixed_tol = mixed_tol
     if edge_split is not None:
@@ -144,6 +153,8 @@ def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=10, qr_sing_tol=1e-
         o.fp_max_iter = int(fp_max_iter)
     if grad_keep_yz is not None:
         o.grad_keep_yz = int(grad_keep_yz)
+    if qr_reg_eps is not None:
+        o.qr_reg_eps = float(qr_reg_eps)
     return o
 
 
@@ -151,13 +162,15 @@ class Context:
     """One CTMRG environment on one GPU (wraps ctm_ctx)."""
 
     def __init__(self, A=None, chi: int = 16, *, a=None, bvec=None, device="cuda:0",
-                 n_warmup: int = -1, precision: int = PREC_FP64, k_tracked: int = 10,
+                 n_warmup: int = -1, precision: int = PREC_FP64, k_tracked=None,
                  qr_sing_tol: float = 1e-14, mixed_tol=None, edge_split=None,
-                 grad_mode=None, fp_tol=None, fp_max_iter=None, grad_keep_yz=None):
+                 grad_mode=None, fp_tol=None, fp_max_iter=None, grad_keep_yz=None,
+                 qr_reg_eps=None):
         torch = _torch()
         self.device = torch.device(device)
         self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol,
-                                 edge_split, grad_mode, fp_tol, fp_max_iter, grad_keep_yz)
+                                 edge_split, grad_mode, fp_tol, fp_max_iter, grad_keep_yz,
+                                 qr_reg_eps)
         self.chi = chi
         L = lib()
         ctx = c_void_p()
@@ -295,6 +308,10 @@ def _energy_function():
     forward: ctm_set_tensor (the context keeps its environment as the starting
     point, as the AD paragraph reuses the previous environment), ctm_converge,
     then ctm_energy_grad, whose dE/dA is saved; backward returns gE * dE/dA.
+    An environment that stopped before tol (CTM_NOTCONV), or a fixed-point
+    series that stopped before fp_tol, is reported as the caller asks
+    (on_notconv: "warn", "raise" or "ignore") and recorded on the context
+    (ctx.last_converged, ctx.last_delta, ctx.last_steps, ctx.grad_converged).
     """
     global _ENERGY_FN
     if _ENERGY_FN is None:
@@ -302,31 +319,51 @@ def _energy_function():
 
         class QRCTMEnergy(torch.autograd.Function):
             @staticmethod
-            def forward(fctx, A, ctx, h_nn, h_nnn, J2, tol, max_steps):
+            def forward(fctx, A, ctx, h_nn, h_nnn, J2, tol, max_steps, on_notconv):
                 ctx.set_tensor(A.detach())
-                ctx.converge(tol, max_steps)
+                ok, steps, dl = ctx.converge(tol, max_steps)
+                ctx.last_converged, ctx.last_steps, ctx.last_delta = ok, steps, dl
+                if not ok:
+                    _report(on_notconv, CTM_NOTCONV,
+                            f"environment not converged: delta {dl:.3e} >= tol {tol:.1e} "
+                            f"after {steps} steps; E and dE/dA come from this environment")
                 e, dA = ctx.energy_grad(h_nn, h_nnn, J2)
+                if not ctx.grad_converged:
+                    _report(on_notconv, CTM_NOTCONV,
+                            "fixed-point series stopped before fp_tol; dE/dA is truncated")
                 fctx.save_for_backward(dA.to(A.dtype))
                 return torch.tensor(e, dtype=A.dtype, device=A.device)
 
             @staticmethod
             def backward(fctx, gE):
                 (dA,) = fctx.saved_tensors
-                return gE * dA, None, None, None, None, None, None
+                return gE * dA, None, None, None, None, None, None, None
 
         _ENERGY_FN = QRCTMEnergy
     return _ENERGY_FN
 
 
+def _report(policy: str, code: int, msg: str):
+    if policy == "raise":
+        raise CTMError(code, msg)
+    if policy == "warn":
+        warnings.warn(msg, ConvergenceWarning, stacklevel=4)
+    elif policy != "ignore":
+        raise ValueError(f"on_notconv must be 'warn', 'raise' or 'ignore', not {policy!r}")
+
+
 def energy(A, ctx: "Context", h_nn, h_nnn=None, J2: float = 0.0, tol: float = 1e-10,
-           max_steps: int = 200):
+           max_steps: int = 200, on_notconv: str = "warn"):
     """Differentiable energy per site E(A) (a torch scalar on A's device).
 
     The environment of ctx is converged for A (to tol, at most max_steps
     steps), then E and dE/dA come from ctm_energy_grad: dE/dA is the derivative
-    of E_k(P(A); C*, T*), k = the context's tracked steps.
+    of E_k(P(A); C*, T*), k = the context's tracked steps (or, with the
+    fixed-point scheme, of the converged energy).  on_notconv decides what an
+    unconverged environment or series does: "warn" (default), "raise" or
+    "ignore"; either way ctx.last_converged and ctx.grad_converged record it.
     """
-    return _energy_function().apply(A, ctx, h_nn, h_nnn, J2, tol, max_steps)
+    return _energy_function().apply(A, ctx, h_nn, h_nnn, J2, tol, max_steps, on_notconv)
 
 
 def qr(M):

@@ -19,11 +19,27 @@ def test_library_exports_every_declared_function():
 
 def test_default_opts():
     o = B.default_opts()
-    assert o.precision == B.PREC_FP64 and o.n_warmup == -1 and o.k_tracked == 10
+    assert o.precision == B.PREC_FP64 and o.n_warmup == -1 and o.k_tracked == -1
     assert o.qr_sing_tol == 1e-14 and o.mixed_tol == 1e-6
     assert o.edge_split == 1 and o.grad_mode == B.GRAD_CHECKPOINT
     assert o.fp_tol == 1e-10 and o.fp_max_iter == 1000
-    assert o.grad_keep_yz == 0
+    assert o.grad_keep_yz == 0 and o.qr_reg_eps == 0.0
+
+
+def test_default_tracked_steps_per_bond_dimension():
+    # k_tracked = -1 plans the checkpoints of the per-D choice of the paper's
+    # timing study (Fig. 3 caption: 10, 12, 14, 16, 20, 24 for D = 2..7; 28 at D = 8)
+    L = P.lib()
+    auto = B.default_opts()
+    for D, k in [(2, 10), (3, 12), (4, 14), (5, 16), (6, 20), (7, 24), (8, 28)]:
+        chi = D * D
+        fixed = B.default_opts(k_tracked=k)
+        assert (L.ctm_workspace_bytes(2, D, chi, ctypes.byref(auto))
+                == L.ctm_workspace_bytes(2, D, chi, ctypes.byref(fixed))), D
+    bad = B.default_opts(k_tracked=-2)
+    assert L.ctm_workspace_bytes(2, 4, 64, ctypes.byref(bad)) == 0
+    neg = B.default_opts(qr_reg_eps=-1.0)
+    assert L.ctm_workspace_bytes(2, 4, 64, ctypes.byref(neg)) == 0
 
 
 def test_kept_yz_adds_two_slots_per_tracked_step():
@@ -49,7 +65,7 @@ def test_split_operand_planned_only_where_the_kernels_apply():
     assert ws(3, 4, 64, on) == ws(3, 4, 64, off)
     assert ws(2, 8, 1024, on) == ws(2, 8, 1024, off)
     bad = B.default_opts(edge_split=2)
-    assert L.ctm_workspace_bytes(2, 4, 64, ctypes.byref(bad)) > 0  # planner only; init rejects
+    assert L.ctm_workspace_bytes(2, 4, 64, ctypes.byref(bad)) == 0  # invalid options
 
 
 def test_workspace_sizes_grow_with_problem():

@@ -168,3 +168,42 @@ def test_kept_yz_equals_recomputed_yz(mode, D, chi, k, split):
     assert e1 == e0
     assert np.linalg.norm(g1 - g0) <= 1e-13 * np.linalg.norm(g0)
     ctx.close()
+
+
+def test_regularised_qr_adjoint():
+    # qr_reg_eps > 0: the product state's rank-1 reduced corner, which fails
+    # with CTM_ESINGULAR by default, gives a finite gradient with the exact
+    # gradient's invariants; on a full-rank case the regularised adjoint equals
+    # the oracle's regularised reverse mode, and a tiny eps the exact one
+    A = inp.product_state_tensor([1.0, 0.3], 2)
+    ctx = P.Context(_dev(A), 8, k_tracked=2, qr_reg_eps=1e-6)
+    _, g = ctx.energy_grad(inp.heisenberg_bond_rotated())
+    g = g.cpu().numpy()
+    assert np.all(np.isfinite(g))
+    assert np.abs(ctm.c4v_average(g) - g).max() <= 1e-14 * max(np.abs(g).max(), 1e-300)
+    ctx.close()
+    d, D, chi, k = 2, 3, 27, 2
+    A, C, T = _env(d, D, chi, seed=1, steps=10)
+    h = inp.heisenberg_bond_rotated()
+    for eps in (1e-3, 1e-13):
+        e_ref, g_ref = adj.energy_grad_k(A, C, T, k, h, qr_reg_eps=eps)
+        c = P.Context(_dev(A), chi, n_warmup=0, k_tracked=k, qr_reg_eps=eps)
+        c.set_env(_dev(C), _dev(T))
+        e, g = c.energy_grad(h)
+        g = g.cpu().numpy()
+        assert abs(e - e_ref) < 1e-12 * abs(e_ref)
+        assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < 1e-9, eps
+        c.close()
+    _, g_exact = adj.energy_grad_k(A, C, T, k, h)
+    _, g_reg = adj.energy_grad_k(A, C, T, k, h, qr_reg_eps=1e-3)
+    assert np.linalg.norm(g_reg - g_exact) > 1e-9 * np.linalg.norm(g_exact)
+
+
+def test_default_tracked_steps_follow_bond_dimension():
+    # k_tracked = -1 (default): the paper's per-D choice (Fig. 3 caption)
+    for D, want in ((2, 10), (3, 12), (4, 14)):
+        A = inp.random_site_tensor(2, D, 1)
+        ctx = P.Context(_dev(A), D * D)
+        ctx.energy_grad(inp.heisenberg_bond_rotated())
+        assert ctx.stats()["grad_steps"] == want, D
+        ctx.close()

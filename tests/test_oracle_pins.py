@@ -409,6 +409,37 @@ def test_qr_backward_matches_finite_differences():
     assert np.abs(fd - g).max() / np.abs(g).max() < 1e-8
 
 
+def test_regularized_triangular_inverse_by_hand():
+    # 2 x 2 by hand: R = [[a, b], [0, c]], d_x = x / (x^2 + eps^2):
+    # back substitution gives [[d_a, -d_a b d_c], [0, d_c]]
+    a_, b_, c_ = 2.0, -0.7, 0.5
+    R = np.array([[a_, b_], [0.0, c_]])
+    eps_rel = 0.3
+    eps = eps_rel * 2.0
+    da, dc = a_ / (a_ * a_ + eps * eps), c_ / (c_ * c_ + eps * eps)
+    want = np.array([[da, -da * b_ * dc], [0.0, dc]])
+    assert np.abs(adj.regularized_inverse(R, eps_rel) - want).max() < 1e-15
+    # a zero pivot gives a zero row and column entry instead of a division by 0
+    Z = np.array([[1.0, 0.4, 0.2], [0.0, 0.0, 0.3], [0.0, 0.0, 0.5]])
+    X = adj.regularized_inverse(Z, 1e-3)
+    assert np.all(np.isfinite(X)) and X[1, 1] == 0.0
+    # eps -> 0: the ordinary inverse (LAPACK), and a diagonal R: r / (r^2 + eps^2)
+    rng = np.random.default_rng(4)
+    U = np.triu(rng.standard_normal((6, 6))) + 3 * np.eye(6)
+    assert np.abs(adj.regularized_inverse(U, 0.0) - np.linalg.inv(U)).max() < 1e-13
+    r = np.array([1.0, -0.5, 1e-3])
+    e2 = (0.1 * 1.0) ** 2
+    assert np.allclose(np.diag(adj.regularized_inverse(np.diag(r), 0.1)), r / (r * r + e2),
+                       rtol=1e-15, atol=0)
+    # the QR adjoint with eps_rel = 0 and with a tiny eps agree
+    M = rng.standard_normal((20, 6))
+    Q, Rq = ctm.qr_pos(M)
+    GQ, GR = rng.standard_normal((20, 6)), np.triu(rng.standard_normal((6, 6)))
+    g0 = adj.qr_backward(Q, Rq, GQ, GR)
+    g1 = adj.qr_backward(Q, Rq, GQ, GR, 1e-12)
+    assert np.abs(g1 - g0).max() < 1e-12 * np.abs(g0).max()
+
+
 def test_energy_gradient_matches_finite_differences():
     d, D, chi, k = 2, 2, 16, 4
     A = inp.random_site_tensor(d, D, 1)
