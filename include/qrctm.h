@@ -53,7 +53,11 @@ extern "C" {
 /* split-BF16: each FP64 operand rounded to FP32 and split exactly into three
    bf16 parts; six bf16 products (all terms down to 2^-24 relative) with FP32
    accumulation on the bf16 matrix cores.  Used for the large products of the
-   step (3a, 3b at the usual sizes); the smaller ones take the FP32 path. */
+   plain form's step (3a writes Y as planes, 3b is the double-layer product of
+   planes, at the usual sizes with D even); the smaller products take the FP32
+   path.  With the ket/bra split 3b (edge_split = 1) there is no bf16 build:
+   every product then runs on the FP32 matrix cores, as CTM_PREC_FP32_MFMA
+   (ctm_stats reports the 3b kernel). */
 #define CTM_PREC_BF16X6_MFMA 2
 
 /* Gradient schemes of ctm_energy_grad (ctm_opts.grad_mode). */
@@ -100,11 +104,22 @@ typedef struct ctm_opts {
                            eps = qr_reg_eps * max|R_ii|, so that a rank-deficient
                            reduced corner gives a finite (regularised) gradient
                            instead of CTM_ESINGULAR                                   */
+    int qr_method;      /* QR of the reduced corner (QR-CTMRG paragraph): CTM_QR_AUTO =
+                           Cholesky-QR2 (Gram matrix, Cholesky, triangular solves, twice;
+                           the same unique factors with diag(R) > 0), with the
+                           Householder factorisation run instead on the GPU whenever the
+                           Cholesky step rejects the matrix (a non-positive pivot,
+                           min R_ii < 1e-5 max R_ii, or a first-pass Q too far from
+                           orthonormal, e.g. a rank-deficient reduced corner);
+                           CTM_QR_HOUSEHOLDER = the Householder factorisation always  */
 } ctm_opts;
+
+#define CTM_QR_AUTO        0
+#define CTM_QR_HOUSEHOLDER 1
 
 /* Fill *o with defaults: FP64, n_warmup = -1, k_tracked = -1 (per D), qr_sing_tol =
    1e-14, mixed_tol = 1e-6, edge_split = 1, grad_mode = CTM_GRAD_CHECKPOINT, fp_tol =
-   1e-10, fp_max_iter = 1000, grad_keep_yz = 0, qr_reg_eps = 0. */
+   1e-10, fp_max_iter = 1000, grad_keep_yz = 0, qr_reg_eps = 0, qr_method = CTM_QR_AUTO. */
 void ctm_default_opts(ctm_opts* o);
 
 /*
@@ -241,7 +256,21 @@ typedef struct ctm_stats_t {
     long long grad_steps;     /* steps reversed by the last ctm_energy_grad    */
     double fp_residual;       /* |G(env) - env| / |env| seen by the last
                                  fixed-point ctm_energy_grad (G: two steps)    */
+    long long qr_fallbacks;   /* QRs (steps and tracked steps) that ran the
+                                 Householder factorisation because Cholesky-QR2
+                                 rejected the reduced corner (CTM_QR_AUTO),
+                                 counted since chi_cur last changed            */
+    int edge_3b_form;         /* kernel of the middle edge product (3b) in the
+                                 context's QR steps: CTM_3B_* below            */
 } ctm_stats_t;
+
+/* ctm_stats_t.edge_3b_form */
+#define CTM_3B_DOUBLE_LAYER_FP64   0  /* one GEMM with the double layer, FP64     */
+#define CTM_3B_DOUBLE_LAYER_FP32   1  /* the same on the FP32 matrix cores         */
+#define CTM_3B_DOUBLE_LAYER_BF16X6 2  /* the same as six bf16 products of split
+                                         planes (FP32 accumulation)               */
+#define CTM_3B_SPLIT_FP64          3  /* fused ket/bra split, FP64                 */
+#define CTM_3B_SPLIT_FP32          4  /* fused ket/bra split, FP32 matrix cores    */
 int ctm_stats(ctm_ctx* ctx, ctm_stats_t* st);
 
 /* Per-phase timing of QR steps with HIP events on the context stream (on = 1)
@@ -257,13 +286,17 @@ void ctm_destroy(ctm_ctx* ctx);
  * Component entry points (one kernel chain each), exposed for tests at full
  * size.  All arrays device, row-major; stream as above; they synchronise.
  *
- * ctm_qr: thin Householder QR of M (m x n, m >= n) with diag(R) >= 0
- *   (QR-CTMRG paragraph: unpivoted QR of the reduced corner).  Q is m x n,
- *   R n x n upper triangular.  ws of ctm_qr_workspace_bytes(m, n).
+ * ctm_qr: thin QR of M (m x n, m >= n) with diag(R) >= 0 (QR-CTMRG paragraph:
+ *   unpivoted QR of the reduced corner).  Q is m x n, R n x n upper
+ *   triangular; Q may alias M.  method: CTM_QR_AUTO or CTM_QR_HOUSEHOLDER as
+ *   for ctm_opts.qr_method.  used_householder (host, may be NULL) receives 1
+ *   when the Householder factorisation ran (always for CTM_QR_HOUSEHOLDER; for
+ *   CTM_QR_AUTO when Cholesky-QR2 rejected M), else 0.  ws of
+ *   ctm_qr_workspace_bytes(m, n).
  */
 size_t ctm_qr_workspace_bytes(int m, int n);
-int ctm_qr(const double* M, double* Q, double* R, int m, int n, void* ws,
-           size_t ws_bytes, void* stream);
+int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void* ws,
+           size_t ws_bytes, void* stream, int* used_householder);
 
 /*
  * ctm_gemm: C = alpha * op(A) op(B) + beta * C, FP64 on the matrix cores (the

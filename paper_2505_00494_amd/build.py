@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqrctm.so")
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "edge_split.hip", "qr.hip", "tensor_ops.hip", "spectrum.hip", "eigh.hip", "energy.hip",
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "edge_split.hip", "qr.hip", "qr_chol.hip", "tensor_ops.hip", "spectrum.hip", "eigh.hip", "energy.hip",
            "adjoint.hip", "ctm_abi.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

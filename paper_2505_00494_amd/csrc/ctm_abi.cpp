@@ -260,8 +260,9 @@ Plan plan_workspace(const Shape& sh, const ctm_opts& o) {
     take(P.energy, P.energy_bytes);
     P.grad_bytes = grad_layout(sh, o.k_tracked, use_split_bw(sh, o), o.grad_keep_yz != 0).total;
     take(P.grad, P.grad_bytes);
-    // planes need the contraction length Dab^2 to be a multiple of 8 (D even)
-    const bool planes = o.precision == CTM_PREC_BF16X6_MFMA && (Dab * Dab) % 8 == 0;
+    // planes need the contraction length Dab^2 to be a multiple of 8 (D even);
+    // the split 3b has no bf16 build, so it takes no planes
+    const bool planes = o.precision == CTM_PREC_BF16X6_MFMA && (Dab * Dab) % 8 == 0 && !use_split(sh, o);
     take(P.Y16, planes ? 3 * sizeof(unsigned short) * chi * chi * Dab * Dab : 0);
     take(P.a16, planes ? 3 * sizeof(unsigned short) * Dab * Dab * Dab * Dab : 0);
     take(P.Bk, use_split(sh, o) ? d8 * edge_split_operand_size(sh.d, sh.D) : 0);
@@ -334,7 +335,10 @@ struct ctm_ctx {
     } owed;
     int last_slot = 0;
     // QR launches on the context's QR workspace (numbers their exchange tags)
+    // since its layout was last set for chi_cur = qr_chi (a new size starts
+    // over at 0, which clears the exchange words and counters first)
     unsigned long long qr_launches = 0;
+    int qr_chi = 0;
     ~ctm_ctx() {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -514,8 +518,13 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
     QRCTM_TRY(mark(0));
     QRCTM_TRY(G(g_reduced_corner(p, chi, Dab)));                                       // a5
     QRCTM_TRY(mark(1));
+    if (c->qr_chi != chi) {
+        c->qr_chi = chi;
+        c->qr_launches = 0;
+    }
     QRCTM_TRY(qr_pos(p.Q, p.Q, p.R, chi * Dab, chi, c->ptr<void>(c->plan.qr), c->plan.qr_bytes,
-                     c->st, c->small() + SL_RATIO, c->bad(), c->qr_launches++));    // a6
+                     c->st, c->small() + SL_RATIO, c->bad(), c->qr_launches++,
+                     c->opts.qr_method == CTM_QR_HOUSEHOLDER ? kQrHouseholder : kQrAuto));  // a6
     if (after_qr) QRCTM_HIP(hipEventRecord(after_qr, c->st));
     QRCTM_TRY(mark(2));
     {
@@ -918,7 +927,8 @@ bool valid_opts(const ctm_opts& o) {
            o.k_tracked >= -1 && (o.edge_split == 0 || o.edge_split == 1) &&
            (o.grad_mode == CTM_GRAD_CHECKPOINT || o.grad_mode == CTM_GRAD_FIXED_POINT) &&
            o.fp_tol > 0.0 && o.fp_max_iter >= 2 && (o.grad_keep_yz == 0 || o.grad_keep_yz == 1) &&
-           o.qr_reg_eps >= 0.0 && std::isfinite(o.qr_reg_eps);
+           o.qr_reg_eps >= 0.0 && std::isfinite(o.qr_reg_eps) &&
+           (o.qr_method == CTM_QR_AUTO || o.qr_method == CTM_QR_HOUSEHOLDER);
 }
 
 // Tracked steps per bond dimension when opts.k_tracked = -1: the paper's timing
@@ -1015,6 +1025,7 @@ void ctm_default_opts(ctm_opts* o) {
     o->fp_max_iter = 1000;
     o->grad_keep_yz = 0;
     o->qr_reg_eps = 0.0;
+    o->qr_method = CTM_QR_AUTO;
 }
 
 size_t ctm_workspace_bytes(int d, int D, int chi, const ctm_opts* opts) {
@@ -1321,6 +1332,18 @@ int ctm_stats(ctm_ctx* c, ctm_stats_t* st) {
         for (int i = 0; i < kPhases; ++i) st->ms_phase[i] = c->ms_phase[i];
         st->grad_steps = c->grad_steps;
         st->fp_residual = c->fp_residual;
+        unsigned long long fb = 0;
+        if (c->qr_launches > 0)
+            QRCTM_TRY(qr_fallback_count(c->ptr<void>(c->plan.qr), c->qr_chi * c->sh.Dab, c->qr_chi,
+                                        c->st, &fb));
+        st->qr_fallbacks = (long long)fb;
+        const bool split = c->plan.Bk.bytes > 0;
+        const int prec = c->opts.precision;
+        if (split) st->edge_3b_form = prec == CTM_PREC_FP64 ? CTM_3B_SPLIT_FP64 : CTM_3B_SPLIT_FP32;
+        else if (prec == CTM_PREC_FP64) st->edge_3b_form = CTM_3B_DOUBLE_LAYER_FP64;
+        else if (prec == CTM_PREC_BF16X6_MFMA && c->plan.Y16.bytes > 0)
+            st->edge_3b_form = CTM_3B_DOUBLE_LAYER_BF16X6;
+        else st->edge_3b_form = CTM_3B_DOUBLE_LAYER_FP32;
         return Status{};
     });
 }
@@ -1351,19 +1374,24 @@ size_t ctm_qr_workspace_bytes(int m, int n) {
     return qr_scratch_layout(m, n).total;
 }
 
-int ctm_qr(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
-           void* stream) {
+int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void* ws,
+           size_t ws_bytes, void* stream, int* used_householder) {
     if (!M || !Q || !R) return fail(nullptr, CTM_EINVAL, "NULL argument");
     if (m < n || n < 1) return fail(nullptr, CTM_EINVAL, "need m >= n >= 1");
+    if (method != CTM_QR_AUTO && method != CTM_QR_HOUSEHOLDER)
+        return fail(nullptr, CTM_EINVAL, "unknown QR method");
     return guarded(nullptr, [&]() -> Status {
         hipStream_t st = static_cast<hipStream_t>(stream);
         const QrScratch L = qr_scratch_layout(m, n);
         int* err = reinterpret_cast<int*>(static_cast<char*>(ws) + L.off_err);
         if (ws_bytes >= L.total) QRCTM_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
-        QRCTM_TRY(qr_pos(M, Q, R, m, n, ws, ws_bytes, st, nullptr, err));
+        QRCTM_TRY(qr_pos(M, Q, R, m, n, ws, ws_bytes, st, nullptr, err, 0,
+                         method == CTM_QR_HOUSEHOLDER ? kQrHouseholder : kQrAuto));
         int h = 0;
         QRCTM_HIP(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, st));
-        QRCTM_TRY(sync(st));
+        unsigned long long fb = 0;
+        QRCTM_TRY(qr_fallback_count(ws, m, n, st, &fb));
+        if (used_householder) *used_householder = (method == CTM_QR_HOUSEHOLDER || fb > 0) ? 1 : 0;
         if (h != 0) {
             Status s;
             s.code = CTM_EHIP;

@@ -387,7 +387,13 @@ template <bool kWide>
 __global__ __launch_bounds__(kQrThreads) void qr_kernel(
     const double* M, int m_, int n_, double* __restrict__ Aw, double* Qo, double* __restrict__ Ro,
     u64* __restrict__ part, u64* __restrict__ rowbuf, u64* __restrict__ redp,
-    u64* __restrict__ redsum, double* __restrict__ ratio, int* __restrict__ err, unsigned tag_base) {
+    u64* __restrict__ redsum, double* __restrict__ ratio, int* __restrict__ err, unsigned tag_base,
+    const int* __restrict__ run_if, unsigned long long* fallbacks) {
+    // behind Cholesky-QR2: run only where it rejected the factorisation
+    if (run_if != nullptr) {
+        if (*run_if == 0) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(fallbacks, 1ull);
+    }
     QrArgs a{M, m_, n_, Aw, Qo, Ro, part, rowbuf, redp, redsum, ratio, err};
     extern __shared__ double lds[];
     const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
@@ -625,9 +631,11 @@ QrScratch qr_scratch_layout(int m, int n) {
     s.off_rowbuf = take(2 * sizeof(u64) * 2 * kPb);
     s.off_red = take(2 * sizeof(u64) * (size_t)L.P * kPb * w);
     s.off_redsum = take(2 * sizeof(u64) * kPb * w);
+    s.off_fallbacks = take(sizeof(unsigned long long));
     s.off_xend = off;
     s.off_ratio = take(sizeof(double));
     s.off_err = take(sizeof(int));
+    s.off_chol = take(cholqr_scratch_layout(m, n).total);
     s.total = off;
     return s;
 }
@@ -640,8 +648,16 @@ bool qr_fits(int m, int n) {
     return L.lds_bytes <= kQrLdsBudget && L.P <= kMaxWg;
 }
 
+Status qr_fallback_count(const void* ws, int m, int n, hipStream_t st, unsigned long long* out) {
+    const QrScratch S = qr_scratch_layout(m, n);
+    QRCTM_HIP(hipMemcpyAsync(out, static_cast<const char*>(ws) + S.off_fallbacks, sizeof(*out),
+                             hipMemcpyDeviceToHost, st));
+    return hip_status(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
 Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, size_t ws_bytes,
-              hipStream_t st, double* diag_ratio_dev, int* err_dev, unsigned long long epoch) {
+              hipStream_t st, double* diag_ratio_dev, int* err_dev, unsigned long long epoch,
+              int method) {
     Status s;
     if (!qr_fits(m, n)) {
         s.code = -1;
@@ -691,11 +707,24 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
                            st, a.part, nwords);
         QRCTM_TRY(launch_check("clear_words_kernel"));
     }
+    const bool chol = method == kQrAuto && cholqr_supported(m, n);
+    int* run_if = nullptr;
+    unsigned long long* fallbacks = reinterpret_cast<unsigned long long*>(base + S.off_fallbacks);
+    if (chol) {
+        const CholQrScratch C = cholqr_scratch_layout(m, n);
+        char* cb = base + S.off_chol;
+        if (e == 0) {  // the Gram kernel's tile tickets start at zero
+            hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(256), 0, st,
+                               reinterpret_cast<u64*>(cb + C.off_cnt), (long long)ceil_div(C.cnt_words, 2));
+            QRCTM_TRY(launch_check("clear_words_kernel"));
+        }
+        QRCTM_TRY(cholqr2(M, Q, R, m, n, cb, C, a.ratio, &run_if, st));
+    }
     unsigned tag_base = (unsigned)e * kQrTagSpan;
     void* args[] = {(void*)&a.M,    (void*)&a.m,     (void*)&a.n,   (void*)&a.A,
                     (void*)&a.Q,    (void*)&a.R,     (void*)&a.part, (void*)&a.rowbuf,
                     (void*)&a.red,  (void*)&a.redsum, (void*)&a.ratio, (void*)&a.err,
-                    (void*)&tag_base};
+                    (void*)&tag_base, (void*)&run_if, (void*)&fallbacks};
     QRCTM_HIP(hipLaunchCooperativeKernel(kern, dim3(L.P), dim3(kQrThreads), args, L.lds_bytes, st));
     return s;
 }

@@ -2,15 +2,22 @@
 // (the standard-CTMRG paragraph iterates the step to convergence; the change
 // in the normalised corner spectrum is the measure used here).
 //
-// One workgroup of 512 threads.  Householder tridiagonalisation of the
-// symmetric chi x chi corner, keeping only its lower triangle (packed in LDS
-// up to chi = 176, beyond that row-major in global scratch, L2 resident).  The
-// rank-2 update of each reflection is applied lazily, in the same sweep of the
-// trailing triangle that forms the next reflection's product A v, so each
-// reflection reads and writes the triangle once.  Eigenvalues of the
-// tridiagonal matrix by Sturm-sequence multisection (1-8 lanes per eigenvalue),
-// |lambda| ranked in descending order (ties by index), normalised by their sum,
-// and delta = || s - s_prev ||_2 with the shorter spectrum padded by zeros.
+// Three kernels on the caller's stream:
+//  * tridiag_kernel, one workgroup of 512 threads: Householder
+//    tridiagonalisation of the symmetric chi x chi corner, keeping only its
+//    lower triangle (packed in LDS up to chi = 176, beyond that row-major in
+//    global scratch, L2 resident).  The rank-2 update of each reflection is
+//    applied lazily, in the same sweep of the trailing triangle that forms the
+//    next reflection's product A v, so each reflection reads and writes the
+//    triangle once.  Writes the diagonal, the squared off-diagonal and a
+//    Gershgorin interval;
+//  * bisect_kernel, one wave per eigenvalue over as many workgroups as needed:
+//    Sturm-sequence multisection, the 64 lanes each placing two of the 128
+//    interior points that cut the interval, until it stops shrinking or is
+//    within 2 eps relative / 4 eps |T| absolute;
+//  * rank_kernel, one workgroup: |lambda| ranked in descending order (ties by
+//    index), normalised by their sum, and delta = || s - s_prev ||_2 with the
+//    shorter spectrum padded by zeros.
 // Every reduction has a fixed order, so the result does not vary between runs.
 #include "common.h"
 #include "spectrum.h"
@@ -137,52 +144,6 @@ __device__ void sturm_counts(const double* d, const double* e2, int n, const dou
     for (; j < n; ++j) step(d[j], e2[j - 1]);
 }
 
-// Eigenvalue e (ascending) of the tridiagonal matrix inside [a, b] by
-// multisection: the g lanes of a group (g = 1, 2, 4 or 8 adjacent lanes) each
-// place NP of the g NP interior points that cut [a, b] into equal parts, and
-// the group keeps the part holding the eigenvalue.  Stops at a width of
-// 2 eps max(|a|, |b|) + atol, or when the interval no longer shrinks.  Every
-// lane of the wave takes part (live = false for lanes without an eigenvalue).
-template <int NP>
-__device__ double multisect(const double* d, const double* e2, int n, int e, int s, int g,
-                            double a, double b, double pivmin, double atol, bool live) {
-    const int M = g * NP;
-    for (int it = 0; it < 256; ++it) {
-        live = live && (b - a > 2.0 * 2.2e-16 * fmax(fabs(a), fabs(b)) + atol);
-        if (!__any(live)) break;
-        const double h = (b - a) / (M + 1);
-        double x[NP];
-        int cnt[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) x[p] = a + (double)(s * NP + p + 1) * h;
-        sturm_counts<NP>(d, e2, n, x, pivmin, cnt);
-        double na = a, nb = b;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (cnt[p] > e) nb = fmin(nb, x[p]);
-            else na = fmax(na, x[p]);
-        }
-        if (g >= 2) {
-            na = fmax(na, dpp_perm<0xB1>(na));
-            nb = fmin(nb, dpp_perm<0xB1>(nb));
-        }
-        if (g >= 4) {
-            na = fmax(na, dpp_perm<0x4E>(na));
-            nb = fmin(nb, dpp_perm<0x4E>(nb));
-        }
-        if (g >= 8) {
-            na = fmax(na, dpp_perm<0x141>(na));
-            nb = fmin(nb, dpp_perm<0x141>(nb));
-        }
-        if (live) {
-            if (na == a && nb == b) live = false;
-            a = na;
-            b = nb;
-        }
-    }
-    return 0.5 * (a + b);
-}
-
 // Lower triangle of the symmetric matrix: rows of a row-major n x n array in
 // global scratch, or the packed triangle in LDS (row i at i(i+1)/2).
 struct GlobalSym {
@@ -200,10 +161,8 @@ struct LdsSym {
 
 
 template <class Store, int MAXN>
-__global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __restrict__ C, int n,
-                                                                double* Sg, const double* s_prev,
-                                                                int n_prev, double* s_out,
-                                                                double* delta_out) {
+__global__ __launch_bounds__(kSpecThreads) void tridiag_kernel(const double* __restrict__ C, int n,
+                                                               double* Sg, double* tri) {
     constexpr int R = (MAXN + kSpecThreads - 1) / kSpecThreads;  // rows / eigenvalues per thread
     constexpr int NC = (MAXN + 63) / 64;                            // 64-column chunks of a row
     // vp, wp: the reflection whose rank-2 update is still pending; vk: the
@@ -389,67 +348,115 @@ __global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __
         hi = fmax(hi, dd[i] + el + er);
         if (i + 1 < n) me2 = fmax(me2, ee[i] * ee[i]);
     }
-    __syncthreads();
-    for (int i = t; i + 1 < n; i += kSpecThreads) ee[i] = ee[i] * ee[i];
-    __syncthreads();
     const double pivmin = 1e-300 * fmax(1.0, me2);
     const double span = fmax(fabs(lo), fabs(hi));
-    lo -= 2.2e-16 * span * n + pivmin;
-    hi += 2.2e-16 * span * n + pivmin;
-    // each eigenvalue to a relative 2 eps or an absolute 4 eps |T|, whichever is larger
-    const double atol = 4.0 * 2.2e-16 * span + pivmin;
-    double* lam = prow;
-    {
-        // lanes per eigenvalue and points per lane: fill the workgroup, two
-        // interleaved recurrences per lane while a wave per SIMD suffices
-        const int g = n <= 64 ? 8 : n <= 128 ? 4 : n <= 256 ? 2 : 1;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int slot = t + r * kSpecThreads;
-            const int e = slot / g, sl = slot % g;
-            const bool live = e < n;
-            const double ev = n <= 256 ? multisect<2>(dd, ee, n, e, sl, g, lo, hi, pivmin, atol, live)
-                                       : multisect<1>(dd, ee, n, e, sl, g, lo, hi, pivmin, atol, live);
-            if (live && sl == 0) lam[e] = fabs(ev);
-        }
+    // d, e^2, the widened Gershgorin interval and the absolute tolerance
+    // (4 eps |T|) of the eigenvalues
+    for (int i = t; i < n; i += kSpecThreads) {
+        tri[i] = dd[i];
+        tri[n + i] = i + 1 < n ? ee[i] * ee[i] : 0.0;
+    }
+    if (t == 0) {
+        tri[2 * n] = lo - (2.2e-16 * span * n + pivmin);
+        tri[2 * n + 1] = hi + (2.2e-16 * span * n + pivmin);
+        tri[2 * n + 2] = pivmin;
+        tri[2 * n + 3] = 4.0 * 2.2e-16 * span + pivmin;
+    }
+}
+
+// |lambda_e| of the tridiagonal matrix for e = one per wave (ascending index):
+// multisection over the Gershgorin interval, 128 points per round (two per
+// lane, interleaved recurrences), the wave keeping the part that holds the
+// eigenvalue, until the width is 2 eps max(|a|, |b|) + atol or stops falling.
+constexpr int kBisWaves = 4;
+__global__ __launch_bounds__(64 * kBisWaves) void bisect_kernel(const double* __restrict__ tri, int n,
+                                                                double* lam) {
+    extern __shared__ double sh[];
+    double* d = sh;
+    double* e2 = sh + n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        d[i] = tri[i];
+        e2[i] = tri[n + i];
     }
     __syncthreads();
-    // rank by |lambda| descending, ties by index
-    double* sorted = vk;
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * kBisWaves + (threadIdx.x >> 6);
+    if (e >= n) return;
+    double a = tri[2 * n], b = tri[2 * n + 1];
+    const double pivmin = tri[2 * n + 2], atol = tri[2 * n + 3];
+    constexpr int NP = 2, M = 64 * NP;
+    for (int it = 0; it < 64; ++it) {
+        if (!(b - a > 2.0 * 2.2e-16 * fmax(fabs(a), fabs(b)) + atol)) break;
+        const double h = (b - a) / (M + 1);
+        double x[NP];
+        int cnt[NP];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int e = t + r * kSpecThreads;
-        if (e < n) {
-            const double mine = lam[e];
-            int rank = 0;
-            for (int jx = 0; jx < n; ++jx) {
-                const double o = lam[jx];
-                rank += (o > mine) || (o == mine && jx < e);
-            }
-            sorted[rank] = mine;
+        for (int p = 0; p < NP; ++p) x[p] = a + (double)(lane * NP + p + 1) * h;
+        sturm_counts<NP>(d, e2, n, x, pivmin, cnt);
+        double na = a, nb = b;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (cnt[p] > e) nb = fmin(nb, x[p]);
+            else na = fmax(na, x[p]);
         }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            na = fmax(na, __shfl_xor(na, o, 64));
+            nb = fmin(nb, __shfl_xor(nb, o, 64));
+        }
+        if (na == a && nb == b) break;
+        a = na;
+        b = nb;
+    }
+    if (lane == 0) lam[e] = fabs(0.5 * (a + b));
+}
+
+// Rank |lambda| descending (ties by index), normalise, and the change against
+// s_prev (one workgroup).
+constexpr int kRankThreads = 1024;
+__global__ __launch_bounds__(kRankThreads) void rank_kernel(const double* __restrict__ lam, int n,
+                                                            const double* s_prev, int n_prev,
+                                                            double* s_out, double* delta_out) {
+    __shared__ double sorted[kMaxN];
+    __shared__ double part[2][kRankThreads / 64];
+    const int t = threadIdx.x;
+    for (int e = t; e < n; e += kRankThreads) {
+        const double mine = lam[e];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double o = lam[j];
+            rank += (o > mine) || (o == mine && j < e);
+        }
+        sorted[rank] = mine;
     }
     __syncthreads();
+    auto bsum = [&](double v, double* pt) {
+        v = wave_sum(v);
+        if ((t & 63) == 0) pt[t >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kRankThreads / 64; ++w) s += pt[w];
+        return s;
+    };
     double ps = 0.0;
-    for (int i = t; i < n; i += kSpecThreads) ps += sorted[i];
-    const double total = block_sum(ps, part[pb]);
-    pb ^= 1;
-    const double inv = 1.0 / total;
+    for (int i = t; i < n; i += kRankThreads) ps += sorted[i];
+    const double inv = 1.0 / bsum(ps, part[0]);
     double dl = 0.0;
     const int nmax = n > n_prev ? n : n_prev;
-    for (int i = t; i < nmax; i += kSpecThreads) {
+    for (int i = t; i < nmax; i += kRankThreads) {
         const double si = i < n ? sorted[i] * inv : 0.0;
         const double sp = (s_prev != nullptr && i < n_prev) ? s_prev[i] : 0.0;
         if (i < n) s_out[i] = si;
         dl += (si - sp) * (si - sp);
     }
-    const double dsum = block_sum(dl, part[pb]);
+    const double dsum = bsum(dl, part[1]);
     if (t == 0) *delta_out = sqrt(dsum);
 }
 
 }  // namespace
 
-size_t spectrum_scratch_bytes(int n) { return sizeof(double) * (size_t)n * n; }
+size_t spectrum_scratch_bytes(int n) { return sizeof(double) * ((size_t)n * n + 3 * (size_t)n + 8); }
 
 Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, int n_prev,
                        double* s_out, double* delta_out, hipStream_t st) {
@@ -459,17 +466,24 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
         s.msg = "spectrum: chi must be in [1, 1024]";
         return s;
     }
+    double* tri = S + (size_t)n * n;      // d, e^2, interval, tolerance
+    double* lam = tri + 2 * (size_t)n + 4;
     auto launch = [&](auto kern, size_t tri_doubles) -> Status {
         const size_t dyn = sizeof(double) * ((size_t)kSpecWaves * n + tri_doubles);
         QRCTM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)dyn));
-        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), dyn, st, C, n, S, s_prev, n_prev, s_out,
-                           delta_out);
-        return launch_check("spectrum_kernel");
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), dyn, st, C, n, S, tri);
+        return launch_check("tridiag_kernel");
     };
-    if (n <= kLdsMaxN) return launch(spectrum_kernel<LdsSym, kLdsMaxN>, (size_t)n * (n + 1) / 2);
-    if (n <= 512) return launch(spectrum_kernel<GlobalSym, 512>, 0);
-    return launch(spectrum_kernel<GlobalSym, kMaxN>, 0);
+    if (n <= kLdsMaxN) QRCTM_TRY(launch(tridiag_kernel<LdsSym, kLdsMaxN>, (size_t)n * (n + 1) / 2));
+    else if (n <= 512) QRCTM_TRY(launch(tridiag_kernel<GlobalSym, 512>, 0));
+    else QRCTM_TRY(launch(tridiag_kernel<GlobalSym, kMaxN>, 0));
+    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)ceil_div(n, kBisWaves)), dim3(64 * kBisWaves),
+                       sizeof(double) * 2 * (size_t)n, st, tri, n, lam);
+    QRCTM_TRY(launch_check("bisect_kernel"));
+    hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(kRankThreads), 0, st, lam, n, s_prev, n_prev, s_out,
+                       delta_out);
+    return launch_check("rank_kernel");
 }
 
 }  // namespace qrctm

@@ -24,6 +24,7 @@ CTM_EINVAL, CTM_EWORKSPACE, CTM_EHIP, CTM_ENONFINITE, CTM_ESINGULAR, CTM_ESTATE 
     -1, -2, -3, -4, -5, -6)
 PREC_FP64, PREC_FP32_MFMA, PREC_BF16X6_MFMA = 0, 1, 2
 GRAD_CHECKPOINT, GRAD_FIXED_POINT = 0, 1
+QR_AUTO, QR_HOUSEHOLDER = 0, 1
 
 
 class CTMError(RuntimeError):
@@ -36,7 +37,7 @@ class CtmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int), ("n_warmup", c_int), ("k_tracked", c_int),
                 ("qr_sing_tol", c_double), ("mixed_tol", c_double), ("edge_split", c_int),
                 ("grad_mode", c_int), ("fp_tol", c_double), ("fp_max_iter", c_int),
-                ("grad_keep_yz", c_int), ("qr_reg_eps", c_double)]
+                ("grad_keep_yz", c_int), ("qr_reg_eps", c_double), ("qr_method", c_int)]
 
 
 class CtmStats(ctypes.Structure):
@@ -44,7 +45,12 @@ class CtmStats(ctypes.Structure):
                 ("last_delta", c_double), ("flops_per_step", c_double),
                 ("r_diag_ratio", c_double), ("timed_steps", c_longlong),
                 ("ms_phase", c_double * 8), ("grad_steps", c_longlong),
-                ("fp_residual", c_double)]
+                ("fp_residual", c_double), ("qr_fallbacks", c_longlong),
+                ("edge_3b_form", c_int)]
+
+EDGE_3B_FORMS = {0: "double-layer GEMM, FP64", 1: "double-layer GEMM, FP32 matrix cores",
+                 2: "double-layer GEMM as six bf16 products of split planes (FP32 accumulation)",
+                 3: "fused ket/bra split, FP64", 4: "fused ket/bra split, FP32 matrix cores"}
 
 PHASES = ("reduced_corner", "qr", "edge_3a", "edge_3b", "edge_3c", "corner", "sym_norm",
           "spectrum")
@@ -90,7 +96,7 @@ def lib():
         "ctm_last_error": (ctypes.c_char_p, [vp]),
         "ctm_destroy": (None, [vp]),
         "ctm_qr_workspace_bytes": (c_size_t, [c_int, c_int]),
-        "ctm_qr": (c_int, [vp, vp, vp, c_int, c_int, vp, c_size_t, vp]),
+        "ctm_qr": (c_int, [vp, vp, vp, c_int, c_int, c_int, vp, c_size_t, vp, ip]),
         "ctm_gemm_workspace_bytes": (c_size_t, [c_int, c_int, c_int]),
         "ctm_gemm": (c_int, [c_int, c_int, c_int, c_int, c_int, c_double, vp, c_int, vp, c_int,
                              c_double, vp, c_int, vp, c_size_t, vp]),
@@ -133,7 +139,7 @@ class ConvergenceWarning(UserWarning):
 
 def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=None, qr_sing_tol=1e-14,
                  mixed_tol=None, edge_split=None, grad_mode=None, fp_tol=None,
-                 fp_max_iter=None, grad_keep_yz=None, qr_reg_eps=None) -> CtmOpts:
+                 fp_max_iter=None, grad_keep_yz=None, qr_reg_eps=None, qr_method=None) -> CtmOpts:
     """ctm_opts with the library's defaults, overridden where an argument is given
     (k_tracked None or -1: the per-D default)."""
     o = CtmOpts()
@@ -155,6 +161,8 @@ def default_opts(precision=PREC_FP64, n_warmup=-1, k_tracked=None, qr_sing_tol=1
         o.grad_keep_yz = int(grad_keep_yz)
     if qr_reg_eps is not None:
         o.qr_reg_eps = float(qr_reg_eps)
+    if qr_method is not None:
+        o.qr_method = int(qr_method)
     return o
 
 
@@ -165,12 +173,12 @@ class Context:
                  n_warmup: int = -1, precision: int = PREC_FP64, k_tracked=None,
                  qr_sing_tol: float = 1e-14, mixed_tol=None, edge_split=None,
                  grad_mode=None, fp_tol=None, fp_max_iter=None, grad_keep_yz=None,
-                 qr_reg_eps=None):
+                 qr_reg_eps=None, qr_method=None):
         torch = _torch()
         self.device = torch.device(device)
         self.opts = default_opts(precision, n_warmup, k_tracked, qr_sing_tol, mixed_tol,
                                  edge_split, grad_mode, fp_tol, fp_max_iter, grad_keep_yz,
-                                 qr_reg_eps)
+                                 qr_reg_eps, qr_method)
         self.chi = chi
         L = lib()
         ctx = c_void_p()
@@ -293,6 +301,7 @@ class Context:
         self._c(lib().ctm_stats(self._ctx, byref(s)))
         out = {k: getattr(s, k) for k, _ in CtmStats._fields_ if k != "ms_phase"}
         out["ms_phase"] = {name: s.ms_phase[i] for i, name in enumerate(PHASES)}
+        out["edge_3b_kernel"] = EDGE_3B_FORMS.get(s.edge_3b_form, "unknown")
         return out
 
     def set_timing(self, on: bool = True):
@@ -366,8 +375,10 @@ def energy(A, ctx: "Context", h_nn, h_nnn=None, J2: float = 0.0, tol: float = 1e
     return _energy_function().apply(A, ctx, h_nn, h_nnn, J2, tol, max_steps, on_notconv)
 
 
-def qr(M):
-    """Thin QR with diag(R) >= 0 of a device matrix (m x n, m >= n) via ctm_qr."""
+def qr(M, method: int = QR_AUTO, return_used=False):
+    """Thin QR with diag(R) >= 0 of a device matrix (m x n, m >= n) via ctm_qr.
+
+    return_used: also return whether the Householder factorisation ran."""
     torch = _torch()
     M = M.to(torch.float64).contiguous()
     m, n = M.shape
@@ -375,9 +386,10 @@ def qr(M):
     R = torch.empty((n, n), dtype=torch.float64, device=M.device)
     nb = lib().ctm_qr_workspace_bytes(m, n)
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=M.device)
+    used = c_int()
     _check(lib().ctm_qr(c_void_p(M.data_ptr()), c_void_p(Q.data_ptr()), c_void_p(R.data_ptr()), m,
-                        n, c_void_p(ws.data_ptr()), nb, _stream(M.device)))
-    return Q, R
+                        n, int(method), c_void_p(ws.data_ptr()), nb, _stream(M.device), byref(used)))
+    return (Q, R, bool(used.value)) if return_used else (Q, R)
 
 
 def gemm(A, B, C=None, *, trans_a=False, trans_b=False, alpha=1.0, beta=0.0):

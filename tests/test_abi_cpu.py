@@ -105,7 +105,8 @@ def test_invalid_arguments_rejected_before_any_gpu_work():
     assert L.ctm_converge(None, 1e-10, 1, None, None) == B.CTM_EINVAL
     assert L.ctm_energy(None, None, None, 0.0, None) == B.CTM_EINVAL
     # QR shape check
-    assert L.ctm_qr(fake, fake, fake, 4, 8, fake, 1 << 20, None) == B.CTM_EINVAL
+    assert L.ctm_qr(fake, fake, fake, 4, 8, 0, fake, 1 << 20, None, None) == B.CTM_EINVAL
+    assert L.ctm_qr(fake, fake, fake, 8, 4, 5, fake, 1 << 20, None, None) == B.CTM_EINVAL
 
 
 def test_binding_refuses_without_gpu():

@@ -39,14 +39,16 @@ def _rel(x, y):
     return np.abs(x - y).max() / np.abs(y).max()
 
 
-@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("split,qr_method", [(0, P.QR_AUTO), (1, P.QR_AUTO), (1, P.QR_HOUSEHOLDER)])
 @pytest.mark.parametrize("d,D,chi,nsteps", [(2, 2, 16, 6), (2, 3, 36, 4), (2, 4, 64, 3),
                                             (2, 5, 75, 2), (2, 6, 144, 2), (2, 7, 98, 1),
                                             (2, 8, 128, 1), (2, 2, 600, 1), (2, 2, 1024, 1)])
-def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps, split):
-    print(f"steps d={d} D={D} chi={chi} edge_split={split}", flush=True)
+def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps, split, qr_method):
+    # both QR methods (Cholesky-QR2 with its fallback, and Householder) give the
+    # unique factors with diag(R) > 0, so both follow the oracle elementwise
+    print(f"steps d={d} D={D} chi={chi} edge_split={split} qr_method={qr_method}", flush=True)
     A, As, a, C, T = _oracle_setup(d, D, chi, seed=1)
-    ctx = P.Context(_dev(A), chi, n_warmup=0, edge_split=split)
+    ctx = P.Context(_dev(A), chi, n_warmup=0, edge_split=split, qr_method=qr_method)
     ctx.set_env(_dev(C), _dev(T))
     s_prev = ctm.spectrum(C)
     for i in range(nsteps):

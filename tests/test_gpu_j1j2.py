@@ -86,25 +86,36 @@ def test_j1j2_gradient_matches_gpu_finite_differences():
     ctx.close()
 
 
-def test_j1j2_fixed_point_gradient_matches_oracle():
-    d, D, chi = 2, 2, 16
-    A = inp.random_site_tensor(d, D, 5)
-    ctx = P.Context(_dev(A), chi)
-    ctx.converge(1e-14, 3000)
-    ctx.step(400)
-    C, T = [x.cpu().numpy() for x in ctx.get_env()]
-    e_ref, g_ref, n_ref = adj.energy_grad_fixed_point(A, C, T, H1, tol=1e-11, max_iter=3000,
-                                                      h_nnn=H2, J2=J2)
+def _oracle_fixed_point(A, D, chi):
+    # an elementwise fixed point of two QR steps (the fixed-point scheme's condition)
+    a = ctm.double_layer(ctm.prepare_site_tensor(A))
+    r = ctm.ctmrg(a, chi, ctm.identity_boundary_vector(D), tol=1e-14, max_steps=3000)
+    C, T = r.C, r.T
+    for _ in range(3000):
+        Cn, Tn = ctm.sym_norm(*ctm.qr_step(*ctm.sym_norm(*ctm.qr_step(C, T, a)), a))
+        dd = max(np.abs(Cn - C).max(), np.abs(Tn - T).max())
+        C, T = Cn, Tn
+        if dd < 1e-15:
+            break
+    assert dd < 1e-15, "not an elementwise fixed point"
+    return C, T
+
+
+@pytest.mark.parametrize("D,chi,seed", [(2, 8, 3), (3, 18, 4)])
+def test_j1j2_fixed_point_gradient_matches_oracle(D, chi, seed):
+    A = inp.random_site_tensor(2, D, seed)
+    C, T = _oracle_fixed_point(A, D, chi)
+    e_ref, g_ref, n_ref = adj.energy_grad_fixed_point(A, C, T, H1, tol=1e-12, h_nnn=H2, J2=J2)
     assert n_ref is not None
-    fp = P.Context(_dev(A), chi, n_warmup=0, grad_mode=P.GRAD_FIXED_POINT, fp_tol=1e-11,
-                   fp_max_iter=3000)
+    fp = P.Context(_dev(A), chi, n_warmup=0, grad_mode=P.GRAD_FIXED_POINT, fp_tol=1e-12,
+                   fp_max_iter=4000)
     fp.set_env(_dev(C), _dev(T))
     e, g = fp.energy_grad(H1, H2, J2)
     assert fp.grad_converged
+    assert abs(fp.stats()["grad_steps"] - n_ref) <= 2
     g = g.cpu().numpy()
     assert abs(e - e_ref) < 1e-12 * abs(e_ref)
     assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < 1e-9
-    ctx.close()
     fp.close()
 
 

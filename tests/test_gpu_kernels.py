@@ -54,7 +54,8 @@ def test_qr_matches_oracle(m, n):
     print(f"qr m={m} n={n}", flush=True)
     rng = np.random.default_rng(m + n)
     M = rng.standard_normal((m, n))
-    Q, R = P.qr(_dev(M))
+    Q, R, used = P.qr(_dev(M), return_used=True)
+    assert not used  # well conditioned: Cholesky-QR2
     Q, R = Q.cpu().numpy(), R.cpu().numpy()
     Qo, Ro = ctm.qr_pos(M)
     assert np.abs(np.tril(R, -1)).max() == 0.0
@@ -65,6 +66,50 @@ def test_qr_matches_oracle(m, n):
     assert np.abs(R - Ro).max() / np.abs(Ro).max() < 1e-12
 
 
+@pytest.mark.parametrize("m,n", [(1000, 37), (5184, 144), (16384, 256), (4096, 1024)])
+def test_qr_householder_method_matches_oracle(m, n):
+    print(f"qr (Householder) m={m} n={n}", flush=True)
+    rng = np.random.default_rng(m + n)
+    M = rng.standard_normal((m, n))
+    Q, R, used = P.qr(_dev(M), method=P.QR_HOUSEHOLDER, return_used=True)
+    assert used
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    Qo, Ro = ctm.qr_pos(M)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-13
+    assert np.abs(Q - Qo).max() < 1e-11
+    assert np.abs(R - Ro).max() / np.abs(Ro).max() < 1e-12
+
+
+@pytest.mark.parametrize("kappa", [1e1, 1e3, 1e7, 1e12, 1e15])
+@pytest.mark.parametrize("m,n", [(5184, 144), (16384, 256)])
+def test_qr_conditioning_extremes(m, n, kappa):
+    # M = U diag(s) V^T with singular values spread geometrically over kappa:
+    # Cholesky-QR2 takes the well-conditioned ones, the Householder kernel
+    # those it rejects (kappa^2 beyond 1/u); every result is an orthonormal Q
+    # with Q R = M to rounding, and Q, R differ from LAPACK's by at most about
+    # kappa times the rounding unit (the condition of the thin QR factors)
+    print(f"qr kappa={kappa:.0e} m={m} n={n}", flush=True)
+    rng = np.random.default_rng(int(np.log10(kappa)) + n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.geomspace(1.0, 1.0 / kappa, n)
+    M = (U * s) @ V.T
+    Q, R, used = P.qr(_dev(M), return_used=True)
+    if kappa <= 1e3:
+        assert not used          # Cholesky-QR2 accepted it
+    if kappa >= 1e12:
+        assert used              # kappa^2 beyond 1/u: the Cholesky step rejects it
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert np.abs(np.tril(R, -1)).max() == 0.0 and np.all(np.diag(R) >= 0)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-13
+    assert np.abs(Q @ R - M).max() / np.abs(M).max() < 1e-13
+    Qo, Ro = ctm.qr_pos(M)
+    bound = 1e-14 * kappa * np.sqrt(n)
+    if bound < 1e-3:
+        assert np.abs(R - Ro).max() / np.abs(Ro).max() < max(bound, 1e-12)
+        assert np.abs(Q - Qo).max() < max(bound, 1e-11)
+
+
 def test_qr_rank_deficient_columns():
     rng = np.random.default_rng(1)
     m, n = 300, 24
@@ -72,7 +117,8 @@ def test_qr_rank_deficient_columns():
     M[:, 5] = 0.0                 # zero column
     M[:, 9] = M[:, 2]             # repeated column
     M[:, 13] = -M[:, 13] * 0.0    # another zero column (negative zero)
-    Q, R = P.qr(_dev(M))
+    Q, R, used = P.qr(_dev(M), return_used=True)
+    assert used  # Cholesky-QR2 rejects it: the Householder kernel ran
     Q, R = Q.cpu().numpy(), R.cpu().numpy()
     assert np.all(np.isfinite(Q)) and np.all(np.isfinite(R))
     assert np.all(np.diag(R) >= 0)

@@ -7,9 +7,11 @@ sqrt(K) 2^-24 per contraction, and the split-BF16 form keeps every term down
 to 2^-24 with the same accumulation; the bounds below are that budget, not
 the FP64 ones.  The measured errors are reported by the benchmark.  The
 split-BF16 kernel serves products of at least 256 tiles of 128 x 128, which
-first occur at D = 6, chi = 144 (3a and 3b).  With the ket/bra-split edge
-contraction (edge_split 1) 3b runs in FP64 in every form, so the mixed forms
-are checked with both settings.
+first occur at D = 6, chi = 144 (3a and 3b) of the plain form (edge_split 0).
+With the ket/bra-split edge contraction (edge_split 1) the split 3b runs on
+the FP32 matrix cores in both mixed forms (it has no bf16 build), so the
+mixed forms are checked with both settings, and ctm_stats names the 3b
+kernel each one ran.
 """
 import numpy as np
 import pytest
@@ -154,22 +156,44 @@ def test_fp32_split_3b_close_to_fp64_split(D, chi):
 
 @pytest.mark.parametrize("D,chi", [(6, 144), (8, 256)])
 def test_mixed_energy_error_within_1e7(D, chi):
-    # the mixed forms' energy after 20 steps against 20 FP64 steps from the same
-    # environment (FP32 block sums over at most 512 of K, longer contractions
-    # split with FP64 partial sums): within 1e-7 relative
+    # the mixed forms' energy after 20 steps against 20 FP64 steps of the same
+    # 3b form from the same environment (FP32 block sums over at most 512 of K,
+    # longer contractions split with FP64 partial sums): within 1e-7 relative.
+    # FP32: the default form (split 3b); split-BF16: the plain form, whose 3b
+    # is the bf16 product of planes
     A = torch.as_tensor(inp.random_site_tensor(2, D, 1), device="cuda:0")
     h = inp.heisenberg_bond_rotated()
     ctx = P.Context(A, chi)
     ctx.step(10)
     C0, T0 = ctx.get_env()
-    ctx.step(20)
-    e64 = ctx.energy(h)
-    for prec in (P.PREC_FP32_MFMA, P.PREC_BF16X6_MFMA):
-        m = P.Context(A, chi, precision=prec, n_warmup=0)
+    for prec, split, kernel in ((P.PREC_FP32_MFMA, 1, "fused ket/bra split, FP32 matrix cores"),
+                                (P.PREC_BF16X6_MFMA, 0, "double-layer GEMM as six bf16 products")):
+        ref = P.Context(A, chi, n_warmup=0, edge_split=split)
+        ref.set_env(C0, T0)
+        ref.step(20)
+        e64 = ref.energy(h)
+        ref.close()
+        m = P.Context(A, chi, precision=prec, n_warmup=0, edge_split=split)
         m.set_env(C0, T0)
         m.step(20)
         em = m.energy(h)
-        print(f"D={D} chi={chi} prec={prec}: energy error {abs(em - e64) / abs(e64):.2e}", flush=True)
+        assert m.stats()["edge_3b_kernel"].startswith(kernel)
+        print(f"D={D} chi={chi} prec={prec} edge_split={split}: energy error "
+              f"{abs(em - e64) / abs(e64):.2e}", flush=True)
         assert abs(em - e64) < 1e-7 * abs(e64)
         m.close()
     ctx.close()
+
+
+def test_stats_name_the_3b_kernel():
+    A = _dev(inp.random_site_tensor(2, 4, 1))
+    want = {(P.PREC_FP64, 1): "fused ket/bra split, FP64",
+            (P.PREC_FP64, 0): "double-layer GEMM, FP64",
+            (P.PREC_FP32_MFMA, 1): "fused ket/bra split, FP32 matrix cores",
+            (P.PREC_FP32_MFMA, 0): "double-layer GEMM, FP32 matrix cores",
+            (P.PREC_BF16X6_MFMA, 1): "fused ket/bra split, FP32 matrix cores",
+            (P.PREC_BF16X6_MFMA, 0): "double-layer GEMM as six bf16 products"}
+    for (prec, split), name in want.items():
+        c = P.Context(A, 64, precision=prec, edge_split=split)
+        assert c.stats()["edge_3b_kernel"].startswith(name), (prec, split)
+        c.close()
