@@ -3,10 +3,11 @@
 
 Workload: C4v QR-CTMRG on a random C4v-symmetrised site tensor, d = 2, D = 6,
 chi = 144 (reduced corner 5184 x 144), FP64.  One "step" is one full QR-CTMRG
-step: reduced corner, Householder QR, T' = Q^T (T a) Q, accelerated corner,
-symmetrise/normalise and the corner-spectrum convergence measure.  The value is
-the library's default form: FP64, with the edge contraction's middle product
-(3b) done by the fused ket/bra-split kernel.
+step: reduced corner, QR (Cholesky-QR2, Householder where it is rejected),
+T' = Q^T (T a) Q, accelerated corner, symmetrise/normalise and the
+corner-spectrum convergence measure.  The value is the library's default form:
+FP64, with the edge contraction's middle product (3b) done by the fused
+ket/bra-split kernel.
 
 The environment is initialised (C4v average, double layer, boundary, standard
 warm-up step) before the timed region; W untimed steps follow; then exactly K
@@ -16,11 +17,15 @@ roofline figure is for the phase with the largest share of the step, and the
 per-kernel figures for the others follow.  The CPU baseline is the FP64 oracle
 on the host cores on a bounded sample of the same workload.
 
-Also reported (same tensor): the plain form (3b as one GEMM with the
-double-layer tensor, 2 chi^2 D^8 flops), the mixed forms (bulk contractions on
-the FP32 matrix cores, or as split-BF16 products on the bf16 matrix cores) with
-their speed-ups and energy errors against FP64, and the time of one dE/dA (k
-tracked steps, energy and the reverse pass).
+Also reported, at D = 6, chi = 144 and (block "target") at the largest
+single-GPU case D = 8, chi = 256, same tensor seed: the forms of the step,
+each with the 3b kernel the library reports for it -- the plain form (3b as
+one FP64 GEMM with the double-layer tensor, 2 chi^2 D^8 flops), the FP32 form
+(default split form on the FP32 matrix cores) and the split-BF16 form (plain
+form, 3b as six bf16 products of split planes) -- with their speed-ups over
+FP64 of the same 3b form and their energy errors against it after 20 steps
+from one environment, and the time of one dE/dA (k tracked steps, energy and
+the reverse pass).
 
 Prints ONE JSON line.
 """
@@ -157,6 +162,152 @@ def cpu_baseline(d, D, chi, seed, budget_s=20.0):
                       f"oracle's own warm-up, {el:.1f} s"}
 
 
+def _timed_steps(torch, c, steps, warmup):
+    if warmup:
+        c.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def _phases(c, nt):
+    c.set_timing(True)
+    c.step(nt)
+    st = c.stats()
+    c.set_timing(False)
+    return {k: v / st["timed_steps"] for k, v in st["ms_phase"].items()}, st
+
+
+def measure_forms(P, A, chi, C0, T0, fp64_sps, args, nt):
+    """The plain form and the mixed forms from one environment (C0, T0).
+
+    Each form: steps/s, per-phase ms, the 3b kernel the library reports, the
+    speed-up over FP64 of the same 3b form (and over the default FP64 form),
+    and the energy after args.acc_steps steps against as many FP64 steps of the
+    same 3b form from (C0, T0)."""
+    import torch
+    from synth import inputs as inp
+    h = inp.heisenberg_bond_rotated()
+    D = int(A.shape[1])
+
+    def one(precision, split):
+        c = P.Context(A, chi, precision=precision, n_warmup=0, edge_split=split)
+        c.set_env(C0, T0)
+        el = _timed_steps(torch, c, args.steps, args.warmup)
+        ms, st = _phases(c, nt)
+        c.set_env(C0, T0)
+        c.step(args.acc_steps)
+        e = c.energy(h)
+        r = {"steps_per_s": args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+             "tflops": st["flops_per_step"] * args.steps / el / 1e12, "ms_per_phase": ms,
+             "edge_3b_kernel": st["edge_3b_kernel"], "energy": e}
+        c.close()
+        torch.cuda.empty_cache()
+        return r
+
+    plain = one(P.PREC_FP64, 0)
+    plain["form"] = "FP64, 3b as one GEMM with the double-layer tensor (2 chi^2 D^8 flops)"
+    t3b = flops_3b(chi, D) / (plain["ms_per_phase"]["edge_3b"] * 1e-3) / 1e12
+    plain.update({"gemm_3b_tflops": t3b, "gemm_3b_frac_fp64_peak": t3b / FP64_MFMA_PEAK_TFLOPS,
+                  "default_form_speedup": fp64_sps / plain["steps_per_s"]})
+    split64 = one(P.PREC_FP64, 1)   # the default FP64 form again, for its energy after acc_steps
+    fp32 = one(P.PREC_FP32_MFMA, 1)
+    fp32["form"] = ("FP32: the default (split 3b) form with every contraction on the FP32 matrix "
+                    "cores (FP32 products, FP32 sums over at most 512 of K); QR, normalisation, "
+                    "spectrum FP64")
+    bf16 = one(P.PREC_BF16X6_MFMA, 0)
+    bf16["form"] = ("split-BF16: the plain form with 3a writing Y as three bf16 planes and 3b as six "
+                    "bf16 products of planes (FP32 accumulation), the smaller products on the FP32 "
+                    "matrix cores; QR, normalisation, spectrum FP64")
+    for r, ref, ref_sps in ((fp32, split64, fp64_sps), (bf16, plain, plain["steps_per_s"])):
+        r["speedup_vs_fp64_same_form"] = r["steps_per_s"] / ref_sps
+        r["speedup_vs_fp64_default_form"] = r["steps_per_s"] / fp64_sps
+        r["speedup_vs_fp64_plain_form"] = r["steps_per_s"] / plain["steps_per_s"]
+        r["energy_fp64_same_form"] = ref["energy"]
+        r["energy_rel_err_vs_fp64"] = abs(r["energy"] - ref["energy"]) / abs(ref["energy"])
+        r["accuracy_steps"] = args.acc_steps
+    return {"plain_fp64": plain, "mixed_fp32": fp32, "mixed_bf16x6": bf16,
+            "mixed_speedup_headline": {
+                "fp32_over_fp64_default_form": fp32["speedup_vs_fp64_same_form"],
+                "bf16x6_over_fp64_plain_form": bf16["speedup_vs_fp64_same_form"],
+                "fp32_over_fp64_plain_form": fp32["speedup_vs_fp64_plain_form"]}}
+
+
+def measure_grad(P, A, chi, ctx, k, keep_yz):
+    """One dE/dA (k tracked steps, energy, reverse pass) from ctx's environment."""
+    import torch
+    from synth import inputs as inp
+    h = inp.heisenberg_bond_rotated()
+    C0, T0 = ctx.get_env()
+    g = P.Context(A, chi, n_warmup=0, k_tracked=k)
+    g.set_env(C0, T0)
+    g.energy_grad(h)                       # warm-up call
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, dA = g.energy_grad(h)
+    torch.cuda.synchronize()
+    out = {"ms": 1e3 * (time.perf_counter() - t0), "k_tracked": k, "energy": e,
+           "grad_norm": float(dA.norm()), "qr_fallbacks": g.stats()["qr_fallbacks"]}
+    g.close()
+    torch.cuda.empty_cache()
+    if keep_yz:
+        # each tracked step's Y and Z kept (2 k chi^2 D^4 doubles more workspace)
+        kc = P.Context(A, chi, n_warmup=0, k_tracked=k, grad_keep_yz=1)
+        kc.set_env(C0, T0)
+        kc.energy_grad(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, dk = kc.energy_grad(h)
+        torch.cuda.synchronize()
+        out["ms_kept_yz"] = 1e3 * (time.perf_counter() - t0)
+        out["kept_yz_rel_diff"] = float((dk - dA).norm() / dA.norm())
+        kc.close()
+        del dk
+    del dA
+    torch.cuda.empty_cache()
+    return out
+
+
+def measure_target(P, inp, torch, args, nt):
+    """The largest single-GPU case, d = 2, D = 8, chi = 256 (same seed): the
+    default FP64 form with per-kernel rooflines, the plain and mixed forms, and
+    one dE/dA with k = args.k."""
+    D, chi, d = 8, 256, 2
+    steps, warmup = args.target_steps, 2
+    print(f"# target block d={d} D={D} chi={chi}", file=sys.stderr, flush=True)
+    A = torch.as_tensor(inp.random_site_tensor(d, D, args.seed), device="cuda:0")
+    t0 = time.perf_counter()
+    c = P.Context(A, chi)
+    t_init = time.perf_counter() - t0
+    el = _timed_steps(torch, c, steps, warmup)
+    sps = steps / el
+    ms, st = _phases(c, nt)
+    figs = kernel_figures(d, D, chi)
+    kern = {}
+    for k, (fl, by) in figs.items():
+        t = ms[k] * 1e-3
+        kern[k] = {"ms_per_launch": ms[k], "achieved_tflops": fl / t / 1e12,
+                   "frac_fp64_peak": fl / t / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                   "algorithmic_hbm_gbs": by / t / 1e9}
+    out = {"config": {"d": d, "D": D, "chi": chi, "seed": args.seed}, "steps": steps,
+           "warmup": warmup, "init_s": t_init, "steps_per_s": sps, "ms_per_step": 1e3 * el / steps,
+           "tflops": st["flops_per_step"] * sps / 1e12, "flops_per_step": st["flops_per_step"],
+           "ms_per_phase": ms, "kernels": kern, "edge_3b_kernel": st["edge_3b_kernel"],
+           "qr_fallbacks": st["qr_fallbacks"]}
+    C0, T0 = c.get_env()
+    sub = argparse.Namespace(steps=steps, warmup=warmup, acc_steps=args.acc_steps)
+    if not args.no_mixed:
+        out["forms"] = measure_forms(P, A, chi, C0, T0, sps, sub, nt)
+    if not args.no_grad:
+        out["grad"] = measure_grad(P, A, chi, c, args.k, keep_yz=False)
+    c.close()
+    del C0, T0
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +321,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-target", action="store_true",
+                    help="skip the d=2, D=8, chi=256 block")
+    ap.add_argument("--target-steps", type=int, default=10)
     ap.add_argument("--acc-steps", type=int, default=20)
     ap.add_argument("--k", type=int, default=10, help="tracked steps of the gradient")
     ap.add_argument("--converge-tol", type=float, default=0.0,
@@ -218,7 +372,8 @@ def main():
     ctx.set_timing(False)
     ms = {k: v / st2["timed_steps"] for k, v in st2["ms_phase"].items()}
     figs = kernel_figures(d, D, chi)
-    names = {"qr": "cooperative blocked Householder QR of the reduced corner (a6)",
+    names = {"qr": "QR of the reduced corner (a6): Cholesky-QR2 (Gram, Cholesky with R^-1, "
+                   "product M R^-1, twice), the Householder kernel idle behind it",
              "edge_3b": "fused ket/bra-split edge contraction Z = Y (A x A) (a7 3b)",
              "edge_3a": "FP64 GEMM Y = Q^T T (a7 3a)",
              "edge_3c": "FP64 GEMM T' = Z Q (a7 3c)"}
@@ -264,131 +419,19 @@ def main():
         "roofline": roof(dom),
         "roofline_kernels": {k: roof(k) for k in figs},
     }
+    st_default = ctx.stats()
+    out["edge_3b_kernel"] = st_default["edge_3b_kernel"]
+    out["qr_fallbacks"] = st_default["qr_fallbacks"]
     C0, T0 = ctx.get_env()
-    # plain form: 3b as one FP64 GEMM with the double-layer tensor
-    pctx = P.Context(A, chi, n_warmup=0, edge_split=0)
-    pctx.set_env(C0, T0)
-    if args.warmup:
-        pctx.step(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pctx.step(args.steps)
-    torch.cuda.synchronize()
-    el_p = time.perf_counter() - t0
-    pctx.set_timing(True)
-    pctx.step(nt)
-    pst = pctx.stats()
-    pctx.close()
-    ms_p = {k: v / pst["timed_steps"] for k, v in pst["ms_phase"].items()}
-    plain_sps = args.steps / el_p
-    t3b = flops_3b(chi, D) / (ms_p["edge_3b"] * 1e-3) / 1e12
-    out["plain_double_layer"] = {
-        "form": "FP64, 3b as one GEMM with the double-layer tensor (2 chi^2 D^8 flops)",
-        "steps_per_s": plain_sps, "ms_per_step": 1e3 * el_p / args.steps,
-        "tflops": pst["flops_per_step"] * plain_sps / 1e12, "ms_per_phase": ms_p,
-        "gemm_3b_tflops": t3b, "gemm_3b_frac_fp64_peak": t3b / FP64_MFMA_PEAK_TFLOPS,
-        "default_form_speedup": steps_per_s / plain_sps}
-    # mixed forms: same tensor, bulk contractions on the FP32 matrix cores or
-    # as split-BF16 products on the bf16 matrix cores; QR, normalisation and
-    # spectrum in FP64
     if not args.no_mixed:
-        h = inp.heisenberg_bond_rotated()
-        nacc = args.acc_steps
-        ctx.set_env(C0, T0)
-        ctx.step(nacc)
-        e64 = ctx.energy(h)
-        conv_ref = {}
-        for key, prec, desc in (
-                ("mixed", P.PREC_FP32_MFMA,
-                 "GEMMs and the fused split 3b on the fp32 matrix cores (FP32 products and "
-                 "accumulation); QR, normalisation, spectrum FP64"),
-                ("mixed_bf16x6", P.PREC_BF16X6_MFMA,
-                 "split-BF16 form: large GEMMs as six bf16 products of three-part operands "
-                 "with FP32 accumulation, the rest (the fused split 3b included) on the fp32 "
-                 "matrix cores; QR, normalisation, spectrum FP64")):
-            mctx = P.Context(A, chi, precision=prec, n_warmup=0)
-            mctx.set_env(C0, T0)
-            if args.warmup:
-                mctx.step(args.warmup)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            mctx.step(args.steps)
-            torch.cuda.synchronize()
-            el_m = time.perf_counter() - t0
-            mctx.set_timing(True)
-            mctx.step(nt)
-            mst = mctx.stats()
-            mctx.set_timing(False)
-            ms_m = {k: v / mst["timed_steps"] for k, v in mst["ms_phase"].items()}
-            # accuracy: the same number of steps from the same environment,
-            # energy from the FP64 energy contraction
-            mctx.set_env(C0, T0)
-            mctx.step(nacc)
-            em = mctx.energy(h)
-            conv = None
-            if args.converge_tol > 0:
-                # time to solution from the same environment: mixed steps down to
-                # mixed_tol, then FP64 steps to the tolerance, against FP64 alone
-                if "fp64" not in conv_ref:
-                    ctx.set_env(C0, T0)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    ok, n, dl = ctx.converge(args.converge_tol, args.converge_max)
-                    torch.cuda.synchronize()
-                    conv_ref["fp64"] = {"converged": ok, "steps": n, "s": time.perf_counter() - t0,
-                                        "energy": ctx.energy(h)}
-                mctx.set_env(C0, T0)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                ok, n, dl = mctx.converge(args.converge_tol, args.converge_max)
-                torch.cuda.synchronize()
-                tm = time.perf_counter() - t0
-                ec = mctx.energy(h)
-                r = conv_ref["fp64"]
-                conv = {"tol": args.converge_tol, "converged": ok, "steps": n, "s": tm,
-                        "mixed_tol": mctx.opts.mixed_tol,
-                        "fp64_steps": r["steps"], "fp64_s": r["s"], "fp64_converged": r["converged"],
-                        "speedup_time_to_solution": r["s"] / tm,
-                        "energy_rel_err_vs_fp64": abs(ec - r["energy"]) / abs(r["energy"])}
-            out[key] = {"precision": desc,
-                        "steps_per_s": args.steps / el_m, "ms_per_step": 1e3 * el_m / args.steps,
-                        "speedup_vs_fp64": (args.steps / el_m) / steps_per_s,
-                        "speedup_vs_plain_fp64": (args.steps / el_m) / plain_sps,
-                        "ms_per_phase": ms_m,
-                        "energy_fp64": e64, "energy_mixed": em,
-                        "energy_rel_err_vs_fp64": abs(em - e64) / abs(e64),
-                        "accuracy_steps": nacc,
-                        "converged_with_fp64_refinement": conv}
-            mctx.close()
-    # dE/dA: k tracked steps + energy + reverse pass from the current environment
+        out["forms"] = measure_forms(P, A, chi, C0, T0, steps_per_s, args, nt)
     if not args.no_grad:
-        gctx = P.Context(A, chi, n_warmup=0, k_tracked=args.k)
-        C0, T0 = ctx.get_env()
-        gctx.set_env(C0, T0)
-        h = inp.heisenberg_bond_rotated()
-        gctx.energy_grad(h)                       # warm-up call
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e, g = gctx.energy_grad(h)
-        torch.cuda.synchronize()
-        out["grad"] = {"ms": 1e3 * (time.perf_counter() - t0), "k_tracked": args.k,
-                       "energy": e, "grad_norm": float(g.norm())}
-        gctx.close()
-        # the same with each tracked step's Y and Z kept (2 k chi^2 D^4 doubles
-        # more workspace, no recomputation of 3a and 3b in the reverse sweep)
-        kctx = P.Context(A, chi, n_warmup=0, k_tracked=args.k, grad_keep_yz=1)
-        kctx.set_env(C0, T0)
-        kctx.energy_grad(h)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ek, gk = kctx.energy_grad(h)
-        torch.cuda.synchronize()
-        out["grad"]["ms_kept_yz"] = 1e3 * (time.perf_counter() - t0)
-        out["grad"]["kept_yz_rel_diff"] = float((gk - g).norm() / g.norm())
-        kctx.close()
-        del gk
-        torch.cuda.empty_cache()
+        out["grad"] = measure_grad(P, A, chi, ctx, args.k, keep_yz=True)
     ctx.close()
+    del C0, T0
+    torch.cuda.empty_cache()
+    if not args.no_target:
+        out["target"] = measure_target(P, inp, torch, args, nt)
     if args.chi_sweep:
         # time per step against chi (same tensor, default form), cf. the paper's Fig. 2b
         sweep = []

@@ -105,7 +105,7 @@ typedef struct ctm_opts {
                            reduced corner gives a finite (regularised) gradient
                            instead of CTM_ESINGULAR                                   */
     int qr_method;      /* QR of the reduced corner (QR-CTMRG paragraph): CTM_QR_AUTO =
-                           Cholesky-QR2 (Gram matrix, Cholesky, triangular solves, twice;
+                           Cholesky-QR2 (Gram matrix, Cholesky, product with R^-1, twice;
                            the same unique factors with diag(R) > 0), with the
                            Householder factorisation run instead on the GPU whenever the
                            Cholesky step rejects the matrix (a non-positive pivot,

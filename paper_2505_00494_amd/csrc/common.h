@@ -98,6 +98,8 @@ struct GemmDesc {
     long long ldb16 = 0, pB16 = 0;
     unsigned short* C16 = nullptr;
     long long pC16 = 0;
+    // if non-null: the product is skipped (C untouched) unless *gate == 0
+    const int* gate = nullptr;
 };
 
 // Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the

@@ -1374,17 +1374,28 @@ size_t ctm_qr_workspace_bytes(int m, int n) {
     return qr_scratch_layout(m, n).total;
 }
 
-int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void* ws,
-           size_t ws_bytes, void* stream, int* used_householder) {
-    if (!M || !Q || !R) return fail(nullptr, CTM_EINVAL, "NULL argument");
-    if (m < n || n < 1) return fail(nullptr, CTM_EINVAL, "need m >= n >= 1");
-    if (method != CTM_QR_AUTO && method != CTM_QR_HOUSEHOLDER)
-        return fail(nullptr, CTM_EINVAL, "unknown QR method");
+}  // extern "C"
+
+namespace {
+
+__global__ void zero_int_word_kernel(int* w) { *w = 0; }
+
+// One thin QR on scratch ws (ws_bytes), as ctm_qr does it:
+// the error word cleared by a kernel, the exchange buffers by qr_pos (epoch
+// 0), then the factorisation; reads back the error word and the fallback count.
+int run_qr(const double* M, double* Q, double* R, int m, int n, int method, void* ws,
+           size_t ws_bytes, hipStream_t st, int* used_householder) {
     return guarded(nullptr, [&]() -> Status {
-        hipStream_t st = static_cast<hipStream_t>(stream);
         const QrScratch L = qr_scratch_layout(m, n);
+        if (ws == nullptr || ws_bytes < L.total) {
+            Status s;
+            s.code = CTM_EWORKSPACE;
+            s.msg = "qr: workspace missing or smaller than ctm_qr_workspace_bytes";
+            return s;
+        }
         int* err = reinterpret_cast<int*>(static_cast<char*>(ws) + L.off_err);
-        if (ws_bytes >= L.total) QRCTM_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+        hipLaunchKernelGGL(zero_int_word_kernel, dim3(1), dim3(1), 0, st, err);
+        QRCTM_TRY(launch_check("zero_int_word_kernel"));
         QRCTM_TRY(qr_pos(M, Q, R, m, n, ws, ws_bytes, st, nullptr, err, 0,
                          method == CTM_QR_HOUSEHOLDER ? kQrHouseholder : kQrAuto));
         int h = 0;
@@ -1395,11 +1406,31 @@ int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void
         if (h != 0) {
             Status s;
             s.code = CTM_EHIP;
-            s.msg = "qr: a grid barrier of the cooperative factorisation timed out";
+            s.msg = "qr: an exchange between the workgroups of the Householder factorisation timed out";
             return s;
         }
         return Status{};
     });
+}
+
+int check_qr_args(const double* M, double* Q, double* R, int m, int n, int method) {
+    if (!M || !Q || !R) return fail(nullptr, CTM_EINVAL, "NULL argument");
+    if (m < n || n < 1) return fail(nullptr, CTM_EINVAL, "need m >= n >= 1");
+    if (method != CTM_QR_AUTO && method != CTM_QR_HOUSEHOLDER)
+        return fail(nullptr, CTM_EINVAL, "unknown QR method");
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void* ws,
+           size_t ws_bytes, void* stream, int* used_householder) {
+    const int bad = check_qr_args(M, Q, R, m, n, method);
+    if (bad) return bad;
+    return run_qr(M, Q, R, m, n, method, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                  used_householder);
 }
 
 size_t ctm_gemm_workspace_bytes(int M, int N, int K) {

@@ -38,6 +38,7 @@ struct KArgs {
     int partial;       // 1: write raw sums to C + split*M*N (plain M x N)
     unsigned short* C16;  // non-null: the result split into three bf16 planes,
     long long pC16;       // plane s at C16[s pC16 + map(m, n)] (alpha only)
+    const int* gate;      // non-null: skip unless *gate == 0
 };
 
 // Matrix-core operation per compute type.  FP64: v_mfma_f64_16x16x4_f64; FP32:
@@ -71,6 +72,7 @@ __device__ __forceinline__ long long out_index(const OutMap& mp, long long m, lo
 
 template <class CT, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs p) {
+    if (p.gate != nullptr && *p.gate != 0) return;
     typedef typename Mma<CT>::acc_t acc_t;
     constexpr int NWN = BN / WN;
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
@@ -250,7 +252,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
 // Sum of split-K partials, then the output map / alpha / beta.
 __global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits, long long M,
                                      long long N, double* C, OutMap mp, double alpha,
-                                     double beta) {
+                                     double beta, const int* gate) {
+    if (gate != nullptr && *gate != 0) return;
     const long long MN = M * N;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < MN;
          e += (long long)gridDim.x * blockDim.x) {
@@ -369,6 +372,7 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
     a.kchunk = pl.kchunk;
     a.C16 = g.prec == 2 ? g.C16 : nullptr;
     a.pC16 = g.pC16;
+    a.gate = g.gate;
     if (a.C16 && (pl.splits > 1 || g.beta != 0.0)) {
         s.code = -1;
         s.msg = "gemm_f64: a split result needs an unsplit K and beta = 0";
@@ -405,7 +409,7 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
         const int blocks = (int)std::min<long long>(ceil_div(MN, 256), 4096);
         hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, st,
                            static_cast<const double*>(splitk_ws), pl.splits, g.M, g.N, g.C, g.map,
-                           g.alpha, g.beta);
+                           g.alpha, g.beta, g.gate);
         QRCTM_TRY(launch_check("splitk_reduce_kernel"));
     }
     return s;

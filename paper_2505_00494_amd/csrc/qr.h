@@ -12,10 +12,9 @@ struct QrScratch {
 
 // Cholesky-QR2 (qr_chol.hip): scratch layout relative to QrScratch::off_chol.
 struct CholQrScratch {
-    size_t off_Q1, off_part, off_G, off_R1, off_R2, off_W1, off_W2, off_work, off_stats, off_state,
-        off_cnt;
-    int cnt_words;
-    size_t total;
+    size_t off_Q1, off_part, off_G, off_R1, off_R2, off_Ri, off_W, off_work, off_stats, off_state,
+        off_splitk;
+    size_t splitk_bytes, total;
 };
 bool cholqr_supported(int m, int n);
 CholQrScratch cholqr_scratch_layout(int m, int n);

@@ -712,13 +712,7 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
     unsigned long long* fallbacks = reinterpret_cast<unsigned long long*>(base + S.off_fallbacks);
     if (chol) {
         const CholQrScratch C = cholqr_scratch_layout(m, n);
-        char* cb = base + S.off_chol;
-        if (e == 0) {  // the Gram kernel's tile tickets start at zero
-            hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(256), 0, st,
-                               reinterpret_cast<u64*>(cb + C.off_cnt), (long long)ceil_div(C.cnt_words, 2));
-            QRCTM_TRY(launch_check("clear_words_kernel"));
-        }
-        QRCTM_TRY(cholqr2(M, Q, R, m, n, cb, C, a.ratio, &run_if, st));
+        QRCTM_TRY(cholqr2(M, Q, R, m, n, base + S.off_chol, C, a.ratio, &run_if, st));
     }
     unsigned tag_base = (unsigned)e * kQrTagSpan;
     void* args[] = {(void*)&a.M,    (void*)&a.m,     (void*)&a.n,   (void*)&a.A,

@@ -8,8 +8,13 @@
   1e-10, and dE/dA through k = 10 tracked steps (the benchmark's gradient)
   agrees with the oracle's reverse mode entry by entry to 1e-9 in norm.
 * Against central differences of the GPU's own forward pass on 32 seeded
-  entries of A (h = 1e-6, both schemes of the differentiated function
-  E_k(P(A); C0, T0) with k = 10), to 1e-6.
+  entries of A (the differentiated function E_k(P(A); C0, T0), k = 10).  The
+  energy after ten steps carries a rounding noise of a few 1e-15 (tens of
+  ulps; the step map amplifies rounding), so a central difference has a noise
+  floor of about that over 2h: at h = 1e-6 it is ~1e-6 of the gradient
+  entries (measured 1.25e-6), at h = 1e-5 ten times less, with the truncation
+  error (h^2) still far below.  The check is 1e-6 at h = 1e-5, and 2.5e-6 at
+  h = 1e-6 (the noise floor plus margin).
 """
 import json
 import os
@@ -79,14 +84,15 @@ def test_d6_chi144_gradient_matches_gpu_finite_differences():
         return ctx.energy(H)
 
     idx = inp.fd_entries(d, D, seed, n=32)
-    fd = []
-    for i in idx:
-        Ap, Am = A.ravel().copy(), A.ravel().copy()
-        Ap[i] += 1e-6
-        Am[i] -= 1e-6
-        fd.append((energy(Ap.reshape(A.shape)) - energy(Am.reshape(A.shape))) / 2e-6)
-    fd = np.array(fd)
-    err = np.linalg.norm(fd - gf[idx]) / np.linalg.norm(gf[idx])
-    print(f"FD (32 entries, h = 1e-6) relative error {err:.3e}", flush=True)
-    assert err < 1e-6
+    for h, bar in ((1e-5, 1e-6), (1e-6, 2.5e-6)):
+        fd = []
+        for i in idx:
+            Ap, Am = A.ravel().copy(), A.ravel().copy()
+            Ap[i] += h
+            Am[i] -= h
+            fd.append((energy(Ap.reshape(A.shape)) - energy(Am.reshape(A.shape))) / (2 * h))
+        fd = np.array(fd)
+        err = np.linalg.norm(fd - gf[idx]) / np.linalg.norm(gf[idx])
+        print(f"FD (32 entries, h = {h:.0e}) relative error {err:.3e}", flush=True)
+        assert err < bar, h
     ctx.close()

@@ -1,8 +1,9 @@
 """Forward and adjoint at d = 2, D = 8, chi = 256 against the oracle's figures.
 
-The oracle needs minutes and ~40 GB at this size, so its results are stored
-in tests/golden/qrctm_d2_D8_chi256.json by tests/golden/make_qrctm_d8_golden.py
-(which calls only oracle/ and synth/).  Both sides start from the same seeded
+The oracle needs half an hour and ~40 GB at this size, so its results are
+stored in tests/golden/qrctm_d2_D8_chi256.json by
+tests/golden/make_qrctm_golden.py (which calls only oracle/ and synth/):
+three QR steps after the warm-up, then dE/dA through k = 4 tracked steps.  Both sides start from the same seeded
 tensor and run their own initialisation and warm-up step; the warm-up keeps
 the 256 largest |lambda| of a 4096 x 4096 enlarged corner, whose spectrum has
 a relative gap of 2e-5 at the cut, so the kept subspace is the same and the

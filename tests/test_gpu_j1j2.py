@@ -144,3 +144,25 @@ def test_j1j2_large_against_stored_oracle(name):
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-9
         assert abs(np.linalg.norm(gf) - gd["grad_norm"]) < 1e-9 * gd["grad_norm"]
     ctx.close()
+
+
+def test_lbfgs_lowers_the_j1j2_energy():
+    # the project's own minimiser (paper_2505_00494_amd.optim) on the J1-J2
+    # energy: every accepted step satisfies the Armijo condition, so the energy
+    # falls monotonically; the environment of each accepted step is reused
+    from paper_2505_00494_amd import optim
+    A0 = inp.random_site_tensor(2, 2, 6)
+    ctx = P.Context(_dev(A0), 16, k_tracked=4)
+    ctx.converge(1e-10, 300)
+    res = optim.lbfgs(ctx, A0, H1, H2, J2, iters=6, tol=1e-10, max_steps=300)
+    es = [h.energy for h in res.history]
+    print("L-BFGS energies:", es, flush=True)
+    assert len(es) >= 4
+    assert all(b < a for a, b in zip(es, es[1:]))
+    assert es[-1] < es[0]
+    # the reported energy is that of the returned tensor from a fresh context
+    chk = P.Context(_dev(res.A), 16)
+    chk.converge(1e-10, 600)
+    assert abs(chk.energy(H1, H2, J2) - res.energy) < 1e-6
+    ctx.close()
+    chk.close()
