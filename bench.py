@@ -49,6 +49,7 @@ HBM_PEAK_GBS = 8000.0
 # Sources whose change makes a stored traffic measurement stale, per kernel.
 TRAFFIC_SOURCES = {
     "qr": ("paper_2505_00494_amd/csrc/qr.hip", "paper_2505_00494_amd/csrc/qr.h",
+           "paper_2505_00494_amd/csrc/qr_chol.hip", "paper_2505_00494_amd/csrc/gemm.hip",
            "paper_2505_00494_amd/csrc/common.h"),
     "edge_3b": ("paper_2505_00494_amd/csrc/edge_split.hip", "paper_2505_00494_amd/csrc/edge_split.h",
                 "paper_2505_00494_amd/csrc/common.h"),

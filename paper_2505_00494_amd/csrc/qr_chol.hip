@@ -214,6 +214,14 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
                 const int e = e0 + u * kCholThreads;
                 if (e >= nn) continue;
                 const int gi = e / n, gj = e - gi * n;
+                if (pass == 2) {
+                    // the first-order factors (kept if max |G - I| <= 1e-8, else
+                    // overwritten below): R2 = I + E_u, R2^{-1} = I - E_u, E_u the
+                    // upper triangle of E = G - I with half its diagonal
+                    const double x = gj > gi ? v[u] : (gj == gi ? 0.5 * (v[u] - 1.0) : 0.0);
+                    R[e] = (gi == gj ? 1.0 : 0.0) + x;
+                    Ri[e] = (gi == gj ? 1.0 : 0.0) - x;
+                }
                 if (gj < gi) continue;
                 if (!isfinite(v[u])) nf = 1;
                 dv = fmax(dv, fabs(v[u] - (gi == gj ? 1.0 : 0.0)));
@@ -237,16 +245,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
         }
     }
     __syncthreads();
-    if (pass == 2 && dev_max <= kFirstOrderMaxDev) {
-        // R2 = I + E_u and R2^{-1} = I - E_u (E_u: upper triangle of E = G - I
-        // with half its diagonal), both exact to |E|^2
-        for (int e = tid; e < nn; e += kCholThreads) {
-            const int gi = e / n, gj = e - gi * n;
-            const double g = G[e];
-            const double x = gj > gi ? g : (gj == gi ? 0.5 * (g - 1.0) : 0.0);
-            R[e] = (gi == gj ? 1.0 : 0.0) + x;
-            Ri[e] = (gi == gj ? 1.0 : 0.0) - x;
-        }
+    if (pass == 2 && dev_max <= kFirstOrderMaxDev) {  // |E|^2 below the rounding unit
         if (tid == 0) *state = bad ? 2 : 0;
         return;
     }
@@ -457,13 +456,26 @@ __global__ __launch_bounds__(256) void rprod_kernel(const double* __restrict__ R
     if (q > nblk) return;
     int I, J;
     tile_of(q, nb, I, J);
+    // k over [16 I, 16 (J + 1)), eight MFMA steps per batch with their 16 loads
+    // issued together (indices clamped into the matrices, values masked)
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = I * kB; k0 < min(n, (J + 1) * kB); k0 += 4) {
-        const int k = k0 + kl;
-        const int ri = I * kB + cl, cj = J * kB + cl;
-        const double a = (k < n && ri < n) ? R2[(size_t)ri * n + k] : 0.0;
-        const double b = (k < n && cj < n) ? R1[(size_t)k * n + cj] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    const int kend = min(n, (J + 1) * kB);
+    const int ri = min(I * kB + cl, n - 1), cj = min(J * kB + cl, n - 1);
+    const bool rok = I * kB + cl < n, cok = J * kB + cl < n;
+    for (int k0 = I * kB; k0 < kend; k0 += 32) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = min(k0 + 4 * u + kl, n - 1);
+            a[u] = R2[ri * n + k];
+            b[u] = R1[k * n + cj];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool kok = k0 + 4 * u + kl < kend;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(kok && rok ? a[u] : 0.0, kok && cok ? b[u] : 0.0,
+                                                       acc, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
