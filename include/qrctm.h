@@ -299,6 +299,23 @@ int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void
            size_t ws_bytes, void* stream, int* used_householder);
 
 /*
+ * ctm_qr_noalloc: ctm_qr for callers that cannot allocate device memory (code
+ *   under stream capture, tight serving loops, hosts that forbid allocation):
+ *   the same factorisation and result, with its scratch in a fixed array of
+ *   ctm_qr_noalloc_max_bytes() (64 MiB) that the library holds on every GPU it
+ *   runs on until the process ends.  Nothing is allocated on any call.  The
+ *   caller passes M, Q, R (device) as for ctm_qr.  Sizes whose scratch
+ *   (ctm_qr_workspace_bytes(m, n)) exceeds the array fail with CTM_EWORKSPACE
+ *   before any GPU work (e.g. 5184 x 144 and 9604 x 196 fit, 16384 x 256 does
+ *   not).  All calls on one GPU share that GPU's array, whose contents persist
+ *   from call to call: calls that overlap on one GPU (other streams, other
+ *   threads) race and must be serialised by the caller.  Synchronises stream.
+ */
+size_t ctm_qr_noalloc_max_bytes(void);
+int ctm_qr_noalloc(const double* M, double* Q, double* R, int m, int n, int method, void* stream,
+                   int* used_householder);
+
+/*
  * ctm_gemm: C = alpha * op(A) op(B) + beta * C, FP64 on the matrix cores (the
  *   kernel behind every contraction of the step).
  *   op(A) is M x K: trans_a = 0 -> A[m*lda + k], 1 -> A[k*lda + m].

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1380,7 +1381,7 @@ namespace {
 
 __global__ void zero_int_word_kernel(int* w) { *w = 0; }
 
-// One thin QR on scratch ws (ws_bytes), as ctm_qr does it:
+// One thin QR on scratch ws (ws_bytes), as ctm_qr and ctm_qr_noalloc do it:
 // the error word cleared by a kernel, the exchange buffers by qr_pos (epoch
 // 0), then the factorisation; reads back the error word and the fallback count.
 int run_qr(const double* M, double* Q, double* R, int m, int n, int method, void* ws,
@@ -1421,6 +1422,40 @@ int check_qr_args(const double* M, double* Q, double* R, int m, int n, int metho
     return 0;
 }
 
+// Scratch of ctm_qr_noalloc: a fixed array in device memory, one copy per GPU,
+// held until the process ends.  Its host-side name is not a device address;
+// kernels get the address hipGetSymbolAddress returns for each device, taken
+// once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+Status noalloc_scratch(void** out) {
+    int dev = -1;
+    QRCTM_HIP(hipGetDevice(&dev));
+    Status s;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        s.code = CTM_EINVAL;
+        s.msg = "ctm_qr_noalloc: device index beyond the library's table";
+        return s;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        QRCTM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (p == nullptr) {
+            s.code = CTM_EHIP;
+            s.msg = "ctm_qr_noalloc: no device address for the scratch array";
+            return s;
+        }
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1430,6 +1465,26 @@ int ctm_qr(const double* M, double* Q, double* R, int m, int n, int method, void
     const int bad = check_qr_args(M, Q, R, m, n, method);
     if (bad) return bad;
     return run_qr(M, Q, R, m, n, method, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                  used_householder);
+}
+
+size_t ctm_qr_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int ctm_qr_noalloc(const double* M, double* Q, double* R, int m, int n, int method, void* stream,
+                   int* used_householder) {
+    const int bad = check_qr_args(M, Q, R, m, n, method);
+    if (bad) return bad;
+    const size_t need = qr_scratch_layout(m, n).total;
+    if (need > kNoAllocScratchBytes)
+        return fail(nullptr, CTM_EWORKSPACE,
+                    "ctm_qr_noalloc: an " + std::to_string(m) + " x " + std::to_string(n) +
+                        " factorisation needs " + std::to_string(need) +
+                        " bytes of scratch, more than the fixed " +
+                        std::to_string(kNoAllocScratchBytes) + " (use ctm_qr with a workspace)");
+    void* ws = nullptr;
+    const int rc = guarded(nullptr, [&]() -> Status { return noalloc_scratch(&ws); });
+    if (rc != 0) return rc;
+    return run_qr(M, Q, R, m, n, method, ws, kNoAllocScratchBytes, static_cast<hipStream_t>(stream),
                   used_householder);
 }
 

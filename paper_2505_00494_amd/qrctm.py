@@ -97,6 +97,8 @@ def lib():
         "ctm_destroy": (None, [vp]),
         "ctm_qr_workspace_bytes": (c_size_t, [c_int, c_int]),
         "ctm_qr": (c_int, [vp, vp, vp, c_int, c_int, c_int, vp, c_size_t, vp, ip]),
+        "ctm_qr_noalloc_max_bytes": (c_size_t, []),
+        "ctm_qr_noalloc": (c_int, [vp, vp, vp, c_int, c_int, c_int, vp, ip]),
         "ctm_gemm_workspace_bytes": (c_size_t, [c_int, c_int, c_int]),
         "ctm_gemm": (c_int, [c_int, c_int, c_int, c_int, c_int, c_double, vp, c_int, vp, c_int,
                              c_double, vp, c_int, vp, c_size_t, vp]),
@@ -389,6 +391,23 @@ def qr(M, method: int = QR_AUTO, return_used=False):
     used = c_int()
     _check(lib().ctm_qr(c_void_p(M.data_ptr()), c_void_p(Q.data_ptr()), c_void_p(R.data_ptr()), m,
                         n, int(method), c_void_p(ws.data_ptr()), nb, _stream(M.device), byref(used)))
+    return (Q, R, bool(used.value)) if return_used else (Q, R)
+
+
+def qr_noalloc(M, Q=None, R=None, method: int = QR_AUTO, return_used=False):
+    """ctm_qr_noalloc: the same thin QR with the library's fixed scratch (no
+    allocation inside the call; Q and R may be passed in preallocated)."""
+    torch = _torch()
+    if M.dtype != torch.float64 or not M.is_contiguous():
+        raise ValueError("M must be a contiguous float64 device tensor")
+    m, n = M.shape
+    if Q is None:
+        Q = torch.empty((m, n), dtype=torch.float64, device=M.device)
+    if R is None:
+        R = torch.empty((n, n), dtype=torch.float64, device=M.device)
+    used = c_int()
+    _check(lib().ctm_qr_noalloc(c_void_p(M.data_ptr()), c_void_p(Q.data_ptr()), c_void_p(R.data_ptr()),
+                                m, n, int(method), _stream(M.device), byref(used)))
     return (Q, R, bool(used.value)) if return_used else (Q, R)
 
 
