@@ -271,6 +271,59 @@ def measure_grad(P, A, chi, ctx, k, keep_yz):
     return out
 
 
+def measure_lbfgs(P, inp, torch, args):
+    """The J1-J2 workload at d = 2, D = 7, chi = 196, J2/J1 = 0.5: ten L-BFGS
+    steps of the library's own minimiser (paper_2505_00494_amd.optim) from the
+    symmetrised random tensor, each energy and gradient from the fixed-point
+    scheme at the converged environment (the checkpointed scheme where the
+    environment is not a fixed point), the environment reused between accepted
+    steps; then the energy of the final tensor in FP64 and in the mixed FP32
+    form from the same environment, and their relative difference."""
+    from paper_2505_00494_amd import optim
+    D, chi, d, J2 = 7, 196, 2, 0.5
+    h1, h2 = inp.heisenberg_bond_rotated(), inp.heisenberg_bond()
+    print(f"# L-BFGS block d={d} D={D} chi={chi} J2={J2}", file=sys.stderr, flush=True)
+    A0 = inp.random_site_tensor(d, D, args.seed)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    ctx = P.Context(torch.as_tensor(A0, device=dev), chi, grad_mode=P.GRAD_FIXED_POINT)
+    fb = P.Context(torch.as_tensor(A0, device=dev), chi, n_warmup=0)
+    ok, steps0, dl0 = ctx.converge(args.lbfgs_tol, args.lbfgs_max_steps)
+
+    def cb(r):
+        print(f"# L-BFGS it {r.it}: E {r.energy:.12f} |g| {r.grad_norm:.3e} step {r.step:.3e} "
+              f"evals {r.evals} env steps {r.env_steps} delta {r.env_delta:.2e} "
+              f"scheme {r.grad_scheme} ({r.seconds:.1f} s)", file=sys.stderr, flush=True)
+
+    res = optim.lbfgs(ctx, A0, h1, h2, J2, iters=args.lbfgs_iters, tol=args.lbfgs_tol,
+                      max_steps=args.lbfgs_max_steps, fallback_ctx=fb, callback=cb)
+    el = time.perf_counter() - t0
+    C1, T1 = ctx.get_env()
+    ctx.close()
+    fb.close()
+    torch.cuda.empty_cache()
+    At = torch.as_tensor(np.ascontiguousarray(res.A), device=dev)
+    energies = {}
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed_fp32", P.PREC_FP32_MFMA)):
+        c = P.Context(At, chi, n_warmup=0, precision=prec)
+        c.set_env(C1, T1)
+        okc, st, dlc = c.converge(args.lbfgs_tol, args.lbfgs_max_steps)
+        energies[name] = {"energy": c.energy(h1, h2, J2), "converged": okc, "steps": st,
+                          "delta": dlc}
+        c.close()
+        torch.cuda.empty_cache()
+    e64, e32 = energies["fp64"]["energy"], energies["mixed_fp32"]["energy"]
+    return {"config": {"d": d, "D": D, "chi": chi, "J2": J2, "seed": args.seed,
+                       "iters": args.lbfgs_iters, "tol": args.lbfgs_tol,
+                       "max_steps": args.lbfgs_max_steps},
+            "initial_env": {"converged": ok, "steps": steps0, "delta": dl0},
+            "seconds": el,
+            "history": [dict(r.__dict__) for r in res.history],
+            "final_energy": res.energy,
+            "final_energy_fp64_vs_mixed_fp32": energies,
+            "mixed_energy_rel_err": abs(e32 - e64) / abs(e64)}
+
+
 def measure_target(P, inp, torch, args, nt):
     """The largest single-GPU case, d = 2, D = 8, chi = 256 (same seed): the
     default FP64 form with per-kernel rooflines, the plain and mixed forms, and
@@ -332,6 +385,11 @@ def main():
     ap.add_argument("--converge-max", type=int, default=600)
     ap.add_argument("--chi-sweep", type=str, default="",
                     help="comma-separated chi values: also time the default form at each")
+    ap.add_argument("--lbfgs", action="store_true",
+                    help="also run ten L-BFGS steps on the J1-J2 energy at D=7, chi=196")
+    ap.add_argument("--lbfgs-iters", type=int, default=10)
+    ap.add_argument("--lbfgs-tol", type=float, default=1e-10)
+    ap.add_argument("--lbfgs-max-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -433,6 +491,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_target:
         out["target"] = measure_target(P, inp, torch, args, nt)
+    if args.lbfgs:
+        out["lbfgs"] = measure_lbfgs(P, inp, torch, args)
     if args.chi_sweep:
         # time per step against chi (same tensor, default form), cf. the paper's Fig. 2b
         sweep = []
