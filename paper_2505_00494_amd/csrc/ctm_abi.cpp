@@ -275,8 +275,10 @@ constexpr int kPhases = 8;  // reduced corner, QR, 3a, 3b, 3c, corner, sym/norm,
 // largest relative change of (C, T) under two QR steps that the fixed-point
 // gradient accepts as a fixed point
 constexpr double kFpMaxResidual = 1e-8;
-// largest QR grid (workgroups) that runs beside the corner spectrum without
-// waiting for it (measured: grids of 162 and 225 never did, 240 and 256 did)
+// largest grid (workgroups) of a cooperative Householder QR that runs beside
+// the corner spectrum without waiting for it (measured: grids of 162 and 225
+// never did, 240 and 256 did).  Behind Cholesky-QR2 the Householder kernel is
+// an ordinary launch and nothing waits for the spectrum.
 constexpr int kQrGridBeside = 224;
 
 // small-scalar slots (doubles) inside Plan::small
@@ -583,7 +585,8 @@ Status qr_step_once(ctm_ctx* c) {
         QRCTM_HIP(hipEventRecord(c->ev_sp[0], c->aux));
         QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
         QRCTM_HIP(hipEventRecord(c->ev_sp[1], c->aux));
-    } else if (qr_grid(chi * c->sh.Dab, chi) <= kQrGridBeside) {
+    } else if (c->opts.qr_method != CTM_QR_HOUSEHOLDER ||
+               qr_grid(chi * c->sh.Dab, chi) <= kQrGridBeside) {
         QRCTM_TRY(launch_owed_spectrum(c, c->ev_normed));
     }
     c->last_slot = slot;

@@ -30,15 +30,16 @@ constexpr int kQrHouseholder = 1;  // Householder only
 
 QrScratch qr_scratch_layout(int m, int n);
 bool qr_fits(int m, int n);
-// Workgroups of the cooperative launch for an m x n factorisation (all of them
+// Workgroups of the Householder kernel for an m x n factorisation (all of them
 // must be resident at once).
 int qr_grid(int m, int n);
 // Q (m x n) and R (n x n) from M (m x n), all device, row-major.  diag_ratio_dev
 // (device, may be null) receives min|R_ii| / max|R_ii|; err_dev (device int, may
 // be null) is or-ed with 2 if a grid barrier timed out.  Q may alias M.  No
 // scratch but ws.  method kQrAuto: Cholesky-QR2 where supported, the
-// cooperative Householder kernel (launched behind it, idle unless needed) where
-// it rejects the factorisation; kQrHouseholder: the Householder kernel only.
+// Householder kernel (an ordinary launch behind it, idle unless needed) where
+// it rejects the factorisation; kQrHouseholder: the Householder kernel only
+// (a cooperative launch).
 // epoch numbers the launches on one ws: 0 (always allowed) clears the
 // exchange buffers first; a caller that passes 0, 1, 2, ... to consecutive
 // launches on the same ws (in stream order) has them cleared only when the

@@ -36,8 +36,10 @@
 // which it must on their first use and whenever the base starts over).  Writers and readers use relaxed agent-scope atomics, so each word
 // is read whole; a reader polls its words until both carry the expected tag.
 // Every exchange only waits for data of the previous one, all workgroups are
-// co-resident (cooperative launch), and every wait is bounded (on timeout an
-// error bit is set and the kernel runs to its end).  Exchange buffers are
+// co-resident (a cooperative launch; behind Cholesky-QR2, where it rarely runs,
+// an ordinary launch of at most one workgroup per CU on an otherwise idle
+// device), and every wait is bounded (on timeout an error bit is set and the
+// kernel runs to its end).  Exchange buffers are
 // double-buffered where a fast workgroup could otherwise overwrite data a slow
 // one has not read: before a workgroup writes exchange t + 2 into a buffer it
 // has read exchange t + 1 from every workgroup, which each sent only after
@@ -719,6 +721,24 @@ Status qr_pos(const double* M, double* Q, double* R, int m, int n, void* ws, siz
                     (void*)&a.Q,    (void*)&a.R,     (void*)&a.part, (void*)&a.rowbuf,
                     (void*)&a.red,  (void*)&a.redsum, (void*)&a.ratio, (void*)&a.err,
                     (void*)&tag_base, (void*)&run_if, (void*)&fallbacks};
+    if (run_if != nullptr) {
+        // behind Cholesky-QR2 the kernel returns at once unless the state word
+        // asks for it: an ordinary launch, since a cooperative one drains the
+        // device before and after it (about 11 us each way at 5184 x 144).  When
+        // it does run, its grid (at most one workgroup per CU, fewer than the
+        // CUs) is placed at once on the otherwise idle device, and every wait in
+        // it is bounded: a workgroup that could not be placed would cost a
+        // time-out error, not a hang
+        if (n > kQrThreads)
+            hipLaunchKernelGGL(qr_kernel<true>, dim3(L.P), dim3(kQrThreads), L.lds_bytes, st, a.M, a.m,
+                               a.n, a.A, a.Q, a.R, a.part, a.rowbuf, a.red, a.redsum, a.ratio, a.err,
+                               tag_base, run_if, fallbacks);
+        else
+            hipLaunchKernelGGL(qr_kernel<false>, dim3(L.P), dim3(kQrThreads), L.lds_bytes, st, a.M, a.m,
+                               a.n, a.A, a.Q, a.R, a.part, a.rowbuf, a.red, a.redsum, a.ratio, a.err,
+                               tag_base, run_if, fallbacks);
+        return launch_check("qr_kernel");
+    }
     QRCTM_HIP(hipLaunchCooperativeKernel(kern, dim3(L.P), dim3(kQrThreads), args, L.lds_bytes, st));
     return s;
 }

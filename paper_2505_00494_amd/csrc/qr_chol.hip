@@ -41,9 +41,9 @@
 // Pass 1 is rejected (state 1) when a pivot is not positive or not finite,
 // or min R1_ii < 1e-5 max R1_ii; pass 2 (state 2) when max |G2 - I| > 0.1,
 // i.e. when Q1 is too far from orthonormal for the second pass to be
-// accurate.  The kernels after a rejection return at once, and the cooperative
-// Householder kernel, launched behind them, runs only when the state is
-// non-zero.  The input M is read by pass 1 only and the output Q is written by
+// accurate.  The kernels after a rejection return at once, and the Householder
+// kernel, launched behind them (an ordinary launch), runs only when the state
+// is non-zero.  The input M is read by pass 1 only and the output Q is written by
 // the last product only, so Q may alias M.
 #include "common.h"
 #include "qr.h"
@@ -196,37 +196,53 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     }
     __syncthreads();
     auto blk = [&](int I, int J) { return B + (size_t)tri_index(I, J, nb) * 256; };
-    const int nn = n * n;  // n <= 1024
+    // Element pairs (gi, gj) row by row: wave w takes rows w, w + 8, ..., lane l
+    // the columns l, l + 64, ...; kU pairs per lane at a time, in order.
+    const int nch = (n + 63) / 64;
+    constexpr int kU = 16;
     // load the upper block triangle (identity beyond n): G read row by row
-    // (coalesced), eight independent loads in flight per thread
+    // (coalesced), kU independent loads in flight per lane
     {
         double dv = 0.0;
         int nf = 0;
-        for (int e0 = tid; e0 < nn; e0 += 8 * kCholThreads) {
-            double v[8];
+        int row0 = wave, ch0 = 0;
+        while (row0 < n) {
+            double v[kU];
+            int row = row0, ch = ch0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kCholThreads;
-                v[u] = e < nn ? G[e] : 0.0;
+            for (int u = 0; u < kU; ++u) {
+                const int gj = ch * 64 + lane;
+                v[u] = (row < n && gj < n) ? G[row * n + gj] : 0.0;
+                if (++ch == nch) {
+                    ch = 0;
+                    row += kCholWaves;
+                }
             }
+            row = row0;
+            ch = ch0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kCholThreads;
-                if (e >= nn) continue;
-                const int gi = e / n, gj = e - gi * n;
+            for (int u = 0; u < kU; ++u) {
+                const int gi = row, gj = ch * 64 + lane;
+                if (++ch == nch) {
+                    ch = 0;
+                    row += kCholWaves;
+                }
+                if (gi >= n || gj >= n) continue;
                 if (pass == 2) {
                     // the first-order factors (kept if max |G - I| <= 1e-8, else
                     // overwritten below): R2 = I + E_u, R2^{-1} = I - E_u, E_u the
                     // upper triangle of E = G - I with half its diagonal
                     const double x = gj > gi ? v[u] : (gj == gi ? 0.5 * (v[u] - 1.0) : 0.0);
-                    R[e] = (gi == gj ? 1.0 : 0.0) + x;
-                    Ri[e] = (gi == gj ? 1.0 : 0.0) - x;
+                    R[gi * n + gj] = (gi == gj ? 1.0 : 0.0) + x;
+                    Ri[gi * n + gj] = (gi == gj ? 1.0 : 0.0) - x;
                 }
                 if (gj < gi) continue;
                 if (!isfinite(v[u])) nf = 1;
                 dv = fmax(dv, fabs(v[u] - (gi == gj ? 1.0 : 0.0)));
                 blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] = v[u];
             }
+            row0 = row;
+            ch0 = ch;
         }
         const int pad0 = n, pad1 = nb * kB;
         for (int e = tid; e < (pad1 - pad0) * pad1; e += kCholThreads) {
@@ -251,7 +267,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     }
     // diagonal block K: wave 0 eliminates on [B_KK | I] (lane c < 16: column c of
     // B_KK, lane 16 + c: column c of I); its rows become R_KK and R_KK^{-T}.
-    // 1/sqrt of a pivot: the hardware estimate and two Newton steps.
+    // Per pivot j: row j is scaled by r = 1/sqrt(p) and row i > j loses
+    // B_ji r^2 times row j (the multipliers B_ji read from lane i).  1/sqrt:
+    // the hardware estimate and two Newton steps.
     auto factor_diag = [&](int K) {
         double* bk = blk(K, K);
         const int c = lane & 31;
@@ -266,7 +284,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
         int nonpos = 0;
 #pragma unroll
         for (int j = 0; j < kB; ++j) {
-            double p = readlane_d(b[j], j);
+            double m[kB];
+#pragma unroll
+            for (int i = j; i < kB; ++i) m[i] = readlane_d(b[j], i);
+            double p = m[j];
             if (!(p > 0.0) || !isfinite(p)) {
                 nonpos = 1;
                 p = 1.0;
@@ -280,9 +301,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
                 pmin = fmin(pmin, dj);
                 pmax = fmax(pmax, dj);
             }
+            const double tj = b[j] * (r * r);
             b[j] *= r;
 #pragma unroll
-            for (int i = j + 1; i < kB; ++i) b[i] -= readlane_d(b[j], i) * b[j];
+            for (int i = j + 1; i < kB; ++i) b[i] = fma(-m[i], tj, b[i]);
         }
         if (lane < 16) {
 #pragma unroll
@@ -350,10 +372,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
         __syncthreads();
     }
     // R (n x n, upper) and the verdict
-    for (int e = tid; e < nn; e += kCholThreads) {
-        const int gi = e / n, gj = e - gi * n;
-        R[e] = gj >= gi ? blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] : 0.0;
-    }
+    for (int gi = wave; gi < n; gi += kCholWaves)
+        for (int gj = lane; gj < n; gj += 64)
+            R[gi * n + gj] = gj >= gi ? blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] : 0.0;
     if (tid == 0) {
         int st = 0;
         if (pass == 1) {
@@ -377,19 +398,34 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
         dbl4 keep[kMaxJ];
         int nj = 0;
         for (int J = I + wave; J < nb; J += kCholWaves, ++nj) {
-            dbl4 t = {0.0, 0.0, 0.0, 0.0};
-            for (int k = I + 1; k <= J; ++k) {
+            // the sum in two independent accumulators (k and k + 1), so that
+            // consecutive MFMAs do not wait for each other
+            auto xop = [&](int k, int kk) -> double {
+                if (kLds) return blk(k, J)[kk * kB + cl];
+                return (k * kB + kk < n && J * kB + cl < n) ? Ri[(k * kB + kk) * n + J * kB + cl] : 0.0;
+            };
+            dbl4 t = {0.0, 0.0, 0.0, 0.0}, t1 = {0.0, 0.0, 0.0, 0.0};
+            for (int k = I + 1; k <= J; k += 2) {
+                const bool two = k + 1 <= J;  // wave-uniform
                 const double* rik = blk(I, k);
+                const double* rik1 = blk(I, two ? k + 1 : k);
+                double a0[4], x0[4], a1[4], x1[4];
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) {
                     const int kk = 4 * s4 + kl;
-                    const double xb = kLds ? blk(k, J)[kk * kB + cl]
-                                           : ((k * kB + kk < n && J * kB + cl < n)
-                                                  ? Ri[(size_t)(k * kB + kk) * n + J * kB + cl]
-                                                  : 0.0);
-                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(rik[cl * kB + kk], xb, t, 0, 0, 0);
+                    a0[s4] = rik[cl * kB + kk];
+                    x0[s4] = xop(k, kk);
+                    a1[s4] = rik1[cl * kB + kk];
+                    x1[s4] = two ? xop(k + 1, kk) : 0.0;
+                }
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s4], x0[s4], t, 0, 0, 0);
+                    if (two) t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s4], x1[s4], t1, 0, 0, 0);
                 }
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[r] += t1[r];
             dbl4 x = {0.0, 0.0, 0.0, 0.0};
             if (J == I) {
                 // X_II = W_I^T: element (4 r + kl, cl) = W_I[cl][4 r + kl]
@@ -421,11 +457,11 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
             __syncthreads();
         }
     }
-    for (int e = tid; e < nn; e += kCholThreads) {
-        const int gi = e / n, gj = e - gi * n;
-        if (kLds) Ri[e] = gj >= gi ? blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] : 0.0;
-        else if (gj < gi) Ri[e] = 0.0;
-    }
+    for (int gi = wave; gi < n; gi += kCholWaves)
+        for (int gj = lane; gj < n; gj += 64) {
+            if (kLds) Ri[gi * n + gj] = gj >= gi ? blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] : 0.0;
+            else if (gj < gi) Ri[gi * n + gj] = 0.0;
+        }
 }
 
 // R = R2 R1 (upper, zeros below) by 16 x 16 blocks, one per wave, and the
