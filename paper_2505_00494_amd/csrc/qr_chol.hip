@@ -33,7 +33,9 @@
 //    the bottom, X_IJ = -W_I^T sum_{I<k<=J} R_Ik X_kJ, X_II = W_I^T.  In pass
 //    2, when max |G2 - I| is below 1e-8, R2 = I + E_u (E = G2 - I, E_u its
 //    upper triangle with half the diagonal) and R2^{-1} = I - E_u, exact to
-//    |E|^2, below the rounding unit, replace the factorisation;
+//    |E|^2, below the rounding unit, replace the factorisation: the Gram
+//    reduction of pass 2 writes them and max |G2 - I| (one atomic maximum per
+//    wave), and the Cholesky kernel then only sets the state word;
 //  * the two products M R^{-1} on the FP64 GEMM of the step (the second gated
 //    by the state word, as it overwrites M when Q aliases M), and
 //    rprod_kernel: R = R2 R1 by upper 16 x 16 blocks, and min|R_ii|/max|R_ii|.
@@ -146,7 +148,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ X,
 // order: workgroup (t, quarter) adds 256 entries of tile t, eight partials'
 // loads in flight at a time.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int n, int nt,
-                                                          int S, double* G, const int* __restrict__ state) {
+                                                          int S, double* G, const int* __restrict__ state,
+                                                          double* R, double* Ri, unsigned long long* devw) {
     if (state != nullptr && *state != 0) return;
     const int t = blockIdx.x / 4, e = (blockIdx.x % 4) * 256 + threadIdx.x;
     int I, J;
@@ -161,10 +164,30 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
         for (int u = 0; u < 8; ++u) v += w[u];
     }
     const int gi = I * kGT + e / kGT, gj = J * kGT + e % kGT;
-    if (gi < n && gj < n) {
+    const bool in = gi < n && gj < n;
+    if (in) {
         G[(size_t)gi * n + gj] = v;
         G[(size_t)gj * n + gi] = v;
     }
+    if (R == nullptr) return;
+    // second pass: the first-order factors R2 = I + E_u, R2^{-1} = I - E_u
+    // (E_u the upper triangle of E = G - I with half its diagonal), kept when
+    // max |G - I| <= 1e-8, and that maximum (a non-finite entry counts as +inf;
+    // non-negative doubles order as their bit patterns)
+    double dev = 0.0;
+    if (in) {
+        const bool up = gj >= gi;
+        const double x = gj > gi ? v : 0.5 * (v - 1.0);
+        R[(size_t)gi * n + gj] = up ? (gi == gj ? 1.0 : 0.0) + x : 0.0;
+        Ri[(size_t)gi * n + gj] = up ? (gi == gj ? 1.0 : 0.0) - x : 0.0;
+        if (I != J) {
+            R[(size_t)gj * n + gi] = 0.0;
+            Ri[(size_t)gj * n + gi] = 0.0;
+        }
+        if (up) dev = isfinite(v) ? fabs(v - (gi == gj ? 1.0 : 0.0)) : INFINITY;
+    }
+    for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(devw, (unsigned long long)__double_as_longlong(dev));
 }
 
 // ---------------------------------------------------------------------------
@@ -176,9 +199,16 @@ template <bool kLds>
 __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __restrict__ G, int n,
                                                             int pass, double* work, double* R,
                                                             double* Ri, double* W, int* state,
-                                                            double* stats) {
+                                                            double* stats, unsigned long long* devw) {
     extern __shared__ double lds[];
     if (pass == 2 && *state != 0) return;
+    if (pass == 1 && devw != nullptr && threadIdx.x == 0) *devw = 0ull;
+    if (pass == 2 && devw != nullptr &&
+        __longlong_as_double((long long)*devw) <= kFirstOrderMaxDev) {
+        // the Gram reduction wrote the first-order factors
+        if (threadIdx.x == 0) *state = 0;
+        return;
+    }
     const int nb = (n + kB - 1) / kB;
     const int nblk = nb * (nb + 1) / 2;
     double* B = kLds ? lds : work;                        // block triangle
@@ -573,6 +603,7 @@ CholQrScratch cholqr_scratch_layout(int m, int n) {
     s.off_work = take(nb > kCholLdsMaxNb ? sizeof(double) * (size_t)nb * (nb + 1) / 2 * 256 : 0);
     s.off_stats = take(sizeof(double) * 4);
     s.off_state = take(sizeof(int));
+    s.off_dev = take(sizeof(unsigned long long));
     s.splitk_bytes = gemm_splitk_bytes(solve_desc(nullptr, nullptr, nullptr, m, n));
     s.off_splitk = take(s.splitk_bytes);
     s.total = off;
@@ -593,6 +624,7 @@ Status cholqr2(const double* M, double* Q, double* R, int m, int n, char* base,
     double* work = reinterpret_cast<double*>(base + L.off_work);
     double* stats = reinterpret_cast<double*>(base + L.off_stats);
     int* state = reinterpret_cast<int*>(base + L.off_state);
+    unsigned long long* devw = reinterpret_cast<unsigned long long*>(base + L.off_dev);
     void* sk = base + L.off_splitk;
     *state_out = state;
 
@@ -611,16 +643,18 @@ Status cholqr2(const double* M, double* Q, double* R, int m, int n, char* base,
         QRCTM_TRY(launch_check("gram_kernel"));
         if (g.S > 1) {
             hipLaunchKernelGGL(gram_reduce_kernel, dim3(g.ntri * 4), dim3(256), 0, st, part, n, g.nt, g.S, G,
-                               gate);
+                               gate, pass == 2 ? R2 : nullptr, pass == 2 ? Ri : nullptr, devw);
             QRCTM_TRY(launch_check("gram_reduce_kernel"));
         }
         double* Rp = pass == 1 ? R1 : R2;
+        // the first-order shortcut of pass 2 comes from the Gram reduction
+        unsigned long long* dw = g.S > 1 ? devw : nullptr;
         if (in_lds)
             hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(kCholThreads), chol_lds, st, G, n, pass,
-                               work, Rp, Ri, W, state, stats);
+                               work, Rp, Ri, W, state, stats, dw);
         else
             hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(kCholThreads), chol_lds, st, G, n, pass,
-                               work, Rp, Ri, W, state, stats);
+                               work, Rp, Ri, W, state, stats, dw);
         QRCTM_TRY(launch_check("chol_kernel"));
         // Q1 = M R1^{-1} into scratch; Q = Q1 R2^{-1} only if both passes were accepted
         GemmDesc sd = solve_desc(X, Ri, pass == 1 ? Q1 : Q, m, n);
