@@ -71,10 +71,36 @@ __device__ __forceinline__ void bf16_split3(float x, unsigned short& h, unsigned
 
 struct OutMap {
     long long mdiv, ms1, ms2, ndiv, ns1, ns2;
+    // 1 / mdiv and 1 / ndiv (set by with_inv before a launch)
+    double minv = 0.0, ninv = 0.0;
     static OutMap plain(long long M, long long N, long long ldc) {
         return OutMap{M > 0 ? M : 1, 0, ldc, N > 0 ? N : 1, 0, 1};
     }
+    OutMap with_inv() const {
+        OutMap o = *this;
+        o.minv = 1.0 / (double)mdiv;
+        o.ninv = 1.0 / (double)ndiv;
+        return o;
+    }
 };
+
+// m / d for 0 <= m < 2^31, 1 <= d < 2^31, with inv = 1 / d rounded: the
+// product is within 2^-21 of m / d, so its truncation is the quotient or one
+// below it, and one comparison of the remainder corrects it (an integer
+// division is a long instruction sequence on the GPU)
+__device__ __forceinline__ int div_inv(int m, int d, double inv) {
+    int q = (int)((double)m * inv);
+    const int r = m - q * d;
+    q += (r >= d ? 1 : 0) - (r < 0 ? 1 : 0);
+    return q;
+}
+// the same for 0 <= m < 2^40 (the product is then within 2^-12 of m / d)
+__device__ __forceinline__ long long div_inv64(long long m, long long d, double inv) {
+    long long q = (long long)((double)m * inv);
+    const long long r = m - q * d;
+    q += (r >= d ? 1 : 0) - (r < 0 ? 1 : 0);
+    return q;
+}
 
 struct GemmDesc {
     int trans_a = 0, trans_b = 0;

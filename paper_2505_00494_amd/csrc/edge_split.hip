@@ -204,6 +204,7 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
 
         const int n = 16 * nt + l16;
         if (n < R) {
+            const double inv_chi = 1.0 / (double)chi;
             const int rb = n / D, db = n % D;
 #pragma unroll
             for (int i = 0; i < MTW; ++i)
@@ -213,7 +214,7 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
                     if (m >= P * R) continue;
                     const int pg = b * P + m / R;
                     if (pg >= npairs) continue;
-                    const int c = m % R, al = pg / chi, f = pg - al * chi;
+                    const int c = m % R, al = div_inv(pg, chi, inv_chi), f = pg - al * chi;
                     const int rk = c / D, dk = c % D;
                     Z[(al * R + rk * D + rb) * chi * R + f * R + dk * D + db] = (double)z[i][r];
                 }

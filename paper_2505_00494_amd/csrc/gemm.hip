@@ -65,9 +65,11 @@ struct Mma<float> {
     __device__ static int row_of(int r, int q) { return MMA_F32_ROW(r, q); }
 };
 
-__device__ __forceinline__ long long out_index(const OutMap& mp, long long m, long long n) {
-    return (m / mp.mdiv) * mp.ms1 + (m % mp.mdiv) * mp.ms2 + (n / mp.ndiv) * mp.ns1 +
-           (n % mp.ndiv) * mp.ns2;
+// (m, n < 2^31, which gemm_f64 checks)
+__device__ __forceinline__ long long out_index(const OutMap& mp, int m, int n) {
+    const int qm = div_inv(m, (int)mp.mdiv, mp.minv), qn = div_inv(n, (int)mp.ndiv, mp.ninv);
+    return qm * mp.ms1 + (m - qm * (int)mp.mdiv) * mp.ms2 + qn * mp.ns1 +
+           (n - qn * (int)mp.ndiv) * mp.ns2;
 }
 
 template <class CT, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
@@ -218,7 +220,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
     for (int j = 0; j < FN; ++j) {
         const long long n = n0 + wn * WN + j * 16 + lrow;
         nok[j] = n < p.N;
-        noff[j] = p.partial ? n : (n / p.map.ndiv) * p.map.ns1 + (n % p.map.ndiv) * p.map.ns2;
+        const int qn = div_inv((int)n, (int)p.map.ndiv, p.map.ninv);
+        noff[j] = p.partial ? n : qn * p.map.ns1 + (n - qn * p.map.ndiv) * p.map.ns2;
     }
     double* Cb = p.partial ? p.C + (long long)blockIdx.y * MN : p.C;
 #pragma unroll
@@ -227,8 +230,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
         for (int r = 0; r < 4; ++r) {
             const long long m = m0 + wm * WM + i * 16 + Mma<CT>::row_of(r, lk);
             if (m >= p.M) continue;
+            const int qm = div_inv((int)m, (int)p.map.mdiv, p.map.minv);
             const long long moff =
-                p.partial ? m * p.N : (m / p.map.mdiv) * p.map.ms1 + (m % p.map.mdiv) * p.map.ms2;
+                p.partial ? m * p.N : qm * p.map.ms1 + (m - qm * p.map.mdiv) * p.map.ms2;
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 if (!nok[j]) continue;
@@ -254,13 +258,16 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits
                                      long long N, double* C, OutMap mp, double alpha,
                                      double beta, const int* gate) {
     if (gate != nullptr && *gate != 0) return;
+    // M, N < 2^31 and M N < 2^40 (checked by gemm_f64)
     const long long MN = M * N;
+    const double invN = 1.0 / (double)N;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < MN;
          e += (long long)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int z = 0; z < splits; ++z) s += part[z * MN + e];
-        const long long m = e / N, n = e % N;
-        const long long o = out_index(mp, m, n);
+        const long long m = div_inv64(e, N, invN);
+        const int n = (int)(e - m * N);
+        const long long o = out_index(mp, (int)m, n);
         C[o] = beta == 0.0 ? alpha * s : alpha * s + beta * C[o];
     }
 }
@@ -355,6 +362,12 @@ size_t gemm_splitk_bytes(const GemmDesc& g) {
 Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStream_t st) {
     Status s;
     if (g.M <= 0 || g.N <= 0) return s;
+    if (g.M >= (1ll << 31) || g.N >= (1ll << 31) || g.M * g.N >= (1ll << 40)) {
+        // the kernels index rows and columns in 32 bits
+        s.code = -1;
+        s.msg = "gemm_f64: M and N must be below 2^31 and M * N below 2^40";
+        return s;
+    }
     if (g.K <= 0) {
         // C = beta * C (alpha * empty sum)
         // handled by a split-less pass of the reduce kernel with zero partials
@@ -370,7 +383,7 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
     KArgs a{};
     a.M = g.M; a.N = g.N; a.K = g.K;
     a.A = g.A; a.lda = g.lda; a.B = g.B; a.ldb = g.ldb;
-    a.alpha = g.alpha; a.beta = g.beta; a.map = g.map;
+    a.alpha = g.alpha; a.beta = g.beta; a.map = g.map.with_inv();
     a.kchunk = pl.kchunk;
     a.C16 = g.prec == 2 ? g.C16 : nullptr;
     a.pC16 = g.pC16;
@@ -410,7 +423,7 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
         const long long MN = g.M * g.N;
         const int blocks = (int)std::min<long long>(ceil_div(MN, 256), 4096);
         hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, st,
-                           static_cast<const double*>(splitk_ws), pl.splits, g.M, g.N, g.C, g.map,
+                           static_cast<const double*>(splitk_ws), pl.splits, g.M, g.N, g.C, g.map.with_inv(),
                            g.alpha, g.beta, g.gate);
         QRCTM_TRY(launch_check("splitk_reduce_kernel"));
     }

@@ -120,9 +120,11 @@ struct Stage {
     }
 };
 
-__device__ __forceinline__ long long map_index(const OutMap& mp, long long m, long long n) {
-    return (m / mp.mdiv) * mp.ms1 + (m % mp.mdiv) * mp.ms2 + (n / mp.ndiv) * mp.ns1 +
-           (n % mp.ndiv) * mp.ns2;
+// (m, n < 2^31, which gemm_f64 checks)
+__device__ __forceinline__ long long map_index(const OutMap& mp, int m, int n) {
+    const int qm = div_inv(m, (int)mp.mdiv, mp.minv), qn = div_inv(n, (int)mp.ndiv, mp.ninv);
+    return qm * mp.ms1 + (m - qm * (int)mp.mdiv) * mp.ms2 + qn * mp.ns1 +
+           (n - qn * (int)mp.ndiv) * mp.ns2;
 }
 
 template <bool APL, bool BPL, bool TA, bool TB, bool OPL>
@@ -233,12 +235,14 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16x6_kernel(BArgs p) {
         for (int r = 0; r < 4; ++r) {
             const long long m = m0 + wm * kWM + i * 16 + 4 * lg + r;
             if (m >= p.M) continue;
-            const long long moff = (m / p.map.mdiv) * p.map.ms1 + (m % p.map.mdiv) * p.map.ms2;
+            const int qm = div_inv((int)m, (int)p.map.mdiv, p.map.minv);
+            const long long moff = qm * p.map.ms1 + (m - qm * p.map.mdiv) * p.map.ms2;
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 const long long n = n0 + wn * kWN + j * 16 + lr;
                 if (n >= p.N) continue;
-                const long long o = moff + (n / p.map.ndiv) * p.map.ns1 + (n % p.map.ndiv) * p.map.ns2;
+                const int qn = div_inv((int)n, (int)p.map.ndiv, p.map.ninv);
+                const long long o = moff + qn * p.map.ns1 + (n - qn * p.map.ndiv) * p.map.ns2;
                 if (OPL) {
                     unsigned short h, mm, l;
                     split1((float)(p.alpha * (double)acc[i][j][r]), h, mm, l);
@@ -287,7 +291,7 @@ Status gemm_bf16x6(const GemmDesc& g, hipStream_t st) {
     a.A = g.A; a.lda = g.lda; a.A16 = g.A16; a.lda16 = g.lda16; a.pA = g.pA16;
     a.B = g.B; a.ldb = g.ldb; a.B16 = g.B16; a.ldb16 = g.ldb16; a.pB = g.pB16;
     a.C = g.C; a.C16 = g.C16; a.pC = g.pC16;
-    a.map = g.map; a.alpha = g.alpha; a.beta = g.beta;
+    a.map = g.map.with_inv(); a.alpha = g.alpha; a.beta = g.beta;
     a.tiles_m = (int)ceil_div(g.M, kBM);
     a.tiles_n = (int)ceil_div(g.N, kBN);
     const dim3 grid((unsigned)(a.tiles_m * a.tiles_n)), block(kThreads);
