@@ -105,8 +105,13 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
     const long long kbeg = (long long)blockIdx.y * p.kchunk;
     const long long kend = min(p.K, kbeg + p.kchunk);
 
-    // raw operand values of the next slab, held in registers across the MFMAs
-    double ra[LA], rb[LB];
+    // raw operand values of the next two slabs, held in registers across the
+    // MFMAs (two register sets, used alternately: a load has two slabs of
+    // matrix-core work to arrive in) for the 128 x 128 tiles, whose two waves
+    // per SIMD have the registers; the smaller tiles keep one slab ahead, so
+    // that as many workgroups as before fit on a CU
+    constexpr bool kPf2 = BM == 128 && BN == 128;
+    double ra0[LA], rb0[LB], ra1[LA], rb1[LB];
 
     // Out-of-range elements are loaded from a clamped (valid) address; they
     // are replaced by zero (and converted to CT) only when stored to LDS, after
@@ -128,7 +133,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
         gk = k0 + kk;
         return (BN * BK % NT == 0 || e < BN * BK) && gn < p.N && gk < kend;
     };
-    auto load = [&](long long k0) {
+    auto load = [&](long long k0, double (&ra)[LA], double (&rb)[LB]) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             long long gm, gk;
@@ -144,7 +149,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
             rb[i] = TB ? p.B[cn * p.ldb + ck] : p.B[ck * p.ldb + cn];
         }
     };
-    auto store = [&](int buf, long long k0) {
+    auto store = [&](int buf, long long k0, const double (&ra)[LA], const double (&rb)[LB]) {
 #pragma unroll
         for (int i = 0; i < LA; ++i) {
             const int e = tid + i * NT;
@@ -178,13 +183,22 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
 
     int buf = 0;
     if (kbeg < kend) {
-        load(kbeg);
-        store(0, kbeg);
+        load(kbeg, ra0, rb0);
+        store(0, kbeg, ra0, rb0);
     }
+    if (kPf2 && kbeg + BK < kend) load(kbeg + BK, ra1, rb1);
     __syncthreads();
-    for (long long k0 = kbeg; k0 < kend; k0 += BK) {
+    // one slab: the loads of slab k0 + 2 BK go into (na, nb) while slab k0 is
+    // multiplied from LDS; then slab k0 + BK, loaded a slab earlier into (ca,
+    // cb), is stored to the other LDS buffer
+    auto slab = [&](long long k0, double (&ca)[LA], double (&cb)[LB], double (&na)[LA],
+                    double (&nb)[LB]) {
         const bool more = k0 + BK < kend;
-        if (more) load(k0 + BK);
+        if (kPf2) {
+            if (k0 + 2 * BK < kend) load(k0 + 2 * BK, na, nb);
+        } else if (more) {
+            load(k0 + BK, ca, cb);
+        }
         CT af[FM][KQ], bf[FN][KQ];
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
@@ -206,9 +220,17 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
                     acc[i][j] = Mma<CT>::run(af[i][q], bf[j][q], acc[i][j]);
-        if (more) store(buf ^ 1, k0 + BK);
+        if (more) store(buf ^ 1, k0 + BK, ca, cb);
         __syncthreads();
         buf ^= 1;
+    };
+    if (kPf2) {
+        for (long long k0 = kbeg; k0 < kend; k0 += 2 * BK) {
+            slab(k0, ra1, rb1, ra0, rb0);
+            if (k0 + BK < kend) slab(k0 + BK, ra0, rb0, ra1, rb1);
+        }
+    } else {
+        for (long long k0 = kbeg; k0 < kend; k0 += BK) slab(k0, ra1, rb1, ra0, rb0);
     }
 
     // epilogue: accumulator element r of a lane is D[row_of(r, lane/16)][lane%16]
