@@ -107,10 +107,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
 
     // raw operand values of the next two slabs, held in registers across the
     // MFMAs (two register sets, used alternately: a load has two slabs of
-    // matrix-core work to arrive in) for the 128 x 128 tiles, whose two waves
-    // per SIMD have the registers; the smaller tiles keep one slab ahead, so
-    // that as many workgroups as before fit on a CU
-    constexpr bool kPf2 = BM == 128 && BN == 128;
+    // matrix-core work to arrive in) for the FP64 128 x 128 tiles, whose two
+    // waves per SIMD have the registers; the other builds keep one slab ahead,
+    // so that as many workgroups as before fit on a CU
+    constexpr bool kPf2 = BM == 128 && BN == 128 && sizeof(CT) == 8;
     double ra0[LA], rb0[LB], ra1[LA], rb1[LB];
 
     // Out-of-range elements are loaded from a clamped (valid) address; they
