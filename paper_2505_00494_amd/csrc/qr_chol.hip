@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     // Element pairs (gi, gj) row by row: wave w takes rows w, w + 8, ..., lane l
     // the columns l, l + 64, ...; kU pairs per lane at a time, in order.
     const int nch = (n + 63) / 64;
-    constexpr int kU = 16;
+    constexpr int kU = 32;
     // load the upper block triangle (identity beyond n): G read row by row
     // (coalesced), kU independent loads in flight per lane
     {
