@@ -225,6 +225,235 @@ __attribute__((amdgpu_waves_per_eu(Shape3b<D>::WPE))) void edge_split_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 forward at D = 6 with both physical indices in one ket product.
+//   GEMM 1  x[(p u_b l_b)][(s r_k d_k)] = sum_{(u_k l_k)} ys[..] Bk[s][(u_k l_k)][(r_k d_k)]
+//           M = 4 * 36 = 144 (9 row tiles, no padding), N = 72, K = 36
+//   GEMM 2  z[(p r_k d_k)][(r_b d_b)] = sum_{(s u_b l_b)} xs[..] Bk[s][(u_b l_b)][(r_b d_b)]
+//           M = 144, N = 36, K = 72 (the prepared Bk is this K x N operand as it stands)
+// Columns that do not fill a 16-wide tile (GEMM 1: 64..71, GEMM 2: 32..35) go
+// to v_mfma_f64_4x4x4f64, four 4 x 4 blocks per instruction.  Its block b takes
+// A[4b + i][k] from lane 16k + 4b + i, which is the 16 x 16 x 4 A fragment as it
+// stands, B[k][j] from lane 16k + 4b + j (here the same four columns for every
+// block), and leaves D[4b + i][j] in lane 16i + 4b + j (lane layouts measured
+// on gfx950).  Instead of 5 x 16 and 3 x 16 columns of 16-wide tiles that is
+// 4 x 16 + 8 and 2 x 16 + 4, and M needs no padding: 729 16x16x4-equivalents
+// per batch of four blocks in place of 1296 for five.
+// GEMM 2 of batch b and GEMM 1 of batch b + 1 run between the same two
+// barriers (x waits in registers while GEMM 2 reads the previous x from xs), so
+// each wave's share of the phase balances across both products.  Waves come in
+// three groups of four; group g holds row tiles 3g .. 3g + 2.  In GEMM 1 wave c
+// of a group takes column tile c of the group's rows; in GEMM 2 waves 0-2 take
+// two of the group's six (row tile, column tile) pairs each, and wave 3 takes
+// the narrow columns of both products.
+// ---------------------------------------------------------------------------
+namespace es6 {
+constexpr int D = 6, R = 36, P = 4, M = P * R, LDM = M, NT = 768, NY = P * R * R;
+constexpr int NL = (NY + NT - 1) / NT;
+constexpr int NPB = 48;  // columns of the prepared Bk
+}  // namespace es6
+
+__global__ __launch_bounds__(es6::NT) __attribute__((amdgpu_waves_per_eu(3))) void edge_split6_kernel(
+    const double* __restrict__ Y, const double* __restrict__ Bk, int chi, int npairs,
+    double* __restrict__ Z, unsigned* ticket) {
+    using namespace es6;
+    __shared__ double ys[R * LDM];       // ys[(u_k l_k)][(p u_b l_b)]
+    __shared__ double xs[2 * R * LDM];   // xs[(s u_b l_b)][(p r_k d_k)]
+    __shared__ double bs[2 * R * NPB];   // Bk[(s k)][n]
+    __shared__ int tk[2];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, q = lane >> 4, l16 = lane & 15;
+    const int w = tid >> 6, c = w & 3, g = w >> 2;
+    // 4x4x4 lane roles: block row 4 bq + q of the tile, column j4
+    const int bq = (lane >> 2) & 3, j4 = lane & 3;
+    const int nbatch = (npairs + P - 1) / P;
+    // one ticket per batch, plus one that ends each workgroup: nbatch + gridDim.x in all
+    auto draw = [&](int slot) {
+        if (tid == 0) {
+            const unsigned t = atomicAdd(ticket, 1u);
+            if (t == (unsigned)(nbatch + gridDim.x - 1)) atomicExch(ticket, 0u);
+            tk[slot] = (int)min(t, (unsigned)nbatch);
+        }
+    };
+    draw(0);
+    __syncthreads();
+    const int b0 = tk[0];
+    if (b0 >= nbatch) return;
+
+    for (int i = tid; i < 2 * R * NPB; i += NT) bs[i] = Bk[i];
+
+    // 32-bit offsets: the host guarantees npairs D^4 + 2^16 < 2^31
+    const int ylim = npairs * R * R;
+    double pre[NL];
+    auto load = [&](int b) {
+        const int base = b * NY;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + i * NT;
+            pre[i] = (e < NY && base + e < ylim) ? Y[base + e] : 0.0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + i * NT;
+            if (e < NY) {
+                const int p = e / (R * R), v = e % (R * R);
+                const int uk = v / (D * R), ub = (v / R) % D, lk = (v / D) % D, lb = v % D;
+                ys[(uk * D + lk) * LDM + p * R + ub * D + lb] = pre[i];
+            }
+        }
+    };
+
+    // GEMM 1 operands of this lane: B column 16 c + l16 of the stacked x columns (s r_k d_k)
+    const int col1 = 16 * c + l16;
+    const int boff1 = (col1 / R) * R * NPB + col1 % R;
+    const int rt0 = 3 * g;  // first row tile of the group
+    dbl4 x1[3];
+    double xr[3][2];  // wave 3: columns 64 + 4 cb + j4
+    auto gemm1 = [&]() {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) x1[i] = dbl4{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xr[i][0] = xr[i][1] = 0.0;
+        if (c < 3) {
+#pragma unroll 3
+            for (int kk = 0; kk < R / 4; ++kk) {
+                const double* a = ys + (4 * kk + q) * LDM + 16 * rt0 + l16;
+                const double bv = bs[boff1 + (4 * kk + q) * NPB];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) x1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[16 * i], bv, x1[i], 0, 0, 0);
+            }
+        } else {
+#pragma unroll 3
+            for (int kk = 0; kk < R / 4; ++kk) {
+                const double* a = ys + (4 * kk + q) * LDM + 16 * rt0 + l16;
+                const double bv = bs[boff1 + (4 * kk + q) * NPB];
+                const double* br = bs + (R + 4 * kk + q) * NPB + 28 + j4;
+                const double b0v = br[0], b1v = br[4];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double av = a[16 * i];
+                    x1[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x1[i], 0, 0, 0);
+                    xr[i][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b0v, xr[i][0], 0, 0, 0);
+                    xr[i][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b1v, xr[i][1], 0, 0, 0);
+                }
+            }
+        }
+    };
+    // x[m][cc] -> xs[(cc / 36) 36 + m % 36][(m / 36) 36 + cc % 36]
+    auto put_x = [&]() {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = 16 * (rt0 + i) + 4 * r + q;
+                xs[((col1 / R) * R + m % R) * LDM + (m / R) * R + col1 % R] = x1[i][r];
+            }
+        if (c == 3) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int m = 16 * (rt0 + i) + 4 * bq + q, cc = 64 + 4 * cb + j4;
+                    xs[(R + m % R) * LDM + (m / R) * R + cc - R] = xr[i][cb];
+                }
+        }
+    };
+
+    // GEMM 2 pairs of waves 0-2: pair j = 2 c + h has row tile rt0 + j % 3 and column tile j / 3
+    int rt2[2], ct2[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = 2 * c + h;
+        rt2[h] = rt0 + j % 3;
+        ct2[h] = j / 3;
+    }
+    dbl4 z2[2];
+    double zr[3];  // wave 3: columns 32 + j4
+    auto gemm2 = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) z2[h] = dbl4{0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) zr[i] = 0.0;
+        if (c < 3) {
+#pragma unroll 3
+            for (int kk = 0; kk < 2 * R / 4; ++kk) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double av = xs[(4 * kk + q) * LDM + 16 * rt2[h] + l16];
+                    const double bv = bs[(4 * kk + q) * NPB + 16 * ct2[h] + l16];
+                    z2[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, z2[h], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll 3
+            for (int kk = 0; kk < 2 * R / 4; ++kk) {
+                const double* a = xs + (4 * kk + q) * LDM + 16 * rt0 + l16;
+                const double bv = bs[(4 * kk + q) * NPB + 32 + j4];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) zr[i] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[16 * i], bv, zr[i], 0, 0, 0);
+            }
+        }
+    };
+    const double inv_chi = 1.0 / (double)chi;
+    // z[n2][n] of batch b: n2 = (p r_k d_k), n = (r_b d_b)
+    auto put_z = [&](int b, int n2, int n, double v) {
+        const int pg = b * P + n2 / R;
+        if (pg >= npairs) return;
+        const int cc = n2 % R, al = div_inv(pg, chi, inv_chi), f = pg - al * chi;
+        const int rk = cc / D, dk = cc % D, rb = n / D, db = n % D;
+        Z[(al * R + rk * D + rb) * chi * R + f * R + dk * D + db] = v;
+    };
+    auto store_z = [&](int b) {
+        if (c < 3) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) put_z(b, 16 * rt2[h] + 4 * r + q, 16 * ct2[h] + l16, z2[h][r]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) put_z(b, 16 * (rt0 + i) + 4 * bq + q, 32 + j4, zr[i]);
+        }
+    };
+
+    // prologue: batch b0 through GEMM 1, its x in xs, the next batch's Y in ys
+    load(b0);
+    store();
+    draw(1);
+    __syncthreads();
+    int nxt = tk[1];
+    if (nxt < nbatch) load(nxt);
+    gemm1();
+    __syncthreads();
+    put_x();
+    if (nxt < nbatch) {
+        store();
+        draw(0);
+    }
+    __syncthreads();
+    int cur_x = b0, cur_y = nxt, slot = 0;
+    while (true) {
+        nxt = cur_y < nbatch ? tk[slot] : nbatch;
+        if (nxt < nbatch) load(nxt);
+        gemm2();
+        if (cur_y < nbatch) gemm1();
+        __syncthreads();  // every read of xs and ys in this phase is done
+        store_z(cur_x);
+        if (cur_y >= nbatch) break;
+        put_x();
+        if (nxt < nbatch) {
+            store();
+            draw(slot ^ 1);
+        }
+        __syncthreads();
+        cur_x = cur_y;
+        cur_y = nxt;
+        slot ^= 1;
+    }
+}
+
 // Bk[s][k][n] = As[s][u][l][dd][r] (k = u D + l, n = r D + dd) and, after it,
 // BkT[s][k][n] = Bk[s][n][k], both [d][KP][NP] and zero outside k, n < D^2;
 // then the ticket counters.
@@ -536,9 +765,27 @@ Status launch_3b_bw(const double* Y, const double* Zb, const double* Bk, const d
     return launch_check("edge_split_bw_reduce_kernel");
 }
 
+Status launch_3b6(const double* Y, const double* Bk, unsigned* ticket, int chi, int npairs,
+                  double* Z, hipStream_t st) {
+    static int per_cu = -1, cus = 0;
+    if (per_cu < 0) {
+        int dev = 0;
+        QRCTM_HIP(hipGetDevice(&dev));
+        QRCTM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QRCTM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, edge_split6_kernel, es6::NT, 0));
+        if (per_cu < 1) per_cu = 1;
+    }
+    const long long nbatch = ceil_div(npairs, es6::P);
+    const int grid = (int)std::min<long long>(nbatch, (long long)per_cu * cus);
+    hipLaunchKernelGGL(edge_split6_kernel, dim3(grid), dim3(es6::NT), 0, st, Y, Bk, chi, npairs, Z,
+                       ticket);
+    return launch_check("edge_split6_kernel");
+}
+
 template <class CT, int D>
 Status launch_3b_t(const double* Y, const double* Bk, unsigned* ticket, int chi, int npairs,
                    double* Z, hipStream_t st) {
+    if constexpr (D == 6 && sizeof(CT) == 8) return launch_3b6(Y, Bk, ticket, chi, npairs, Z, st);
     using S = Shape3b<D>;
     static int per_cu = -1, cus = 0;
     if (per_cu < 0) {

@@ -41,7 +41,8 @@ def _rel(x, y):
 
 @pytest.mark.parametrize("split,qr_method", [(0, P.QR_AUTO), (1, P.QR_AUTO), (1, P.QR_HOUSEHOLDER)])
 @pytest.mark.parametrize("d,D,chi,nsteps", [(2, 2, 16, 6), (2, 3, 36, 4), (2, 4, 64, 3),
-                                            (2, 5, 75, 2), (2, 6, 144, 2), (2, 7, 98, 1),
+                                            (2, 5, 75, 2), (2, 6, 144, 2), (2, 6, 37, 2),
+                                            (2, 7, 98, 1),
                                             (2, 8, 128, 1), (2, 2, 600, 1), (2, 2, 1024, 1)])
 def test_qr_steps_match_oracle_elementwise(d, D, chi, nsteps, split, qr_method):
     # both QR methods (Cholesky-QR2 with its fallback, and Householder) give the
