@@ -2,22 +2,22 @@
 // (the standard-CTMRG paragraph iterates the step to convergence; the change
 // in the normalised corner spectrum is the measure used here).
 //
-// Three kernels on the caller's stream:
-//  * tridiag_kernel, one workgroup of 512 threads: Householder
-//    tridiagonalisation of the symmetric chi x chi corner, keeping only its
-//    lower triangle (packed in LDS up to chi = 176, beyond that row-major in
-//    global scratch, L2 resident).  The rank-2 update of each reflection is
-//    applied lazily, in the same sweep of the trailing triangle that forms the
-//    next reflection's product A v, so each reflection reads and writes the
-//    triangle once.  Writes the diagonal, the squared off-diagonal and a
-//    Gershgorin interval;
-//  * bisect_kernel, one wave per eigenvalue over as many workgroups as needed:
-//    Sturm-sequence multisection, the 64 lanes each placing two of the 128
-//    interior points that cut the interval, until it stops shrinking or is
+// One kernel of one workgroup (512 threads) on the caller's stream, so that
+// beside a running step it occupies a single CU:
+//  * Householder tridiagonalisation of the symmetric chi x chi corner, keeping
+//    only its lower triangle (packed in LDS up to chi = 176, beyond that
+//    row-major in global scratch, L2 resident).  The rank-2 update of each
+//    reflection is applied lazily, in the same sweep of the trailing triangle
+//    that forms the next reflection's product A v, so each reflection reads and
+//    writes the triangle once;
+//  * Sturm-sequence multisection over the Gershgorin interval: one round of
+//    512 evenly spaced points brackets every eigenvalue, then each eigenvalue
+//    gets a group of lanes of one wave (64 / ceil(chi / 8) of them), which cut
+//    its interval at one point each per round, until it stops shrinking or is
 //    within 2 eps relative / 4 eps |T| absolute;
-//  * rank_kernel, one workgroup: |lambda| ranked in descending order (ties by
-//    index), normalised by their sum, and delta = || s - s_prev ||_2 with the
-//    shorter spectrum padded by zeros.
+//  * |lambda| ranked in descending order (ties by index), normalised by their
+//    sum, and delta = || s - s_prev ||_2 with the shorter spectrum padded by
+//    zeros.
 // Every reduction has a fixed order, so the result does not vary between runs.
 #include "common.h"
 #include "spectrum.h"
@@ -102,31 +102,36 @@ __device__ double block_sum(double v, double* part) {
 }
 
 // Sturm counts (eigenvalues below x) of the tridiagonal matrix (d, e^2) at NP
-// points, their recurrences interleaved.  1/q is the hardware reciprocal with
-// two Newton steps; |q| >= pivmin = 1e-300 max(1, max e^2) keeps every value
-// finite.
+// points, their recurrences interleaved.  The count is the number of negative
+// pivots q_j = d_j - x - e^2_{j-1} / q_{j-1} of T - x I = L D L^T; here without
+// the division, through the leading minors p_j = (d_j - x) p_{j-1} - e^2_{j-1}
+// p_{j-2} (q_j = p_j / p_{j-1}, negative where the two signs differ), the pair
+// (p_j, p_{j-1}) scaled by a power of two after every step so that p_j lies in
+// [1/2, 1).  A pivot below pivmin = 1e-300 max(1, max e^2) in magnitude is
+// replaced by -pivmin (p_j = -pivmin p_{j-1}), which keeps every value finite.
 template <int NP>
 __device__ void sturm_counts(const double* d, const double* e2, int n, const double* x,
                              double pivmin, int* cnt) {
-    double q[NP];
+    double u[NP], v[NP];  // p_j and p_{j-1}, scaled
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        q[p] = d[0] - x[p];
-        if (fabs(q[p]) < pivmin) q[p] = -pivmin;
-        cnt[p] = q[p] < 0.0;
+        u[p] = d[0] - x[p];
+        if (fabs(u[p]) < pivmin) u[p] = -pivmin;
+        v[p] = 1.0;
+        cnt[p] = u[p] < 0.0;
     }
     auto step = [&](double dj, double ej) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            double r = __builtin_amdgcn_rcp(q[p]);
-            double h = fma(-q[p], r, 1.0);
-            r = fma(r, h, r);
-            h = fma(-q[p], r, 1.0);
-            r = fma(r, h, r);
-            double qq = fma(-ej, r, dj - x[p]);
-            if (fabs(qq) < pivmin) qq = -pivmin;
-            q[p] = qq;
-            cnt[p] += qq < 0.0;
+            double un = fma(dj - x[p], u[p], -(ej * v[p]));
+            if (fabs(un) < pivmin * fabs(u[p])) un = -pivmin * u[p];
+            cnt[p] += (un < 0.0) != (u[p] < 0.0);
+            // 2^(1022 - e) for the biased exponent e of un, built from its bits
+            // (pivmin <= |un / u| <= 1/pivmin keeps e within [24, 2020])
+            const unsigned ex = (unsigned)(__double_as_longlong(un) >> 52) & 0x7ffu;
+            const double sc = __longlong_as_double((long long)(2045u - ex) << 52);
+            v[p] = u[p] * sc;
+            u[p] = un * sc;
         }
     };
     // eight entries of (d, e^2) read ahead of their use
@@ -134,12 +139,12 @@ __device__ void sturm_counts(const double* d, const double* e2, int n, const dou
     for (; j + 8 <= n; j += 8) {
         double dv[8], ev[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            dv[u] = d[j + u];
-            ev[u] = e2[j + u - 1];
+        for (int w = 0; w < 8; ++w) {
+            dv[w] = d[j + w];
+            ev[w] = e2[j + w - 1];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) step(dv[u], ev[u]);
+        for (int w = 0; w < 8; ++w) step(dv[w], ev[w]);
     }
     for (; j < n; ++j) step(d[j], e2[j - 1]);
 }
@@ -161,14 +166,17 @@ struct LdsSym {
 
 
 template <class Store, int MAXN>
-__global__ __launch_bounds__(kSpecThreads) void tridiag_kernel(const double* __restrict__ C, int n,
-                                                               double* Sg, double* tri) {
+__global__ __launch_bounds__(kSpecThreads) void spectrum_kernel(const double* __restrict__ C, int n,
+                                                                double* Sg, const double* s_prev,
+                                                                int n_prev, double* s_out,
+                                                                double* delta_out) {
     constexpr int R = (MAXN + kSpecThreads - 1) / kSpecThreads;  // rows / eigenvalues per thread
     constexpr int NC = (MAXN + 63) / 64;                            // 64-column chunks of a row
     // vp, wp: the reflection whose rank-2 update is still pending; vk: the
     // current reflection; prow: row part of A v; dd, ee: the tridiagonal matrix
     __shared__ double vp[MAXN], wp[MAXN], vk[MAXN], prow[MAXN], dd[MAXN], ee[MAXN];
     __shared__ double part[2][kSpecWaves];
+    __shared__ int cgrid[kSpecThreads];  // Sturm counts of the bracketing points
     __shared__ double alpha_sh;
     extern __shared__ double dyn[];
     double* pcol = dyn;  // [kSpecWaves][n]: column part of A v, one row per wave
@@ -350,77 +358,72 @@ __global__ __launch_bounds__(kSpecThreads) void tridiag_kernel(const double* __r
     }
     const double pivmin = 1e-300 * fmax(1.0, me2);
     const double span = fmax(fabs(lo), fabs(hi));
-    // d, e^2, the widened Gershgorin interval and the absolute tolerance
-    // (4 eps |T|) of the eigenvalues
-    for (int i = t; i < n; i += kSpecThreads) {
-        tri[i] = dd[i];
-        tri[n + i] = i + 1 < n ? ee[i] * ee[i] : 0.0;
-    }
-    if (t == 0) {
-        tri[2 * n] = lo - (2.2e-16 * span * n + pivmin);
-        tri[2 * n + 1] = hi + (2.2e-16 * span * n + pivmin);
-        tri[2 * n + 2] = pivmin;
-        tri[2 * n + 3] = 4.0 * 2.2e-16 * span + pivmin;
-    }
-}
+    // the widened interval and the absolute tolerance (4 eps |T|) of the eigenvalues
+    lo -= 2.2e-16 * span * n + pivmin;
+    hi += 2.2e-16 * span * n + pivmin;
+    const double atol = 4.0 * 2.2e-16 * span + pivmin;
+    // e^2 (in wp) and the eigenvalue magnitudes (in vk); the reflection arrays are free
+    double* e2 = wp;
+    double* lam = vk;
+    for (int i = t; i < n; i += kSpecThreads) e2[i] = i + 1 < n ? ee[i] * ee[i] : 0.0;
+    __syncthreads();
 
-// |lambda_e| of the tridiagonal matrix for e = one per wave (ascending index):
-// multisection over the Gershgorin interval, 128 points per round (two per
-// lane, interleaved recurrences), the wave keeping the part that holds the
-// eigenvalue, until the width is 2 eps max(|a|, |b|) + atol or stops falling.
-constexpr int kBisWaves = 4;
-__global__ __launch_bounds__(64 * kBisWaves) void bisect_kernel(const double* __restrict__ tri, int n,
-                                                                double* lam) {
-    extern __shared__ double sh[];
-    double* d = sh;
-    double* e2 = sh + n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        d[i] = tri[i];
-        e2[i] = tri[n + i];
+    // Bracketing: the counts at kSpecThreads evenly spaced points of the
+    // interval, one per thread; eigenvalue e starts from the two neighbouring
+    // points whose counts enclose it (found by bisection over the points, with
+    // count(lo) = 0 and count(hi) = n at the ends).
+    const double hg = (hi - lo) / (double)(kSpecThreads + 1);
+    {
+        const double x = lo + (double)(t + 1) * hg;
+        int cnt;
+        sturm_counts<1>(dd, e2, n, &x, pivmin, &cnt);
+        cgrid[t] = cnt;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * kBisWaves + (threadIdx.x >> 6);
-    if (e >= n) return;
-    double a = tri[2 * n], b = tri[2 * n + 1];
-    const double pivmin = tri[2 * n + 2], atol = tri[2 * n + 3];
-    constexpr int NP = 2, M = 64 * NP;
-    for (int it = 0; it < 64; ++it) {
-        if (!(b - a > 2.0 * 2.2e-16 * fmax(fabs(a), fabs(b)) + atol)) break;
-        const double h = (b - a) / (M + 1);
-        double x[NP];
-        int cnt[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) x[p] = a + (double)(lane * NP + p + 1) * h;
-        sturm_counts<NP>(d, e2, n, x, pivmin, cnt);
-        double na = a, nb = b;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (cnt[p] > e) nb = fmin(nb, x[p]);
-            else na = fmax(na, x[p]);
+    // Multisection: eigenvalue e (ascending) gets a group of L lanes of one wave,
+    // which cut its interval at one point each per round and keep the part that
+    // holds it, until the width is 2 eps max(|a|, |b|) + atol or stops falling.  G groups per wave cover kSpecWaves G eigenvalues per pass.
+    const int G = min(64, (n + kSpecWaves - 1) / kSpecWaves);
+    const int L = 64 / G;
+    const int g = lane / L, sub = lane % L;
+    for (int base = 0; base < n; base += kSpecWaves * G) {
+        const int e = base + wv * G + g;
+        bool act = g < G && e < n;
+        const bool valid = act;
+        int jl = -1, jh = kSpecThreads;  // count(point jl) <= e < count(point jh)
+        while (jh - jl > 1) {
+            const int jm = (jl + jh) >> 1;
+            if (cgrid[jm] <= (valid ? e : n)) jl = jm;
+            else jh = jm;
         }
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            na = fmax(na, __shfl_xor(na, o, 64));
-            nb = fmin(nb, __shfl_xor(nb, o, 64));
+        double a = jl < 0 ? lo : lo + (double)(jl + 1) * hg;
+        double b = jh >= kSpecThreads ? hi : lo + (double)(jh + 1) * hg;
+        for (int it = 0; it < 4096; ++it) {
+            act = act && (b - a > 2.0 * 2.2e-16 * fmax(fabs(a), fabs(b)) + atol);
+            if (!__any(act)) break;
+            const double x = a + (double)(sub + 1) * ((b - a) / (double)(L + 1));
+            int cnt;
+            sturm_counts<1>(dd, e2, n, &x, pivmin, &cnt);
+            double na = cnt <= e ? x : a, nb = cnt > e ? x : b;
+            for (int j = 0; j < L; ++j) {
+                const int src = g * L + j;
+                na = fmax(na, __shfl(na, src, 64));
+                nb = fmin(nb, __shfl(nb, src, 64));
+            }
+            if (act) {
+                if (na == a && nb == b) act = false;
+                a = na;
+                b = nb;
+            }
         }
-        if (na == a && nb == b) break;
-        a = na;
-        b = nb;
+        if (valid && sub == 0) lam[e] = fabs(0.5 * (a + b));
     }
-    if (lane == 0) lam[e] = fabs(0.5 * (a + b));
-}
+    __syncthreads();
 
-// Rank |lambda| descending (ties by index), normalise, and the change against
-// s_prev (one workgroup).
-constexpr int kRankThreads = 1024;
-__global__ __launch_bounds__(kRankThreads) void rank_kernel(const double* __restrict__ lam, int n,
-                                                            const double* s_prev, int n_prev,
-                                                            double* s_out, double* delta_out) {
-    __shared__ double sorted[kMaxN];
-    __shared__ double part[2][kRankThreads / 64];
-    const int t = threadIdx.x;
-    for (int e = t; e < n; e += kRankThreads) {
+    // |lambda| ranked in descending order (ties by index), normalised, and the
+    // change against s_prev with the shorter spectrum padded by zeros
+    double* sorted = prow;
+    for (int e = t; e < n; e += kSpecThreads) {
         const double mine = lam[e];
         int rank = 0;
         for (int j = 0; j < n; ++j) {
@@ -430,27 +433,19 @@ __global__ __launch_bounds__(kRankThreads) void rank_kernel(const double* __rest
         sorted[rank] = mine;
     }
     __syncthreads();
-    auto bsum = [&](double v, double* pt) {
-        v = wave_sum(v);
-        if ((t & 63) == 0) pt[t >> 6] = v;
-        __syncthreads();
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kRankThreads / 64; ++w) s += pt[w];
-        return s;
-    };
     double ps = 0.0;
-    for (int i = t; i < n; i += kRankThreads) ps += sorted[i];
-    const double inv = 1.0 / bsum(ps, part[0]);
+    for (int i = t; i < n; i += kSpecThreads) ps += sorted[i];
+    const double inv = 1.0 / block_sum(ps, part[pb]);
+    pb ^= 1;
     double dl = 0.0;
     const int nmax = n > n_prev ? n : n_prev;
-    for (int i = t; i < nmax; i += kRankThreads) {
+    for (int i = t; i < nmax; i += kSpecThreads) {
         const double si = i < n ? sorted[i] * inv : 0.0;
         const double sp = (s_prev != nullptr && i < n_prev) ? s_prev[i] : 0.0;
         if (i < n) s_out[i] = si;
         dl += (si - sp) * (si - sp);
     }
-    const double dsum = bsum(dl, part[1]);
+    const double dsum = block_sum(dl, part[pb]);
     if (t == 0) *delta_out = sqrt(dsum);
 }
 
@@ -466,24 +461,17 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
         s.msg = "spectrum: chi must be in [1, 1024]";
         return s;
     }
-    double* tri = S + (size_t)n * n;      // d, e^2, interval, tolerance
-    double* lam = tri + 2 * (size_t)n + 4;
     auto launch = [&](auto kern, size_t tri_doubles) -> Status {
         const size_t dyn = sizeof(double) * ((size_t)kSpecWaves * n + tri_doubles);
         QRCTM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)dyn));
-        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), dyn, st, C, n, S, tri);
-        return launch_check("tridiag_kernel");
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), dyn, st, C, n, S, s_prev, n_prev, s_out,
+                           delta_out);
+        return launch_check("spectrum_kernel");
     };
-    if (n <= kLdsMaxN) QRCTM_TRY(launch(tridiag_kernel<LdsSym, kLdsMaxN>, (size_t)n * (n + 1) / 2));
-    else if (n <= 512) QRCTM_TRY(launch(tridiag_kernel<GlobalSym, 512>, 0));
-    else QRCTM_TRY(launch(tridiag_kernel<GlobalSym, kMaxN>, 0));
-    hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)ceil_div(n, kBisWaves)), dim3(64 * kBisWaves),
-                       sizeof(double) * 2 * (size_t)n, st, tri, n, lam);
-    QRCTM_TRY(launch_check("bisect_kernel"));
-    hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(kRankThreads), 0, st, lam, n, s_prev, n_prev, s_out,
-                       delta_out);
-    return launch_check("rank_kernel");
+    if (n <= kLdsMaxN) return launch(spectrum_kernel<LdsSym, kLdsMaxN>, (size_t)n * (n + 1) / 2);
+    if (n <= 512) return launch(spectrum_kernel<GlobalSym, 512>, 0);
+    return launch(spectrum_kernel<GlobalSym, kMaxN>, 0);
 }
 
 }  // namespace qrctm
