@@ -53,6 +53,8 @@ TRAFFIC_SOURCES = {
            "paper_2505_00494_amd/csrc/common.h"),
     "edge_3b": ("paper_2505_00494_amd/csrc/edge_split.hip", "paper_2505_00494_amd/csrc/edge_split.h",
                 "paper_2505_00494_amd/csrc/common.h"),
+    "edge_3c": ("paper_2505_00494_amd/csrc/gemm.hip", "paper_2505_00494_amd/csrc/step_gemms.h",
+                "paper_2505_00494_amd/csrc/common.h"),
 }
 
 
