@@ -126,6 +126,11 @@ struct GemmDesc {
     long long pC16 = 0;
     // if non-null: the product is skipped (C untouched) unless *gate == 0
     const int* gate = nullptr;
+    // if non-null: a persistent grid (as many workgroups as fit at once) draws
+    // the (tile, K split) items from this counter, which must be zero before
+    // the launch and is zero again after it (launches sharing one counter must
+    // be ordered, e.g. on one stream)
+    unsigned* ticket = nullptr;
 };
 
 // Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the

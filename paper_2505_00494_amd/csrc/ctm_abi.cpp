@@ -286,7 +286,7 @@ constexpr int kQrGridBeside = 224;
 // auxiliary stream); SL_DELTA_SCRATCH: delta of spectra computed outside the loop.
 constexpr int kDeltaSlots = 8;
 enum { SL_NORMS = 2, SL_RATIO = 4, SL_SCALE = 5, SL_BAD = 8, SL_IMAX = 10, SL_E = 16,
-       SL_DELTA = 32, SL_DELTA_SCRATCH = 48 };
+       SL_DELTA = 32, SL_DELTA_SCRATCH = 48, SL_TICKET = 56 };
 
 }  // namespace
 
@@ -371,6 +371,8 @@ struct ctm_ctx {
     double* small() const { return ptr(plan.small); }
     int* bad() const { return reinterpret_cast<int*>(ptr(plan.small) + SL_BAD); }
     int* imax() const { return reinterpret_cast<int*>(ptr(plan.small) + SL_IMAX); }
+    // counter of the step's persistent 3c GEMM (zero between launches)
+    unsigned* gemm_ticket() const { return reinterpret_cast<unsigned*>(ptr(plan.small) + SL_TICKET); }
 };
 
 namespace {
@@ -556,7 +558,15 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
         QRCTM_TRY(G(gb));
     }
     QRCTM_TRY(mark(4));
-    QRCTM_TRY(G(g_edge_c(p, p.Q, chi, chi, Dab)));                                     // a7 3c
+    {
+        // 3c on a persistent grid: the corner spectrum of the previous step runs
+        // beside it and holds a CU (measured at D = 6: a fixed grid 239 us beside
+        // it and 195 alone, the persistent one 200 and 193; 3a, with many more
+        // tiles, loses less and gains nothing)
+        GemmDesc gc = g_edge_c(p, p.Q, chi, chi, Dab);                                 // a7 3c
+        gc.ticket = c->gemm_ticket();
+        QRCTM_TRY(G(gc));
+    }
     QRCTM_TRY(mark(5));
     QRCTM_TRY(G(g_corner_w(p, chi, Dab)));                                             // a8
     QRCTM_TRY(G(g_corner_c(p, chi, Dab)));
@@ -974,7 +984,8 @@ int create(ctm_ctx** out, const Shape& sh, const ctm_opts* opts, void* ws, size_
     c->ws = static_cast<char*>(ws);
     c->ws_bytes = ws_bytes;
     c->plan = P;
-    bool ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipMemsetAsync(c->gemm_ticket(), 0, sizeof(unsigned), c->st) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_normed, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&c->ev_qrdone, hipEventDisableTiming) == hipSuccess;

@@ -39,6 +39,8 @@ struct KArgs {
     unsigned short* C16;  // non-null: the result split into three bf16 planes,
     long long pC16;       // plane s at C16[s pC16 + map(m, n)] (alpha only)
     const int* gate;      // non-null: skip unless *gate == 0
+    unsigned* ticket;     // non-null: persistent grid drawing its items (tile, split) here
+    int items;            // tiles_m tiles_n splits
 };
 
 // Matrix-core operation per compute type.  FP64: v_mfma_f64_16x16x4_f64; FP32:
@@ -72,7 +74,7 @@ __device__ __forceinline__ long long out_index(const OutMap& mp, int m, int n) {
            (n - qn * (int)mp.ndiv) * mp.ns2;
 }
 
-template <class CT, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+template <class CT, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool PERS>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs p) {
     if (p.gate != nullptr && *p.gate != 0) return;
     typedef typename Mma<CT>::acc_t acc_t;
@@ -91,9 +93,16 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
     const int wave = tid >> 6;
     const int wm = wave / NWN, wn = wave % NWN;
 
+    // Item (bid, split): tile bid of the K range split.  A fixed grid has one
+    // item per workgroup; a persistent grid (PERS, p.ticket) draws items from
+    // the counter, so that a workgroup that starts late or runs slowly (its CU
+    // shared with other work) simply takes fewer.  One ticket per item plus
+    // one that ends each workgroup; the workgroup that draws the last ticket
+    // of the launch resets the counter.
+    auto body = [&](const int bid, const int split) {
+
     // grouped tile order: GROUP consecutive tile rows share B columns in L2
     constexpr int GROUP = 8;
-    const int bid = blockIdx.x;
     const int per_group = GROUP * p.tiles_n;
     const int g = bid / per_group;
     const int first_m = g * GROUP;
@@ -102,7 +111,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
     const int tn = (bid % per_group) / gsz;
     const long long m0 = (long long)tm * BM, n0 = (long long)tn * BN;
 
-    const long long kbeg = (long long)blockIdx.y * p.kchunk;
+    const long long kbeg = (long long)split * p.kchunk;
     const long long kend = min(p.K, kbeg + p.kchunk);
 
     // raw operand values of the next two slabs, held in registers across the
@@ -245,7 +254,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
         const int qn = div_inv((int)n, (int)p.map.ndiv, p.map.ninv);
         noff[j] = p.partial ? n : qn * p.map.ns1 + (n - qn * p.map.ndiv) * p.map.ns2;
     }
-    double* Cb = p.partial ? p.C + (long long)blockIdx.y * MN : p.C;
+    double* Cb = p.partial ? p.C + (long long)split * MN : p.C;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -273,6 +282,25 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(KArgs 
                 else *o = p.beta == 0.0 ? p.alpha * v : p.alpha * v + p.beta * *o;
             }
         }
+    };
+    if constexpr (PERS) {
+        __shared__ int item_s;
+        const int ntiles = p.tiles_m * p.tiles_n;
+        while (true) {
+            __syncthreads();  // the previous item's reads of item_s and LDS are done
+            if (tid == 0) {
+                const unsigned t = atomicAdd(p.ticket, 1u);
+                if (t == (unsigned)(p.items + gridDim.x - 1)) atomicExch(p.ticket, 0u);
+                item_s = (int)min(t, (unsigned)p.items);
+            }
+            __syncthreads();
+            const int item = item_s;
+            if (item >= p.items) break;
+            body(item % ntiles, item / ntiles);
+        }
+    } else {
+        body(blockIdx.x, blockIdx.y);
+    }
 }
 
 // Sum of split-K partials, then the output map / alpha / beta.
@@ -297,8 +325,24 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, class CT = double>
 void launch_cfg(const KArgs& a, int splits, hipStream_t st) {
     constexpr int NT = (BM / WM) * (BN / WN) * 64;
+    if (a.ticket != nullptr) {
+        auto kern = gemm_kernel<CT, BM, BN, BK, WM, WN, TA, TB, true>;
+        // persistent: as many workgroups as fit on the device at once
+        static int slots = 0;
+        if (slots == 0) {
+            int dev = 0, cus = 0, per_cu = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess)
+                per_cu = cus = 0;
+            slots = std::max(1, per_cu * cus);
+        }
+        const int grid = std::min(a.items, slots);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, st, a);
+        return;
+    }
     dim3 grid(a.tiles_m * a.tiles_n, splits);
-    hipLaunchKernelGGL((gemm_kernel<CT, BM, BN, BK, WM, WN, TA, TB>), grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((gemm_kernel<CT, BM, BN, BK, WM, WN, TA, TB, false>), grid, dim3(NT), 0, st, a);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, class CT>
@@ -417,6 +461,8 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
     }
     a.tiles_m = (int)ceil_div(g.M, pl.bm);
     a.tiles_n = (int)ceil_div(g.N, pl.bn);
+    a.ticket = g.ticket;
+    a.items = a.tiles_m * a.tiles_n * pl.splits;
     if (pl.splits > 1) {
         const size_t need = (size_t)pl.splits * g.M * g.N * sizeof(double);
         if (splitk_ws == nullptr || splitk_bytes < need) {
