@@ -373,6 +373,19 @@ constexpr int kTargetBlocks = 512;
 // 1024 1.25e-7 / 2.3e-8, 512 4.2e-8 / 7.3e-8, 256 4.0e-8 / 3.0e-8 but slower)
 constexpr long long kF32Chunk = 512;
 
+// compute units of the current device (256 if the query fails)
+long long device_cus() {
+    static long long cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cus = n;
+    }
+    return cus;
+}
+
 // Tile choice measured on the step's shapes: large M and N take 128x128; a
 // skinny N (the edge contraction 3c, N = chi) takes 128x48 tiles with split-K;
 // everything else 64x64.  Split-K brings small grids to about 2 blocks per CU.
@@ -405,6 +418,23 @@ Plan make_plan(const GemmDesc& g) {
         if (s >= 2) {
             long long kc = ceil_div(g.K, s);
             kc = ceil_div(kc, 16) * 16;
+            pl.splits = (int)ceil_div(g.K, kc);
+            pl.kchunk = kc;
+        }
+    }
+    // Tiles a little over a multiple of the CU count leave a last, nearly empty
+    // round of tiles (measured: 3c at D = 6, chi = 320, 270 tiles of 128 x 128,
+    // took twice 3a's time for the same flops).  Where there are at least as
+    // many tiles as CUs, K is split into the s that minimises the rounds per
+    // unit of work, ceil(tiles s / CUs) / s, if that beats no split by 10%.
+    if (pl.splits == 1 && tiles >= device_cus() && g.K >= 1024 && g.C16 == nullptr) {
+        const long long cus = device_cus();
+        auto cost = [&](long long s) { return (double)ceil_div(tiles * s, cus) / (double)s; };
+        long long best = 1;
+        for (long long s = 2; s <= 8 && g.K / s >= 256; ++s)
+            if (cost(s) < cost(best) - 1e-9) best = s;
+        if (cost(best) < 0.9 * cost(1)) {
+            long long kc = ceil_div(ceil_div(g.K, best), 16) * 16;
             pl.splits = (int)ceil_div(g.K, kc);
             pl.kchunk = kc;
         }
