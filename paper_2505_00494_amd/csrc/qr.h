@@ -12,7 +12,7 @@ struct QrScratch {
 
 // Cholesky-QR2 (qr_chol.hip): scratch layout relative to QrScratch::off_chol.
 struct CholQrScratch {
-    size_t off_Q1, off_part, off_G, off_R1, off_R2, off_Ri, off_W, off_work, off_stats, off_state,
+    size_t off_Q1, off_part, off_G, off_R1, off_R2, off_Ri, off_work, off_stats, off_state,
         off_dev, off_splitk;
     size_t splitk_bytes, total;
 };

@@ -29,8 +29,10 @@
 //    also yields W_K = R_KK^{-T}; all waves form the block row W_K B_KJ, and in
 //    the trailing update B_IJ -= B_KI^T B_KJ (matrix cores) wave 0 takes the
 //    next diagonal block and factors it at once while the others update the
-//    rest (two barriers per block column).  Then R^{-1} by block rows from
-//    the bottom, X_IJ = -W_I^T sum_{I<k<=J} R_Ik X_kJ, X_II = W_I^T.  In pass
+//    rest (two barriers per block column).  The same row operations applied
+//    to the identity give R^{-T} (Gauss-Jordan), kept in the slots of the
+//    finished block rows of R; the waves that do not factor write R and
+//    R^{-1} out block by block as they become final.  In pass
 //    2, when max |G2 - I| is below 1e-8, R2 = I + E_u (E = G2 - I, E_u its
 //    upper triangle with half the diagonal) and R2^{-1} = I - E_u, exact to
 //    |E|^2, below the rounding unit, replace the factorisation: the Gram
@@ -191,15 +193,24 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky G = R^T R of the n x n G (one workgroup), then R^{-1}.  Writes R
-// and Ri = R^{-1} (n x n, upper, zeros below), the state word and, in pass 1,
-// the extreme pivots.  W: nb blocks of scratch for R_KK^{-T}.
+// Cholesky G = R^T R of the n x n G (one workgroup) and R^{-1} with it.
+// Writes R and Ri = R^{-1} (n x n, upper, zeros below), the state word and,
+// in pass 1, the extreme pivots.
+//
+// Row operations that take G to R take [G | I] to [R | R^{-T}], so R^{-1} is
+// accumulated beside the factorisation (Gauss-Jordan on the block triangle):
+// block row K of R^{-T}, X_KJ (J < K), goes through the same steps as R's,
+// X_KJ <- W_K X_KJ with W_K = R_KK^{-T}, and its trailing update is
+// X_IJ -= R_KI^T X_KJ (I > K).  X_IJ (J < I) lives in the slot of R_JI, which
+// step J still reads; the slot turns into X_IJ at step J + 1, whose first
+// touch also adds the term X_IJ = -R_JI^T W_J that step J would have written.
+// Each slot is written by one wave per phase and read by no other in it.
 // ---------------------------------------------------------------------------
 template <bool kLds>
 __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __restrict__ G, int n,
                                                             int pass, double* work, double* R,
-                                                            double* Ri, double* W, int* state,
-                                                            double* stats, unsigned long long* devw) {
+                                                            double* Ri, int* state, double* stats,
+                                                            unsigned long long* devw) {
     extern __shared__ double lds[];
     if (pass == 2 && *state != 0) return;
     if (pass == 1 && devw != nullptr && threadIdx.x == 0) *devw = 0ull;
@@ -211,8 +222,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     }
     const int nb = (n + kB - 1) / kB;
     const int nblk = nb * (nb + 1) / 2;
-    double* B = kLds ? lds : work;                        // block triangle
-    double* Wl = kLds ? lds + (size_t)nblk * 256 : lds;   // W_K of the current block
+    double* B = kLds ? lds : work;                                 // block triangle
+    double* const Wr = kLds ? lds + (size_t)nblk * 256 : lds;      // W_K, ring of three
     __shared__ int bad;
     __shared__ double dev_max;
     __shared__ double piv_min, piv_max;
@@ -226,62 +237,66 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     }
     __syncthreads();
     auto blk = [&](int I, int J) { return B + (size_t)tri_index(I, J, nb) * 256; };
-    // Element pairs (gi, gj) row by row: wave w takes rows w, w + 8, ..., lane l
-    // the columns l, l + 64, ...; kU pairs per lane at a time, in order.
-    const int nch = (n + 63) / 64;
-    constexpr int kU = 32;
-    // load the upper block triangle (identity beyond n): G read row by row
-    // (coalesced), kU independent loads in flight per lane
+    auto wblk = [&](int K) { return Wr + (K % 3) * 256; };
+    // load the upper block triangle (identity beyond n): element e of the
+    // triangle is element e % 256 of block e / 256 (row by row), thread t takes
+    // e = t, t + 512, ...: a wave reads whole rows of 16 of G, and kU loads per
+    // lane are in flight (one round at chi <= 176)
     {
+        constexpr int kU = 24;
+        const int total = nblk * 256;
         double dv = 0.0;
         int nf = 0;
-        int row0 = wave, ch0 = 0;
-        while (row0 < n) {
+        const bool first_order = pass == 2 && devw == nullptr;
+        for (int e0 = tid; e0 < total; e0 += kU * kCholThreads) {
+            int bi, bj;
+            tile_of(e0 >> 8, nb, bi, bj);
+            int I = bi, J = bj;
             double v[kU];
-            int row = row0, ch = ch0;
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int gj = ch * 64 + lane;
-                v[u] = (row < n && gj < n) ? G[row * n + gj] : 0.0;
-                if (++ch == nch) {
-                    ch = 0;
-                    row += kCholWaves;
+            for (int u = 0; u < kU; ++u) {  // block of e0 + 512 u: two blocks on each time
+                const int e = e0 + u * kCholThreads;
+                const int gi = I * kB + ((e >> 4) & 15), gj = J * kB + (e & 15);
+                v[u] = (e < total && gi < n && gj < n) ? G[(size_t)gi * n + gj] : (gi == gj ? 1.0 : 0.0);
+                J += 2;
+                while (J >= nb && I < nb) {
+                    ++I;
+                    J += I - nb;
                 }
             }
-            row = row0;
-            ch = ch0;
+            I = bi;
+            J = bj;
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int gi = row, gj = ch * 64 + lane;
-                if (++ch == nch) {
-                    ch = 0;
-                    row += kCholWaves;
+                const int e = e0 + u * kCholThreads;
+                if (e < total) {
+                    const int gi = I * kB + ((e >> 4) & 15), gj = J * kB + (e & 15);
+                    blk(I, J)[e & 255] = v[u];
+                    if (gi < n && gj < n && gj >= gi) {
+                        if (!isfinite(v[u])) nf = 1;
+                        dv = fmax(dv, fabs(v[u] - (gi == gj ? 1.0 : 0.0)));
+                        if (first_order) {
+                            // the first-order factors (kept if max |G - I| <= 1e-8, else
+                            // overwritten below): R2 = I + E_u, R2^{-1} = I - E_u, E_u the
+                            // upper triangle of E = G - I with half its diagonal
+                            const double x = gj > gi ? v[u] : 0.5 * (v[u] - 1.0);
+                            R[(size_t)gi * n + gj] = (gi == gj ? 1.0 : 0.0) + x;
+                            Ri[(size_t)gi * n + gj] = (gi == gj ? 1.0 : 0.0) - x;
+                        }
+                    }
                 }
-                if (gi >= n || gj >= n) continue;
-                if (pass == 2) {
-                    // the first-order factors (kept if max |G - I| <= 1e-8, else
-                    // overwritten below): R2 = I + E_u, R2^{-1} = I - E_u, E_u the
-                    // upper triangle of E = G - I with half its diagonal
-                    const double x = gj > gi ? v[u] : (gj == gi ? 0.5 * (v[u] - 1.0) : 0.0);
-                    R[gi * n + gj] = (gi == gj ? 1.0 : 0.0) + x;
-                    Ri[gi * n + gj] = (gi == gj ? 1.0 : 0.0) - x;
+                J += 2;
+                while (J >= nb && I < nb) {
+                    ++I;
+                    J += I - nb;
                 }
-                if (gj < gi) continue;
-                if (!isfinite(v[u])) nf = 1;
-                dv = fmax(dv, fabs(v[u] - (gi == gj ? 1.0 : 0.0)));
-                blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] = v[u];
             }
-            row0 = row;
-            ch0 = ch;
         }
-        const int pad0 = n, pad1 = nb * kB;
-        for (int e = tid; e < (pad1 - pad0) * pad1; e += kCholThreads) {
-            const int gi = pad0 + e / pad1, gj = e % pad1;
-            if (gj >= gi) blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] = gi == gj ? 1.0 : 0.0;
-        }
-        for (int e = tid; e < pad0 * (pad1 - pad0); e += kCholThreads) {
-            const int gi = e / (pad1 - pad0), gj = pad0 + e % (pad1 - pad0);
-            blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] = 0.0;
+        if (first_order) {
+            for (int e = tid; e < n * n; e += kCholThreads) {
+                const int gi = e / n, gj = e % n;
+                if (gj < gi) R[e] = Ri[e] = 0.0;
+            }
         }
         if (nf) atomicOr(&bad, 1);
         if (pass == 2) {
@@ -296,12 +311,17 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
         return;
     }
     // diagonal block K: wave 0 eliminates on [B_KK | I] (lane c < 16: column c of
-    // B_KK, lane 16 + c: column c of I); its rows become R_KK and R_KK^{-T}.
-    // Per pivot j: row j is scaled by r = 1/sqrt(p) and row i > j loses
-    // B_ji r^2 times row j (the multipliers B_ji read from lane i).  1/sqrt:
-    // the hardware estimate and two Newton steps.
+    // B_KK, lane 16 + c: column c of I); its rows become R_KK and W_K = R_KK^{-T}.
+    // Per pivot j (p = B_jj): row i > j loses B_ji / p times row j (the
+    // multipliers B_ji read from lane i), row j + 1 first, as its lane j + 1
+    // holds the next pivot; then row j is scaled by 1/sqrt(p).  Only 1/p lies
+    // on the chain from one pivot to the next (the hardware estimate and two
+    // Newton steps); 1/sqrt(p) likewise, beside it.  A pivot that is not
+    // positive or not finite is recorded and replaced by 1 (the pass is then
+    // rejected).
     auto factor_diag = [&](int K) {
         double* bk = blk(K, K);
+        double* wk = wblk(K);
         const int c = lane & 31;
         double b[kB];
 #pragma unroll
@@ -322,29 +342,29 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
                 nonpos = 1;
                 p = 1.0;
             }
+            double y = __builtin_amdgcn_rcp(p);
+            y = fma(y, fma(-p, y, 1.0), y);
+            y = fma(y, fma(-p, y, 1.0), y);
+            const double tj = b[j] * y;
+#pragma unroll
+            for (int i = j + 1; i < kB; ++i) b[i] = fma(-m[i], tj, b[i]);
             double r = __builtin_amdgcn_rsq(p);
             const double hp = 0.5 * p;
             r = r * fma(-hp * r, r, 1.5);
             r = r * fma(-hp * r, r, 1.5);
+            b[j] *= r;
             const double dj = p * r;
             if (K * kB + j < n) {
                 pmin = fmin(pmin, dj);
                 pmax = fmax(pmax, dj);
             }
-            const double tj = b[j] * (r * r);
-            b[j] *= r;
-#pragma unroll
-            for (int i = j + 1; i < kB; ++i) b[i] = fma(-m[i], tj, b[i]);
         }
         if (lane < 16) {
 #pragma unroll
             for (int r = 0; r < kB; ++r) bk[r * kB + c] = r <= c ? b[r] : 0.0;
         } else if (lane < 32) {
 #pragma unroll
-            for (int r = 0; r < kB; ++r) {
-                Wl[r * kB + (c - 16)] = b[r];
-                W[(size_t)K * 256 + r * kB + (c - 16)] = b[r];
-            }
+            for (int r = 0; r < kB; ++r) wk[r * kB + (c - 16)] = b[r];
         }
         if (lane == 0) {
             if (nonpos) bad |= 2;
@@ -352,146 +372,195 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
             piv_max = fmax(piv_max, pmax);
         }
     };
-    // B_IJ -= B_KI^T B_KJ on the matrix cores (one wave)
-    auto trail = [&](int K, int I, int J) {
-        const double* bi = blk(K, I);
-        const double* bj = blk(K, J);
-        double* bij = blk(I, J);
-        dbl4 acc;
+    // 16 x 16 products of one wave on the matrix cores.  acc in the accumulator
+    // layout (lane l, register r: element (4 r + l / 16, l % 16)), which is also
+    // the B-operand layout of a next product.  mm_tn: acc -= a^T b; mm_nn2:
+    // a b; mm_nr: acc += a t with t held in registers.
+    auto ld = [&](const double* d) {
+        dbl4 x;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = bij[(4 * r + kl) * kB + cl];
+        for (int r = 0; r < 4; ++r) x[r] = d[(4 * r + kl) * kB + cl];
+        return x;
+    };
+    auto st = [&](double* d, const dbl4& x) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[(4 * r + kl) * kB + cl] = x[r];
+    };
+    auto mm_tn = [&](dbl4 acc, const double* a, const double* b) {
+        double av[4], bv[4];
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
-            const int k = 4 * s4 + kl;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi[k * kB + cl], bj[k * kB + cl], acc, 0, 0, 0);
+            av[s4] = -a[(4 * s4 + kl) * kB + cl];
+            bv[s4] = b[(4 * s4 + kl) * kB + cl];
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) bij[(4 * r + kl) * kB + cl] = acc[r];
+        for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4], acc, 0, 0, 0);
+        return acc;
+    };
+    auto mm_nn2 = [&](const double* a, const double* b) {  // a b, two chains of two steps
+        double av[4], bv[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            av[s4] = a[cl * kB + 4 * s4 + kl];
+            bv[s4] = b[(4 * s4 + kl) * kB + cl];
+        }
+        dbl4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], bv[2], c1, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], bv[3], c1, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c0[r] += c1[r];
+        return c0;
+    };
+    auto mm_nr = [&](dbl4 acc, const double* a, const dbl4& t) {
+        double av[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) av[s4] = a[cl * kB + 4 * s4 + kl];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], t[s4], acc, 0, 0, 0);
+        return acc;
+    };
+    const dbl4 zero4 = {0.0, 0.0, 0.0, 0.0};
+    // block (K, J) of R and block (J, K) of Ri = X^T (X_KJ, J < K, in the slot
+    // of (J, K); X_KK = W_K), zeros outside the triangles, to global memory
+    auto write_out = [&](int K, int J) {
+        const double* rs = J >= K ? blk(K, J) : nullptr;
+        const double* xs = J < K ? blk(J, K) : (J == K ? wblk(K) : nullptr);
+        double rv[4], xv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            rv[r] = rs != nullptr ? rs[(4 * r + kl) * kB + cl] : 0.0;
+            xv[r] = xs != nullptr ? xs[cl * kB + 4 * r + kl] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = 4 * r + kl;
+            const int ri = K * kB + a, rj = J * kB + cl;  // R element (ri, rj)
+            if (ri < n && rj < n) R[(size_t)ri * n + rj] = rv[r];
+            const int xi = J * kB + a, xj = K * kB + cl;  // Ri element (xi, xj) = X_KJ[cl][a]
+            if (xi < n && xj < n) Ri[(size_t)xi * n + xj] = xv[r];
+        }
+    };
+    // one trailing block: s -= a^T b, where s first becomes -s^T w if `first`
+    // (the slot's first touch); two of them at a time, so that the loads and
+    // the two chains of matrix-core steps overlap
+    struct Item {
+        double* s;
+        const double* a;
+        const double* b;
+        const double* w;
+        bool first;
+    };
+    auto two_items = [&](const Item& x, const Item& y, bool store_y) {
+        double xs[4], ys[4], xa[4], xb[4], ya[4], yb[4], xw[4], yw[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int o = (4 * s4 + kl) * kB + cl;
+            xs[s4] = x.s[o];
+            ys[s4] = y.s[o];
+            xa[s4] = -x.a[o];
+            xb[s4] = x.b[o];
+            ya[s4] = -y.a[o];
+            yb[s4] = y.b[o];
+            xw[s4] = x.w[o];
+            yw[s4] = y.w[o];
+        }
+        dbl4 ax = {xs[0], xs[1], xs[2], xs[3]}, ay = {ys[0], ys[1], ys[2], ys[3]};
+        if (x.first) {
+            ax = zero4;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) ax = __builtin_amdgcn_mfma_f64_16x16x4f64(-xs[s4], xw[s4], ax, 0, 0, 0);
+        }
+        if (y.first) {
+            ay = zero4;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) ay = __builtin_amdgcn_mfma_f64_16x16x4f64(-ys[s4], yw[s4], ay, 0, 0, 0);
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            ax = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[s4], xb[s4], ax, 0, 0, 0);
+            ay = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[s4], yb[s4], ay, 0, 0, 0);
+        }
+        st(x.s, ax);
+        if (store_y) st(y.s, ay);
     };
     if (wave == 0) factor_diag(0);
     __syncthreads();
     for (int K = 0; K < nb; ++K) {
-        // block row: B_KJ <- W_K B_KJ for J > K
-        for (int J = K + 1 + wave; J < nb; J += kCholWaves) {
-            double* bj = blk(K, J);
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int k = 4 * s4 + kl;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[cl * kB + k], bj[k * kB + cl], acc, 0, 0, 0);
+        // block row K: R_KJ = W_K B_KJ (J > K) and X_KJ <- W_K X_KJ (J < K); the
+        // slot of (K - 1, K) still holds R_{K-1,K}, so X_{K,K-1} = -W_K R_{K-1,K}^T W_{K-1}
+        for (int t = wave; t < nb - 1; t += kCholWaves) {
+            const int J = t < K ? t : t + 1;
+            double* s = J > K ? blk(K, J) : blk(J, K);
+            if (J == K - 1) {
+                const dbl4 u = mm_tn(zero4, s, wblk(K - 1));
+                st(s, mm_nr(zero4, wblk(K), u));
+            } else {
+                st(s, mm_nn2(wblk(K), s));
             }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bj[(4 * r + kl) * kB + cl] = acc[r];
         }
         __syncthreads();
-        if (K + 1 == nb) break;
-        // trailing blocks K < I <= J: wave 0 updates B_{K+1,K+1} and factors it
-        // (lookahead), the other waves take the remaining blocks
+        if (K + 1 == nb) {
+            for (int J = wave; J < nb; J += kCholWaves) write_out(K, J);
+            break;
+        }
+        // trailing blocks: wave 0 updates B_{K+1,K+1} and factors it (lookahead);
+        // the other waves take B_IJ -= R_KI^T R_KJ (K < I <= J), X_IJ -= R_KI^T X_KJ
+        // (I > K, J < K; at J = K - 1 the slot's first touch, X_IJ = -R_JI^T W_J
+        // first), and write block row K of R and block column K of Ri
         if (wave == 0) {
-            trail(K, K + 1, K + 1);
+            double* s = blk(K + 1, K + 1);
+            st(s, mm_tn(ld(s), blk(K, K + 1), blk(K, K + 1)));
             factor_diag(K + 1);
         } else {
-            int p = 0;
-            for (int I = K + 1; I < nb; ++I) {
-                for (int J = I; J < nb; ++J) {
-                    if (I == K + 1 && J == K + 1) continue;
-                    if (p++ % (kCholWaves - 1) == wave - 1) trail(K, I, J);
+            // items: the trailing blocks of B after (K+1, K+1), row by row; the
+            // blocks X_IJ (I > K, J < K); the write-outs.  Wave w takes items
+            // w - 1, w + 6, ..., two at a time.
+            const int nt = nb - K - 1;
+            const int nleft = nt * (nt + 1) / 2 - 1, nx = nt * K;
+            auto item = [&](int q) {
+                Item it;
+                if (q < nleft) {
+                    int i, j;
+                    tile_of(q + 1, nt, i, j);
+                    it.s = blk(K + 1 + i, K + 1 + j);
+                    it.a = blk(K, K + 1 + i);
+                    it.b = blk(K, K + 1 + j);
+                    it.w = it.s;
+                    it.first = false;
+                } else {
+                    const int t = q - nleft, I = K + 1 + t / K, J = t % K;
+                    it.s = blk(J, I);
+                    it.a = blk(K, I);
+                    it.b = blk(J, K);
+                    it.first = J == K - 1;
+                    it.w = it.first ? wblk(J) : it.s;
                 }
+                return it;
+            };
+            constexpr int kTw = kCholWaves - 1;
+            for (int q = wave - 1; q < nleft + nx; q += 2 * kTw) {
+                const bool two = q + kTw < nleft + nx;
+                const Item x = item(q);
+                two_items(x, two ? item(q + kTw) : x, two);
             }
+            for (int q = nleft + nx; q < nleft + nx + nb; ++q)
+                if (q % kTw == wave - 1) write_out(K, q - nleft - nx);
         }
         __syncthreads();
     }
-    // R (n x n, upper) and the verdict
-    for (int gi = wave; gi < n; gi += kCholWaves)
-        for (int gj = lane; gj < n; gj += 64)
-            R[gi * n + gj] = gj >= gi ? blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] : 0.0;
     if (tid == 0) {
-        int st = 0;
+        int st_ = 0;
         if (pass == 1) {
-            if (bad || !(piv_min >= kPass1MinRatio * piv_max)) st = 1;
+            if (bad || !(piv_min >= kPass1MinRatio * piv_max)) st_ = 1;
             stats[0] = piv_min;
             stats[1] = piv_max;
         } else {
-            if (bad || !(dev_max <= kPass2MaxDev)) st = 2;
+            if (bad || !(dev_max <= kPass2MaxDev)) st_ = 2;
         }
-        *state = st;
+        *state = st_;
     }
-    // R^{-1} by block rows from the bottom: X_II = W_I^T and, for J > I,
-    // X_IJ = -W_I^T T with T = sum_{I<k<=J} R_Ik X_kJ (T in the accumulator
-    // layout is already the B operand of the second product).  In LDS, block
-    // row I of X replaces that of R once every wave has read it; in global
-    // memory X goes to Ri directly and is read back from there.
-    __syncthreads();
-    constexpr int kMaxJ = kLds ? (kCholLdsMaxNb + kCholWaves - 1) / kCholWaves : 1;
-    for (int I = nb - 1; I >= 0; --I) {
-        const double* wi = W + (size_t)I * 256;
-        dbl4 keep[kMaxJ];
-        int nj = 0;
-        for (int J = I + wave; J < nb; J += kCholWaves, ++nj) {
-            // the sum in two independent accumulators (k and k + 1), so that
-            // consecutive MFMAs do not wait for each other
-            auto xop = [&](int k, int kk) -> double {
-                if (kLds) return blk(k, J)[kk * kB + cl];
-                return (k * kB + kk < n && J * kB + cl < n) ? Ri[(k * kB + kk) * n + J * kB + cl] : 0.0;
-            };
-            dbl4 t = {0.0, 0.0, 0.0, 0.0}, t1 = {0.0, 0.0, 0.0, 0.0};
-            for (int k = I + 1; k <= J; k += 2) {
-                const bool two = k + 1 <= J;  // wave-uniform
-                const double* rik = blk(I, k);
-                const double* rik1 = blk(I, two ? k + 1 : k);
-                double a0[4], x0[4], a1[4], x1[4];
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    const int kk = 4 * s4 + kl;
-                    a0[s4] = rik[cl * kB + kk];
-                    x0[s4] = xop(k, kk);
-                    a1[s4] = rik1[cl * kB + kk];
-                    x1[s4] = two ? xop(k + 1, kk) : 0.0;
-                }
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    t = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s4], x0[s4], t, 0, 0, 0);
-                    if (two) t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s4], x1[s4], t1, 0, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t[r] += t1[r];
-            dbl4 x = {0.0, 0.0, 0.0, 0.0};
-            if (J == I) {
-                // X_II = W_I^T: element (4 r + kl, cl) = W_I[cl][4 r + kl]
-#pragma unroll
-                for (int r = 0; r < 4; ++r) x[r] = wi[cl * kB + 4 * r + kl];
-            } else {
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
-                    x = __builtin_amdgcn_mfma_f64_16x16x4f64(-wi[(4 * s4 + kl) * kB + cl], t[s4], x, 0, 0, 0);
-            }
-            if (kLds) {
-                keep[nj] = x;
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int gi = I * kB + 4 * r + kl, gj = J * kB + cl;
-                    if (gi < n && gj < n) Ri[(size_t)gi * n + gj] = x[r];
-                }
-            }
-        }
-        __syncthreads();
-        if (kLds) {
-            nj = 0;
-            for (int J = I + wave; J < nb; J += kCholWaves, ++nj) {
-                double* xij = blk(I, J);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) xij[(4 * r + kl) * kB + cl] = keep[nj][r];
-            }
-            __syncthreads();
-        }
-    }
-    for (int gi = wave; gi < n; gi += kCholWaves)
-        for (int gj = lane; gj < n; gj += 64) {
-            if (kLds) Ri[gi * n + gj] = gj >= gi ? blk(gi / kB, gj / kB)[(gi % kB) * kB + gj % kB] : 0.0;
-            else if (gj < gi) Ri[gi * n + gj] = 0.0;
-        }
 }
 
 // R = R2 R1 (upper, zeros below) by 16 x 16 blocks, one per wave, and the
@@ -599,7 +668,6 @@ CholQrScratch cholqr_scratch_layout(int m, int n) {
     s.off_R1 = take(sizeof(double) * (size_t)n * n);
     s.off_R2 = take(sizeof(double) * (size_t)n * n);
     s.off_Ri = take(sizeof(double) * (size_t)n * n);
-    s.off_W = take(sizeof(double) * (size_t)nb * 256);
     s.off_work = take(nb > kCholLdsMaxNb ? sizeof(double) * (size_t)nb * (nb + 1) / 2 * 256 : 0);
     s.off_stats = take(sizeof(double) * 4);
     s.off_state = take(sizeof(int));
@@ -620,7 +688,6 @@ Status cholqr2(const double* M, double* Q, double* R, int m, int n, char* base,
     double* R1 = reinterpret_cast<double*>(base + L.off_R1);
     double* R2 = reinterpret_cast<double*>(base + L.off_R2);
     double* Ri = reinterpret_cast<double*>(base + L.off_Ri);
-    double* W = reinterpret_cast<double*>(base + L.off_W);
     double* work = reinterpret_cast<double*>(base + L.off_work);
     double* stats = reinterpret_cast<double*>(base + L.off_stats);
     int* state = reinterpret_cast<int*>(base + L.off_state);
@@ -630,7 +697,7 @@ Status cholqr2(const double* M, double* Q, double* R, int m, int n, char* base,
 
     const bool in_lds = nb <= kCholLdsMaxNb;
     const size_t chol_lds =
-        sizeof(double) * (in_lds ? (size_t)nb * (nb + 1) / 2 * 256 + 256 : 256);
+        sizeof(double) * ((in_lds ? (size_t)nb * (nb + 1) / 2 * 256 : 0) + 3 * 256);
     const void* chol = in_lds ? (const void*)chol_kernel<true> : (const void*)chol_kernel<false>;
     QRCTM_HIP(hipFuncSetAttribute(chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds));
     const int nblk = nb * (nb + 1) / 2;
@@ -651,10 +718,10 @@ Status cholqr2(const double* M, double* Q, double* R, int m, int n, char* base,
         unsigned long long* dw = g.S > 1 ? devw : nullptr;
         if (in_lds)
             hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(kCholThreads), chol_lds, st, G, n, pass,
-                               work, Rp, Ri, W, state, stats, dw);
+                               work, Rp, Ri, state, stats, dw);
         else
             hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(kCholThreads), chol_lds, st, G, n, pass,
-                               work, Rp, Ri, W, state, stats, dw);
+                               work, Rp, Ri, state, stats, dw);
         QRCTM_TRY(launch_check("chol_kernel"));
         // Q1 = M R1^{-1} into scratch; Q = Q1 R2^{-1} only if both passes were accepted
         GemmDesc sd = solve_desc(X, Ri, pass == 1 ? Q1 : Q, m, n);

@@ -48,8 +48,8 @@ def test_gemm_alpha_beta_and_split_k():
     _gemm_case(200, 200, 40, 0, 0, 2.0, 1.0, seed=4)
 
 
-@pytest.mark.parametrize("m,n", [(64, 16), (1000, 37), (1024, 64), (5184, 144), (9604, 196),
-                                 (16384, 256), (2400, 600), (21600, 600), (4096, 1024)])
+@pytest.mark.parametrize("m,n", [(64, 16), (500, 17), (1000, 37), (1024, 64), (5184, 144), (3000, 170),
+                                 (9604, 196), (16384, 256), (2400, 600), (21600, 600), (4096, 1024)])
 def test_qr_matches_oracle(m, n):
     print(f"qr m={m} n={n}", flush=True)
     rng = np.random.default_rng(m + n)
