@@ -3,7 +3,8 @@
 // in the normalised corner spectrum is the measure used here).
 //
 // One kernel of one workgroup (512 threads) on the caller's stream, so that
-// beside a running step it occupies a single CU:
+// beside a running step it occupies a single CU (with all of that CU's LDS, so
+// that no workgroup of the step shares it):
 //  * Householder tridiagonalisation of the symmetric chi x chi corner, keeping
 //    only its lower triangle (packed in LDS up to chi = 176, beyond that
 //    row-major in global scratch, L2 resident).  The rank-2 update of each
@@ -462,7 +463,16 @@ Status corner_spectrum(const double* C, int n, double* S, const double* s_prev, 
         return s;
     }
     auto launch = [&](auto kern, size_t tri_doubles) -> Status {
-        const size_t dyn = sizeof(double) * ((size_t)kSpecWaves * n + tri_doubles);
+        size_t dyn = sizeof(double) * ((size_t)kSpecWaves * n + tri_doubles);
+        {
+            // all of the CU's LDS, so that no workgroup of the step beside it
+            // shares the CU (measured at D = 6, chi = 144: the spectrum beside the
+            // step 866 -> 837 us, the step 1185 -> 1195 steps/s)
+            hipFuncAttributes fa;
+            QRCTM_HIP(hipFuncGetAttributes(&fa, (const void*)kern));
+            const size_t whole = 160 * 1024;
+            if (fa.sharedSizeBytes + dyn < whole) dyn = whole - fa.sharedSizeBytes;
+        }
         QRCTM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)dyn));
         hipLaunchKernelGGL(kern, dim3(1), dim3(kSpecThreads), dyn, st, C, n, S, s_prev, n_prev, s_out,
