@@ -662,11 +662,26 @@ __attribute__((amdgpu_waves_per_eu(ShapeBw<D>::WPE))) void edge_split_bw_kernel(
                         const double* As_ = kind ? ys : xs;
                         const double* Bs_ = kind ? xbs : zs;
                         const int oa = (16 * it + l16) * LDM + q, ob = (16 * jt + l16) * LDM + q;
+                        if constexpr (D <= 6) {
+                            // the K sum in two chains (even and odd k steps), so that
+                            // consecutive matrix-core steps do not wait for each other
+                            dbl4 a1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll S::KU2
-                        for (int kk = 0; kk < MP / 4; ++kk)
-                            ab[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(As_[oa + 4 * kk],
-                                                                           Bs_[ob + 4 * kk],
-                                                                           ab[s][t], 0, 0, 0);
+                            for (int kk = 0; kk < MP / 4; kk += 2) {
+                                ab[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                    As_[oa + 4 * kk], Bs_[ob + 4 * kk], ab[s][t], 0, 0, 0);
+                                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(As_[oa + 4 * kk + 4],
+                                                                         Bs_[ob + 4 * kk + 4], a1, 0,
+                                                                         0, 0);
+                            }
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) ab[s][t][r] += a1[r];
+                        } else {
+#pragma unroll S::KU2
+                            for (int kk = 0; kk < MP / 4; ++kk)
+                                ab[s][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                    As_[oa + 4 * kk], Bs_[ob + 4 * kk], ab[s][t], 0, 0, 0);
+                        }
                     }
                 }
             }
