@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     // load the upper block triangle (identity beyond n): element e of the
     // triangle is element e % 256 of block e / 256 (row by row), thread t takes
     // e = t, t + 512, ...: a wave reads whole rows of 16 of G, and kU loads per
-    // lane are in flight (one round at chi <= 176)
+    // lane are in flight (one round up to chi = 144, two up to 176)
     {
         constexpr int kU = 24;
         const int total = nblk * 256;
