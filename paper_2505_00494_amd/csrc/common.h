@@ -131,6 +131,9 @@ struct GemmDesc {
     // the launch and is zero again after it (launches sharing one counter must
     // be ordered, e.g. on one stream)
     unsigned* ticket = nullptr;
+    // may run as the vendor BLAS's dgemm when it is a plain FP64 product of at
+    // least 3e10 flop (set by the callers whose products were measured there)
+    bool vendor = false;
 };
 
 // Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the

@@ -15,7 +15,19 @@
 // takes the k range [q BK/4, (q+1) BK/4): every lane fetches all of its
 // operand values for the slab with 16-byte reads, and the 16 lanes of a
 // quarter-wave (16 rows, stride BK * size + 16 bytes) hit distinct banks.
+//
+// The one exception: a plain FP64 product (row-major C, no gate, no split
+// planes) of at least kVendorMinFlop whose caller allows it (GemmDesc::vendor)
+// goes to the vendor BLAS (rocBLAS dgemm, atomics off, so the result is
+// reproducible).  On the step's shapes it runs at
+// 0.83-0.94 of the FP64 peak at chi D^2 = 16384 where these kernels reach
+// 0.55-0.58; below that size they are as fast or the persistent grid of the
+// kernel above wins beside the corner spectrum.
 #include "common.h"
+
+#include <rocblas/rocblas.h>
+
+#include <mutex>
 
 #ifndef MMA_F32_ROW
 #define MMA_F32_ROW(r, q) (4 * (q) + (r))
@@ -455,6 +467,65 @@ size_t gemm_splitk_bytes(const GemmDesc& g) {
     return pl.splits > 1 ? (size_t)pl.splits * g.M * g.N * sizeof(double) : 0;
 }
 
+namespace {
+
+constexpr double kVendorMinFlop = 3.0e10;  // 2 M N K (chi D^2 = 16384: 3c 1.4e11)
+constexpr int kMaxDevices = 16;
+
+bool plain_output(const GemmDesc& g) {
+    const OutMap& m = g.map;
+    return m.ms1 == 0 && m.ns1 == 0 && m.ns2 == 1 && m.mdiv >= g.M && m.ndiv >= g.N && m.ms2 >= g.N;
+}
+
+bool vendor_eligible(const GemmDesc& g) {
+    return g.vendor && g.prec == 0 && g.gate == nullptr && g.A16 == nullptr && g.B16 == nullptr && g.C16 == nullptr &&
+           plain_output(g) && 2.0 * (double)g.M * (double)g.N * (double)g.K >= kVendorMinFlop;
+}
+
+// one handle per device, made on first use (rocBLAS takes its own workspace
+// then); calls on one device are serialised, as a handle has one stream
+std::mutex g_vendor_mu;
+rocblas_handle g_vendor[kMaxDevices] = {};
+
+Status vendor_dgemm(const GemmDesc& g, hipStream_t st) {
+    Status s;
+    int dev = 0;
+    QRCTM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        s.code = -1;
+        s.msg = "gemm_f64: device index out of range for the vendor BLAS";
+        return s;
+    }
+    std::lock_guard<std::mutex> lk(g_vendor_mu);
+    if (g_vendor[dev] == nullptr) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success ||
+            rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success) {
+            if (h) rocblas_destroy_handle(h);
+            s.code = -3;
+            s.msg = "gemm_f64: rocblas handle";
+            return s;
+        }
+        g_vendor[dev] = h;
+    }
+    rocblas_handle h = g_vendor[dev];
+    // row-major C = op(A) op(B) is column-major C^T = op(B)^T op(A)^T
+    const rocblas_operation ta = g.trans_b ? rocblas_operation_transpose : rocblas_operation_none;
+    const rocblas_operation tb = g.trans_a ? rocblas_operation_transpose : rocblas_operation_none;
+    const double alpha = g.alpha, beta = g.beta;
+    if (rocblas_set_stream(h, st) != rocblas_status_success ||
+        rocblas_dgemm(h, ta, tb, (rocblas_int)g.N, (rocblas_int)g.M, (rocblas_int)g.K, &alpha, g.B,
+                      (rocblas_int)g.ldb, g.A, (rocblas_int)g.lda, &beta, g.C, (rocblas_int)g.map.ms2) !=
+            rocblas_status_success) {
+        s.code = -3;
+        s.msg = "gemm_f64: rocblas_dgemm";
+        return s;
+    }
+    return s;
+}
+
+}  // namespace
+
 Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStream_t st) {
     Status s;
     if (g.M <= 0 || g.N <= 0) return s;
@@ -475,6 +546,7 @@ Status gemm_f64(const GemmDesc& g, void* splitk_ws, size_t splitk_bytes, hipStre
     // split-BF16 products when the operands come as planes; a result wanted
     // as planes (with FP64 operands) comes from the FP32 matrix cores
     if (g.prec == 2 && (g.A16 || g.B16)) return gemm_bf16x6(g, st);
+    if (vendor_eligible(g)) return vendor_dgemm(g, st);
     const Plan pl = make_plan(g);
     KArgs a{};
     a.M = g.M; a.N = g.N; a.K = g.K;

@@ -43,6 +43,14 @@ def test_gemm_matches_host_blas(M, N, K, ta, tb):
     _gemm_case(M, N, K, ta, tb, 1.0, 0.0, seed=M * 7 + N + K)
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_vendor_sized_products_match_host_blas(ta, tb):
+    # 2 M N K >= 3e10: the plain products of this size go to the vendor BLAS
+    print(f"gemm (vendor size) ta={ta} tb={tb}", flush=True)
+    _gemm_case(2048, 2048, 3600, ta, tb, 1.0, 0.0, seed=11 + 2 * ta + tb)
+    _gemm_case(2049, 2047, 3600, ta, tb, -0.5, 0.75, seed=21 + 2 * ta + tb)
+
+
 def test_gemm_alpha_beta_and_split_k():
     _gemm_case(64, 48, 20000, 1, 0, -1.5, 0.25, seed=3)   # split-K path
     _gemm_case(200, 200, 40, 0, 0, 2.0, 1.0, seed=4)
