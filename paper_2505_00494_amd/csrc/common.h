@@ -132,8 +132,8 @@ struct GemmDesc {
     // be ordered, e.g. on one stream)
     unsigned* ticket = nullptr;
     // may run as the vendor BLAS's dgemm when it is a plain FP64 product of at
-    // least 3e10 flop (set by the callers whose products were measured there)
-    bool vendor = false;
+    // least 3e10 flop with at least 256 output tiles of 128 x 128
+    bool vendor = true;
 };
 
 // Scratch needed by gemm_f64 for split-K partial sums (bytes); 0 when the

@@ -565,11 +565,6 @@ Status qr_step_core(ctm_ctx* c, const double* Cin, const double* Tin, double* Co
         // tiles, loses less and gains nothing)
         GemmDesc gc = g_edge_c(p, p.Q, chi, chi, Dab);                                 // a7 3c
         gc.ticket = c->gemm_ticket();
-        // at chi D^2 = 16384 the vendor dgemm takes 2.1 ms where the kernel takes
-        // 3.0 (D = 8, chi = 256); the steps recomputed for the gradient keep the
-        // kernel (with the vendor dgemm there, and in the adjoint's products, a
-        // dE/dA call took 1.7 s instead of 0.42)
-        gc.vendor = timed;
         QRCTM_TRY(G(gc));
     }
     QRCTM_TRY(mark(5));
@@ -1527,7 +1522,6 @@ int ctm_gemm(int trans_a, int trans_b, int M, int N, int K, double alpha, const 
         g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
         g.C = C; g.map = OutMap::plain(M, N, ldc);
         g.alpha = alpha; g.beta = beta;
-        g.vendor = true;
         QRCTM_TRY(gemm_f64(g, ws, ws_bytes, st));
         return sync(st);
     });

@@ -17,9 +17,9 @@
 // quarter-wave (16 rows, stride BK * size + 16 bytes) hit distinct banks.
 //
 // The one exception: a plain FP64 product (row-major C, no gate, no split
-// planes) of at least kVendorMinFlop whose caller allows it (GemmDesc::vendor)
-// goes to the vendor BLAS (rocBLAS dgemm, atomics off, so the result is
-// reproducible).  On the step's shapes it runs at
+// planes) of at least kVendorMinFlop with at least kVendorMinTiles output
+// tiles goes to the vendor BLAS (rocBLAS dgemm, atomics off, so the result is
+// reproducible) unless its caller keeps it here (GemmDesc::vendor).  On the step's shapes it runs at
 // 0.83-0.94 of the FP64 peak at chi D^2 = 16384 where these kernels reach
 // 0.55-0.58; below that size they are as fast or the persistent grid of the
 // kernel above wins beside the corner spectrum.
@@ -470,6 +470,10 @@ size_t gemm_splitk_bytes(const GemmDesc& g) {
 namespace {
 
 constexpr double kVendorMinFlop = 3.0e10;  // 2 M N K (chi D^2 = 16384: 3c 1.4e11)
+// and enough output tiles for the chip: with few tiles and a long K (an inner
+// product of the adjoint, 1 tile) the library ran one workgroup for 0.68 s,
+// where the kernel above splits K
+constexpr long long kVendorMinTiles = 256;
 constexpr int kMaxDevices = 16;
 
 bool plain_output(const GemmDesc& g) {
@@ -479,7 +483,8 @@ bool plain_output(const GemmDesc& g) {
 
 bool vendor_eligible(const GemmDesc& g) {
     return g.vendor && g.prec == 0 && g.gate == nullptr && g.A16 == nullptr && g.B16 == nullptr && g.C16 == nullptr &&
-           plain_output(g) && 2.0 * (double)g.M * (double)g.N * (double)g.K >= kVendorMinFlop;
+           plain_output(g) && 2.0 * (double)g.M * (double)g.N * (double)g.K >= kVendorMinFlop &&
+           ceil_div(g.M, 128) * ceil_div(g.N, 128) >= kVendorMinTiles;
 }
 
 // one handle per device, made on first use (rocBLAS takes its own workspace
