@@ -318,7 +318,8 @@ int ctm_qr_noalloc(const double* M, double* Q, double* R, int m, int n, int meth
 /*
  * ctm_gemm: C = alpha * op(A) op(B) + beta * C, FP64 on the matrix cores (the
  *   kernel behind every contraction of the step; products of at least 3e10
- *   flop, 2 M N K, run as rocBLAS dgemm with atomics off, reproducibly).
+ *   flop, 2 M N K, with at least 256 output tiles of 128 x 128 run as rocBLAS
+ *   dgemm with atomics off, reproducibly).
  *   op(A) is M x K: trans_a = 0 -> A[m*lda + k], 1 -> A[k*lda + m].
  *   op(B) is K x N: trans_b = 0 -> B[k*ldb + n], 1 -> B[n*ldb + k].
  *   C is M x N at C[m*ldc + n].  ws: device scratch of at least
